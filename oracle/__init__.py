@@ -1,0 +1,154 @@
+"""CPU oracle for the hybrid quicksort + bitonic sort (TEST INFRASTRUCTURE).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The product path (the HIP
+library and its Python binding) never imports, links or calls it.
+
+The arithmetic lives in ``hsort_oracle.c`` (plain scalar C, one thread); this
+module only loads the shared object built from it and marshals numpy arrays.
+Every function cites the part of the paper it follows in the C source.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hsort_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_I64 = ctypes.c_int64
+_P = ctypes.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, -O2, no intrinsics)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        for name, args, res in [
+            ("oracle_sort_i32", [_P, _I64, _I64], _I64),
+            ("oracle_sort_f64", [_P, _I64, _I64], _I64),
+            ("oracle_sort_kv_i32", [_P, _P, _I64, _I64], _I64),
+            ("oracle_sort_segmented_i32", [_P, _P, _I64, _I64], _I64),
+            ("oracle_partition_le_i32", [_P, _I64, ctypes.c_int32], _I64),
+            ("oracle_simd_partition_i32", [_P, _I64, ctypes.c_int32, ctypes.c_int], _I64),
+            ("oracle_qs_appendix_i32", [_P, _I64, _P], None),
+            ("oracle_bitonic_apply", [_P, _P, ctypes.c_int], None),
+            ("oracle_bitonic_exhaustive_failures", [ctypes.c_int], _I64),
+            ("oracle_bitonic_merger_failures", [ctypes.c_int], _I64),
+            ("oracle_key_f64", [ctypes.c_uint64], ctypes.c_uint64),
+            ("oracle_unkey_f64", [ctypes.c_uint64], ctypes.c_uint64),
+        ]:
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+LEAF = 256  # the paper's sort bound: 16 vectors of 16 int32
+
+
+def sort_i32(keys: np.ndarray, leaf: int = LEAF) -> np.ndarray:
+    a = np.ascontiguousarray(keys, dtype=np.int32).copy()
+    if lib().oracle_sort_i32(_ptr(a), a.size, leaf) < 0:
+        raise MemoryError("oracle_sort_i32")
+    return a
+
+
+def sort_i32_depth(keys: np.ndarray, leaf: int = LEAF):
+    a = np.ascontiguousarray(keys, dtype=np.int32).copy()
+    d = lib().oracle_sort_i32(_ptr(a), a.size, leaf)
+    return a, d
+
+
+def sort_f64(keys: np.ndarray, leaf: int = LEAF) -> np.ndarray:
+    """Sort float64 values by IEEE totalOrder; returns the permuted values."""
+    a = np.ascontiguousarray(keys, dtype=np.float64).copy().view(np.uint64)
+    if lib().oracle_sort_f64(_ptr(a), a.size, leaf) < 0:
+        raise MemoryError("oracle_sort_f64")
+    return a.view(np.float64)
+
+
+def sort_kv_i32(keys: np.ndarray, vals: np.ndarray, leaf: int = LEAF):
+    k = np.ascontiguousarray(keys, dtype=np.int32).copy()
+    v = np.ascontiguousarray(vals, dtype=np.int32).copy()
+    assert k.size == v.size
+    if lib().oracle_sort_kv_i32(_ptr(k), _ptr(v), k.size, leaf) < 0:
+        raise MemoryError("oracle_sort_kv_i32")
+    return k, v
+
+
+def sort_segmented_i32(keys: np.ndarray, offsets: np.ndarray, leaf: int = LEAF) -> np.ndarray:
+    k = np.ascontiguousarray(keys, dtype=np.int32).copy()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    if lib().oracle_sort_segmented_i32(_ptr(k), _ptr(off), off.size - 1, leaf) < 0:
+        raise MemoryError("oracle_sort_segmented_i32")
+    return k
+
+
+def partition_le_i32(keys: np.ndarray, pivot: int):
+    a = np.ascontiguousarray(keys, dtype=np.int32).copy()
+    k = lib().oracle_partition_le_i32(_ptr(a), a.size, int(pivot))
+    return a, int(k)
+
+
+def simd_partition_i32(keys: np.ndarray, pivot: int, vec_size: int = 16):
+    a = np.ascontiguousarray(keys, dtype=np.int32).copy()
+    k = lib().oracle_simd_partition_i32(_ptr(a), a.size, int(pivot), int(vec_size))
+    return a, int(k)
+
+
+def qs_appendix_i32(keys: np.ndarray):
+    a = np.ascontiguousarray(keys, dtype=np.int32).copy()
+    first = ctypes.c_int32(0)
+    lib().oracle_qs_appendix_i32(_ptr(a), a.size, ctypes.addressof(first))
+    return a, int(first.value)
+
+
+def bitonic_apply(keys: np.ndarray, vals: np.ndarray | None = None):
+    k = np.ascontiguousarray(keys, dtype=np.uint64).copy()
+    logn = int(k.size).bit_length() - 1
+    assert (1 << logn) == k.size
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.int32).copy()
+    lib().oracle_bitonic_apply(_ptr(k), None if v is None else _ptr(v), logn)
+    return k if v is None else (k, v)
+
+
+def bitonic_exhaustive_failures(logn: int) -> int:
+    return int(lib().oracle_bitonic_exhaustive_failures(logn))
+
+
+def bitonic_merger_failures(logn: int) -> int:
+    return int(lib().oracle_bitonic_merger_failures(logn))
+
+
+def key_f64(bits: int) -> int:
+    return int(lib().oracle_key_f64(bits))
+
+
+def unkey_f64(key: int) -> int:
+    return int(lib().oracle_unkey_f64(key))
