@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 hybrid quicksort + bitonic sort.
+
+One step sorts one batch of synthetic keys resident in HBM.  The default
+workload sorts four arrays of 2^27 float64 keys (uniform [0,1), N(0,1),
+already sorted, reverse sorted; IEEE totalOrder), so one step is 2^29 keys.
+
+Printed: ONE JSON line with the sort throughput (Gkeys/s, from HIP events on
+the sort stream around each sort call; the restore copy of the unsorted input
+before each sort is outside the events), the roofline of the dominant kernel
+(the partition pass: algorithmic bytes 2*s per key per level over its event
+time), and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--extra]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+CONFIGS = {
+    # name: (kind, n, distributions or None, seed, description)
+    "f64_2e27": ("f64", 1 << 27, ["uniform", "normal", "sorted", "reverse"], 2,
+                 "sort_f64, 2^27 float64 keys x 4 distributions (uniform [0,1), N(0,1), sorted, reverse)"),
+    "i32_2e20": ("i32", 1 << 20, None, 1, "sort_i32, 2^20 int32 keys uniform over the full range"),
+    "i32_2e28": ("i32", 1 << 28, None, 1, "sort_i32, 2^28 int32 keys uniform over the full range"),
+    "kv_2e28": ("kv", 1 << 28, None, 4,
+                "sort_kv_i32, 2^28 int32 pairs, 2^16 distinct keys, values = original index"),
+    "seg_A": ("seg", 200000, (16, 1 << 13), 5,
+              "sort_segmented_i32, 200,000 int32 arrays, sizes log-uniform in [16, 2^13]"),
+    "seg_B": ("seg", 2840, (16, 1 << 20), 5,
+              "sort_segmented_i32, 2,840 int32 arrays, sizes log-uniform in [16, 2^20]"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_inputs(name):
+    import numpy as np
+
+    import workloads
+    kind, n, extra, seed, _ = CONFIGS[name]
+    if kind == "f64":
+        return [("f64", workloads.f64(n, d, seed=seed)) for d in extra]
+    if kind == "i32":
+        return [("i32", workloads.uniform_i32(n, seed=seed))]
+    if kind == "kv":
+        k, v = workloads.kv_dup_i32(n, seed=seed)
+        return [("kv", (k, v))]
+    if kind == "seg":
+        lo, hi = extra
+        off = workloads.segment_offsets(n, lo, hi, seed=seed)
+        return [("seg", (workloads.uniform_i32(int(off[-1]), seed=seed + 1), off.astype(np.int64)))]
+    raise ValueError(kind)
+
+
+class Case:
+    """One array of the step: pristine device copy + work buffers."""
+
+    def __init__(self, kind, data, torch):
+        self.kind = kind
+        dev = "cuda"
+        if kind in ("f64", "i32"):
+            self.src = torch.from_numpy(data).to(dev)
+            self.work = torch.empty_like(self.src)
+            self.n = data.size
+            self.s = data.itemsize
+        elif kind == "kv":
+            k, v = data
+            self.src = torch.from_numpy(k).to(dev)
+            self.vsrc = torch.from_numpy(v).to(dev)
+            self.work = torch.empty_like(self.src)
+            self.vwork = torch.empty_like(self.vsrc)
+            self.n = k.size
+            self.s = 8
+        else:
+            k, off = data
+            self.src = torch.from_numpy(k).to(dev)
+            self.work = torch.empty_like(self.src)
+            self.off = torch.from_numpy(off).to(dev)
+            self.n = k.size
+            self.s = 4
+
+    def restore(self):
+        self.work.copy_(self.src)
+        if self.kind == "kv":
+            self.vwork.copy_(self.vsrc)
+
+    def sort(self, hs):
+        if self.kind in ("f64", "i32"):
+            return hs.sort_(self.work, stats=True)
+        if self.kind == "kv":
+            return hs.sort_kv_(self.work, self.vwork, stats=True)
+        return hs.sort_segmented_(self.work, self.off, stats=True)
+
+
+def run_gpu(name, steps, warmup):
+    import torch
+
+    import paper_1704_08579_amd as hs
+    hs.lib()
+    cases = [Case(k, d, torch) for k, d in make_inputs(name)]
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    sort_ms = []
+    acc = dict(bytes_alg=0, keys_part=0, part_ms=0.0, part_launches=0, local_ms=0.0, local_keys=0)
+    for step in range(warmup + steps):
+        timed = step >= warmup
+        if step == warmup:
+            torch.cuda.synchronize()
+            t_wall = time.perf_counter()
+        ms_step = 0.0
+        for c in cases:
+            c.restore()
+            ev0.record()
+            st = c.sort(hs)
+            ev1.record()
+            ev1.synchronize()
+            ms_step += ev0.elapsed_time(ev1)
+            if timed:
+                acc["bytes_alg"] += st["bytes_alg"]
+                acc["keys_part"] += st["keys_partitioned"]
+                acc["part_ms"] += st["partition_ms"]
+                acc["part_launches"] += st["partition_launches"]
+                acc["local_ms"] += st["local_ms"]
+                acc["local_keys"] += c.n
+        if timed:
+            sort_ms.append(ms_step)
+        log(f"[bench] {name} step {step} ({'timed' if timed else 'warmup'}): {ms_step:.3f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    keys_step = sum(c.n for c in cases)
+    s = cases[0].s
+    ms = sum(sort_ms) / len(sort_ms)
+    part_bytes = 2 * s * acc["keys_part"]
+    part_gbs = part_bytes / (acc["part_ms"] * 1e-3) / 1e9 if acc["part_ms"] > 0 else 0.0
+    local_gbs = 2 * s * acc["local_keys"] / (acc["local_ms"] * 1e-3) / 1e9 if acc["local_ms"] > 0 else 0.0
+    total_s = sum(sort_ms) * 1e-3
+    return dict(
+        name=name, keys_per_step=keys_step, ms_per_step=ms, wall_ms_per_step=wall * 1e3 / steps,
+        gkeys=keys_step / (ms * 1e-3) / 1e9,
+        bytes_per_key=acc["bytes_alg"] / (keys_step * steps),
+        whole_sort_roofline=acc["bytes_alg"] / total_s / 1e9 / HBM_PEAK_GBS,
+        partition=dict(gbs=part_gbs, ms_per_step=acc["part_ms"] / steps,
+                       launches_per_step=acc["part_launches"] / steps,
+                       bytes_per_launch=part_bytes / max(1, acc["part_launches"]),
+                       avg_launch_ms=acc["part_ms"] / max(1, acc["part_launches"])),
+        local=dict(gbs=local_gbs, ms_per_step=acc["local_ms"] / steps),
+        elem_bytes=s,
+    )
+
+
+def cpu_baseline(name):
+    """The oracle (single thread, as written) on a bounded sample of the
+    workload: the first 2^26 keys of the first array of the step."""
+    import numpy as np
+
+    import oracle
+    kind, n, extra, seed, _ = CONFIGS[name]
+    inputs = make_inputs(name)
+    kind0, data = inputs[0]
+    m = min(n, 1 << 26)
+    t0 = time.perf_counter()
+    if kind0 == "f64":
+        oracle.sort_f64(data[:m])
+        what = f"first 2^{m.bit_length() - 1} keys of the {extra[0]} float64 array"
+    elif kind0 == "i32":
+        oracle.sort_i32(data[:m])
+        what = f"first 2^{m.bit_length() - 1} keys of the int32 array"
+    elif kind0 == "kv":
+        oracle.sort_kv_i32(data[0][:m], data[1][:m])
+        what = f"first 2^{m.bit_length() - 1} pairs"
+    else:
+        k, off = data
+        nseg = int(np.searchsorted(off, m, side="right")) - 1
+        sub = off[: nseg + 1]
+        oracle.sort_segmented_i32(k[: int(sub[-1])], sub)
+        m = int(sub[-1])
+        what = f"first {nseg} segments ({m} keys)"
+    dt = time.perf_counter() - t0
+    return {"value": m / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": what + f", {dt:.1f} s on one host core ({platform.processor() or platform.machine()}, "
+                             f"os.cpu_count()={os.cpu_count()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="f64_2e27", choices=sorted(CONFIGS))
+    ap.add_argument("--extra", action="store_true", help="also run the int32, key/value and batched configs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    r = run_gpu(args.config, args.steps, args.warmup)
+    extra = {}
+    if args.extra:
+        for nm in ["i32_2e28", "kv_2e28", "seg_A", "seg_B", "i32_2e20"]:
+            if nm == args.config:
+                continue
+            e = run_gpu(nm, max(3, args.steps // 2), 1)
+            extra[nm] = {"gkeys_per_s": round(e["gkeys"], 3), "ms_per_step": round(e["ms_per_step"], 3),
+                         "bytes_per_key": round(e["bytes_per_key"], 1),
+                         "partition_gbs": round(e["partition"]["gbs"], 1),
+                         "whole_sort_roofline_frac": round(e["whole_sort_roofline"], 4),
+                         "workload": CONFIGS[nm][4]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.config)
+
+    kind, n, _, _, desc = CONFIGS[args.config]
+    p = r["partition"]
+    out = {
+        "metric": "sorted Gkeys/s + HBM roofline %",
+        "value": round(r["gkeys"], 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "u64", "i32": "u32", "kv": "u64", "seg": "u32"}[kind],
+        "data": "synthetic",
+        "config": {"workload": desc, "keys_per_step": r["keys_per_step"],
+                   "bytes_per_key": round(r["bytes_per_key"], 1),
+                   "whole_sort_roofline_frac": round(r["whole_sort_roofline"], 4),
+                   "wall_ms_per_step_incl_restore": round(r["wall_ms_per_step"], 3),
+                   "local_sort_gbs": round(r["local"]["gbs"], 1),
+                   "local_sort_ms_per_step": round(r["local"]["ms_per_step"], 3),
+                   "partition_ms_per_step": round(p["ms_per_step"], 3),
+                   "partition_launches_per_step": p["launches_per_step"]},
+        "roofline": {"bound": "hbm", "kernel": "k_partition (global partition pass)",
+                     "achieved": round(p["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": round(p["bytes_per_launch"]),
+                     "avg_launch_ms": round(p["avg_launch_ms"], 4)},
+        "cpu_baseline": cpu,
+    }
+    if extra:
+        out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,141 @@
+/*
+ * hsort.h -- C ABI of the MI355X (gfx950) hybrid quicksort + bitonic sort.
+ *
+ * The method is the hybrid sort of Bramas, "A Novel Hybrid Quicksort
+ * Algorithm Vectorized using AVX-512 on Intel Skylake" (arXiv 1704.08579):
+ * quicksort partitioning around a pivot (Sec. III-B, Algorithm 3; Sec. III-C,
+ * Algorithm 4) with partitions below a bound sorted by a branch-free bitonic
+ * network (Sec. III-A, Algorithms 1 and 2), for int32 keys, float64 keys and
+ * int32 key/value pairs (Sec. III-D).
+ *
+ * Conventions shared by every entry point:
+ *   - Every array pointer is a DEVICE pointer (hipMalloc memory, or e.g. a
+ *     torch tensor's data_ptr()).  `stream` is a hipStream_t; NULL means the
+ *     null stream.  Work is enqueued on `stream`; the level-synchronous
+ *     driver reads small counters back between launches, so the call returns
+ *     after the partition levels have been issued, with the final local-sort
+ *     launch still in flight on `stream`.
+ *   - Sorts are in place, ascending and not stable: the paper's partition
+ *     and bitonic network are not stable (Sec. II-A).  Equal keys of the
+ *     key/value sort come out ordered by value (a valid, deterministic
+ *     choice among the permutations the method allows).
+ *   - The caller owns every array and the stream; the library keeps no
+ *     pointer once the call's work on `stream` has completed.  Scratch
+ *     memory ("workspace") is owned by the library, cached per device and
+ *     grown on demand, unless the caller passes one in hs_opts.
+ *   - Errors are reported by return code only (hs_status); nothing is
+ *     thrown across the ABI.  Argument errors are detected before any
+ *     launch.  hs_last_error() returns a thread-local message describing
+ *     the last non-OK return of the calling thread.
+ *   - Limits: 0 <= n < 2^31 elements per call (positions fit 32 bits inside
+ *     the kernels; byte offsets are 64-bit).
+ */
+#ifndef HSORT_H
+#define HSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define HS_API __attribute__((visibility("default")))
+#else
+#define HS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hs_status {
+    HS_OK = 0,
+    HS_EINVAL = -1,       /* bad argument (null pointer, n out of range, overlap, ...) */
+    HS_ENOMEM = -2,       /* device allocation of the workspace failed */
+    HS_EHIP = -3,         /* a HIP runtime call failed; see hs_last_error() */
+    HS_EWORKSPACE = -4,   /* caller-provided workspace is too small */
+    HS_EUNSUPPORTED = -5, /* device is not gfx950, or an option is not supported */
+    HS_EINTERNAL = -6     /* a kernel reported a broken invariant */
+} hs_status;
+
+/* Operation codes for hs_workspace_size(). */
+enum { HS_OP_SORT_I32 = 0, HS_OP_SORT_F64 = 1, HS_OP_SORT_KV_I32 = 2,
+       HS_OP_PARTITION_I32 = 3, HS_OP_SORT_SEGMENTED_I32 = 4 };
+
+/* Pivot rules (hs_opts.pivot_rule). */
+enum { HS_PIVOT_AUTO = 0,     /* the tuned default */
+       HS_PIVOT_MEDIAN3 = 1,  /* median of first, middle, last (Sec. IV-A) */
+       HS_PIVOT_NINTHER = 2,  /* median of three medians of three */
+       HS_PIVOT_SAMPLE = 3 }; /* median of a 31-element strided sample */
+
+/* Optional per-call statistics (host memory).  Filling it costs one extra
+ * stream synchronisation. */
+typedef struct hs_stats {
+    int64_t passes;        /* global partition levels run */
+    int64_t bytes_alg;     /* algorithmic HBM bytes: 2*s per key per pass and per local sort */
+    int64_t keys_partitioned; /* sum over levels of the keys in partitioned segments */
+    int64_t tasks;         /* on-chip (local sort / fill) tasks */
+    int64_t max_depth;     /* deepest global level that partitioned */
+    int32_t fallback_used; /* reserved: 1 if a fallback driver ran */
+    int32_t reserved;
+    double bucket_imbalance; /* reserved for the multiway forms */
+    /* Kernel times measured with HIP events on `stream` around each launch
+     * (filled only when stats are requested). */
+    double partition_ms;   /* sum over the partition-pass launches */
+    double local_ms;       /* the on-chip sort launch */
+    int64_t partition_launches;
+} hs_stats;
+
+/* Optional tuning knobs.  A NULL hs_opts*, or 0 in a field, selects the
+ * tuned default. */
+typedef struct hs_opts {
+    int32_t pivot_rule;   /* HS_PIVOT_* */
+    int32_t local_T;      /* on-chip segment limit; a power of two <= the type's maximum */
+    int32_t reserved0;
+    int32_t reserved1;
+    uint64_t seed;        /* reserved */
+    void *workspace;      /* caller-owned device scratch, or NULL */
+    size_t workspace_bytes;
+} hs_opts;
+
+/* Sort n int32 keys in place (Algorithm 4 on int32). */
+HS_API int hs_sort_i32(int32_t *keys, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream);
+
+/* Sort n float64 keys in place by IEEE 754-2008 totalOrder:
+ * -NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN.  Output bits are the input
+ * bits, permuted. */
+HS_API int hs_sort_f64(double *keys, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream);
+
+/* Sort n (key, value) pairs held as two separate arrays (Sec. III-D) by key,
+ * in place; every value moves with its key.  keys and vals must not
+ * overlap. */
+HS_API int hs_sort_kv_i32(int32_t *keys, int32_t *vals, int64_t n, const hs_opts *opts,
+                   hs_stats *stats, void *stream);
+
+/* Partition n int32 keys in place around `pivot` (Algorithm 3's contract):
+ * afterwards keys[0,k) <= pivot < keys[k,n), with k = #{x <= pivot} written
+ * to the DEVICE int64 *d_count_le.  The order inside each side is
+ * unspecified. */
+HS_API int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_le,
+                     const hs_opts *opts, void *stream);
+
+/* Sort nseg independent int32 segments in place: segment i is
+ * keys[off[i], off[i+1]) with the DEVICE array off[nseg+1], off[0] = 0,
+ * non-decreasing, off[nseg] = n_total (the caller states n_total so that no
+ * read-back is needed). */
+HS_API int hs_sort_segmented_i32(int32_t *keys, int64_t n_total, const int64_t *d_offsets,
+                          int64_t nseg, const hs_opts *opts, hs_stats *stats, void *stream);
+
+/* Bytes of workspace that operation `op` needs for n keys (and nseg
+ * segments) with the given options. */
+HS_API int hs_workspace_size(int op, int64_t n, int64_t nseg, const hs_opts *opts, size_t *bytes);
+
+/* Thread-local description of the last non-OK return ("" if none). */
+HS_API const char *hs_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+HS_API int hs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSORT_H */

@@ -1,0 +1,183 @@
+"""hsort: MI355X (gfx950) hybrid quicksort + bitonic sort.
+
+Thin Python binding over the C ABI of ``include/hsort.h`` (libhsort.so, built
+from ``csrc/`` with hipcc).  PyTorch supplies device memory and the current
+HIP stream; every step of the sort runs in the library's HIP kernels.  There
+is no fallback: if the library is missing or the device is not gfx950 the
+calls raise.
+
+    import torch, paper_1704_08579_amd as hsort
+    x = torch.randint(-2**31, 2**31, (1 << 20,), dtype=torch.int32, device="cuda")
+    hsort.sort_(x)                      # in place, ascending
+    hsort.sort_kv_(keys, vals)          # values follow their keys
+    k = hsort.partition_(x, pivot)      # x[:k] <= pivot < x[k:]
+    hsort.sort_segmented_(x, offsets)   # each [off[i], off[i+1]) on its own
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["sort_", "sort_kv_", "partition_", "sort_segmented_", "workspace_size", "Stats", "Opts",
+           "lib", "LIB_PATH", "HSortError"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhsort.so")
+
+HS_OK = 0
+OP_SORT_I32, OP_SORT_F64, OP_SORT_KV_I32, OP_PARTITION_I32, OP_SORT_SEGMENTED_I32 = range(5)
+PIVOT_AUTO, PIVOT_MEDIAN3, PIVOT_NINTHER, PIVOT_SAMPLE = range(4)
+
+_STATUS = {0: "HS_OK", -1: "HS_EINVAL", -2: "HS_ENOMEM", -3: "HS_EHIP", -4: "HS_EWORKSPACE",
+           -5: "HS_EUNSUPPORTED", -6: "HS_EINTERNAL"}
+
+
+class HSortError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int64), ("bytes_alg", ctypes.c_int64),
+                ("keys_partitioned", ctypes.c_int64), ("tasks", ctypes.c_int64),
+                ("max_depth", ctypes.c_int64), ("fallback_used", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("bucket_imbalance", ctypes.c_double),
+                ("partition_ms", ctypes.c_double), ("local_ms", ctypes.c_double),
+                ("partition_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("pivot_rule", ctypes.c_int32), ("local_T", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+
+_SIGS = {
+    "hs_sort_i32": ([_P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_sort_f64": ([_P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_sort_kv_i32": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_partition_i32": ([_P, _I64, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+    "hs_sort_segmented_i32": ([_P, _I64, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_workspace_size": ([ctypes.c_int, _I64, _I64, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hs_last_error": ([], ctypes.c_char_p),
+    "hs_version": ([], ctypes.c_int),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhsort.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1704_08579_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != HS_OK:
+        msg = lib().hs_last_error()
+        raise HSortError(rc, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(t) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _require(t, dtypes, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU device")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dim() != 1:
+        raise ValueError(f"{name} must be one-dimensional")
+
+
+def _opts_ptr(opts):
+    return None if opts is None else ctypes.addressof(opts)
+
+
+def sort_(t, opts: Opts | None = None, stats: bool = False):
+    """Sort a 1-D int32 or float64 CUDA tensor in place (float64 by IEEE totalOrder)."""
+    torch = _torch()
+    _require(t, (torch.int32, torch.float64), "t")
+    st = Stats() if stats else None
+    with torch.cuda.device(t.device):
+        fn = lib().hs_sort_i32 if t.dtype == torch.int32 else lib().hs_sort_f64
+        _check(fn(t.data_ptr(), t.numel(), _opts_ptr(opts), None if st is None else ctypes.addressof(st),
+                  _stream_handle(t)))
+    return st.as_dict() if st is not None else t
+
+
+def sort_kv_(keys, vals, opts: Opts | None = None, stats: bool = False):
+    """Sort int32 (key, value) pairs held in two tensors, in place, by key."""
+    torch = _torch()
+    _require(keys, (torch.int32,), "keys")
+    _require(vals, (torch.int32,), "vals")
+    if keys.numel() != vals.numel() or keys.device != vals.device:
+        raise ValueError("keys and vals must have the same size and device")
+    st = Stats() if stats else None
+    with torch.cuda.device(keys.device):
+        _check(lib().hs_sort_kv_i32(keys.data_ptr(), vals.data_ptr(), keys.numel(), _opts_ptr(opts),
+                                    None if st is None else ctypes.addressof(st), _stream_handle(keys)))
+    return st.as_dict() if st is not None else (keys, vals)
+
+
+def partition_(t, pivot: int, count_out=None, opts: Opts | None = None):
+    """Partition an int32 tensor in place: t[:k] <= pivot < t[k:].  The count
+    k is written on the device into `count_out` (a 1-element int64 tensor,
+    allocated if None), which is returned; no host synchronisation."""
+    torch = _torch()
+    _require(t, (torch.int32,), "t")
+    if count_out is None:
+        count_out = torch.empty(1, dtype=torch.int64, device=t.device)
+    _require(count_out, (torch.int64,), "count_out")
+    with torch.cuda.device(t.device):
+        _check(lib().hs_partition_i32(t.data_ptr(), t.numel(), int(pivot), count_out.data_ptr(),
+                                      _opts_ptr(opts), _stream_handle(t)))
+    return count_out
+
+
+def sort_segmented_(t, offsets, opts: Opts | None = None, stats: bool = False):
+    """Sort every segment t[off[i]:off[i+1]] of an int32 tensor in place.
+    `offsets` is an int64 CUDA tensor of nseg+1 entries, off[0] = 0,
+    non-decreasing, off[-1] = t.numel()."""
+    torch = _torch()
+    _require(t, (torch.int32,), "t")
+    _require(offsets, (torch.int64,), "offsets")
+    st = Stats() if stats else None
+    with torch.cuda.device(t.device):
+        _check(lib().hs_sort_segmented_i32(t.data_ptr(), t.numel(), offsets.data_ptr(), offsets.numel() - 1,
+                                           _opts_ptr(opts), None if st is None else ctypes.addressof(st),
+                                           _stream_handle(t)))
+    return st.as_dict() if st is not None else t
+
+
+def workspace_size(op: int, n: int, nseg: int = 0, opts: Opts | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().hs_workspace_size(op, n, nseg, _opts_ptr(opts), ctypes.byref(out)))
+    return int(out.value)

@@ -1,0 +1,187 @@
+// hs_device.hpp -- device primitives of the gfx950 hybrid sort.
+//
+//  * order-key codecs: the caller's int32 / float64 / (int32 key, int32 value)
+//    formats are mapped to unsigned words whose unsigned order is the key
+//    order, so every kernel compares plain unsigned integers;
+//  * wavefront (64-lane) scan and lane shuffles;
+//  * the same-direction bitonic network of the paper (Sec. II-A, Fig. 2
+//    caption; Sec. III-A, Algorithms 1 and 2) held in VGPRs of one wave.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace hs {
+
+constexpr int WAVE = 64;
+
+enum Fmt : int { FMT_I32 = 0, FMT_F64 = 1, FMT_KV = 2 };
+
+template <int F> struct KeyOf { using type = uint64_t; };
+template <> struct KeyOf<FMT_I32> { using type = uint32_t; };
+
+// The caller's arrays, in the caller's format.
+struct Raw {
+    void *keys;
+    int32_t *vals;  // key/value sorts only
+};
+
+// ---------------------------------------------------------------- codecs
+//
+// int32: flipping the sign bit maps two's-complement order onto unsigned
+// order.  float64: IEEE 754-2008 totalOrder -- negative values (sign bit
+// set) have every bit inverted, non-negative values get the sign bit set.
+// key/value: the int32 key's order word in the high half and the value's
+// bits in the low half, so a pair moves as one word and ties between equal
+// keys are broken by value (the method is unstable, so any tie order is a
+// valid output; this one is deterministic).
+
+__device__ __forceinline__ uint32_t enc_i32(uint32_t bits) { return bits ^ 0x80000000u; }
+__device__ __forceinline__ uint32_t dec_i32(uint32_t k) { return k ^ 0x80000000u; }
+__device__ __forceinline__ uint64_t enc_f64(uint64_t b)
+{
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ uint64_t dec_f64(uint64_t k)
+{
+    return (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+}
+__device__ __forceinline__ uint64_t enc_kv(uint32_t key, uint32_t val)
+{
+    return ((uint64_t)enc_i32(key) << 32) | val;
+}
+
+template <int F>
+__device__ __forceinline__ typename KeyOf<F>::type raw_load(const Raw &r, uint32_t i)
+{
+    if constexpr (F == FMT_I32) {
+        return enc_i32(((const uint32_t *)r.keys)[i]);
+    } else if constexpr (F == FMT_F64) {
+        return enc_f64(((const uint64_t *)r.keys)[i]);
+    } else {
+        return enc_kv(((const uint32_t *)r.keys)[i], (uint32_t)r.vals[i]);
+    }
+}
+
+template <int F>
+__device__ __forceinline__ void raw_store(const Raw &r, uint32_t i, typename KeyOf<F>::type k)
+{
+    if constexpr (F == FMT_I32) {
+        ((uint32_t *)r.keys)[i] = dec_i32(k);
+    } else if constexpr (F == FMT_F64) {
+        ((uint64_t *)r.keys)[i] = dec_f64(k);
+    } else {
+        ((uint32_t *)r.keys)[i] = dec_i32((uint32_t)(k >> 32));
+        r.vals[i] = (int32_t)(uint32_t)k;
+    }
+}
+
+template <typename K> __device__ __forceinline__ constexpr K key_max() { return ~K(0); }
+
+// ---------------------------------------------------------------- lanes
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int m) { return (uint32_t)__shfl_xor((int)v, m); }
+__device__ __forceinline__ uint64_t shfl_xor(uint64_t v, int m)
+{
+    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
+    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint32_t t = (uint32_t)__shfl_up((int)v, d);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Number of set bits of a 64-bit lane mask below the calling lane.
+__device__ __forceinline__ uint32_t mask_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// ---------------------------------------------------------------- static loops
+
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void static_for(Fn &&fn)
+{
+    if constexpr (B < E) {
+        fn(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(fn);
+    }
+}
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+constexpr int hibit(int x) { return x <= 1 ? x : (hibit(x >> 1) << 1); }
+
+// ---------------------------------------------------------------- bitonic network
+//
+// A wave holds N = 64*KPL keys, KPL per lane, network index i = lane*KPL + j
+// for register j.  One comparator layer with XOR mask M pairs i with i ^ M;
+// the lower index keeps the minimum.  When M < KPL both partners sit in the
+// same lane and the exchange is a register min/max; otherwise the partner of
+// register j is register j ^ (M mod KPL) of lane ^ (M / KPL).  Since every
+// key format used here is an injective order word (equal words are equal
+// bits), min/max exchanges are exact: a pad with the greatest word and a
+// real element equal to it are indistinguishable.
+
+template <int M, int KPL, typename K>
+__device__ __forceinline__ void cmpx_layer(K (&x)[KPL], int lane)
+{
+    if constexpr (M < KPL) {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+            const int jp = j ^ M;
+            if (j < jp) {
+                const K a = x[j], b = x[jp];
+                const bool lt = a < b;
+                x[j] = lt ? a : b;
+                x[jp] = lt ? b : a;
+            }
+        }
+    } else {
+        constexpr int ML = M / KPL;
+        constexpr int MR = M % KPL;
+        constexpr int HB = hibit(ML);
+        const bool lower = (lane & HB) == 0;
+        K y[KPL];
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) y[j] = shfl_xor(x[j ^ MR], ML);
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+            const K a = x[j], b = y[j];
+            const bool lt = a < b;
+            x[j] = (lower == lt) ? a : b;
+        }
+    }
+}
+
+// Stage s merges sorted runs of 2^(s-1) into runs of 2^s: the mirror layer
+// (mask 2^s - 1, "extremities to the centre"), then half-cleaners at
+// distances 2^(s-2) .. 1 ("linear progression").
+template <int KPL, typename K>
+__device__ __forceinline__ void bitonic_wave(K (&x)[KPL], int lane)
+{
+    constexpr int LOGN = 6 + ilog2(KPL);
+    static_for<1, LOGN + 1>([&](auto S) {
+        constexpr int s = decltype(S)::value;
+        cmpx_layer<(1 << s) - 1, KPL>(x, lane);
+        static_for<0, (s >= 2 ? s - 1 : 0)>([&](auto I) {
+            constexpr int t = s - 2 - decltype(I)::value;
+            cmpx_layer<(1 << t), KPL>(x, lane);
+        });
+    });
+}
+
+}  // namespace hs

@@ -1,0 +1,447 @@
+// hs_sort.hip -- host runtime and C ABI of the gfx950 hybrid sort.
+//
+// Drives the kernels of hs_kernels.hpp level by level (the recursion of
+// Sec. III-C, Algorithm 4, one partition level per launch), owns the cached
+// per-device workspace and implements every entry point of hsort.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "hs_kernels.hpp"
+#include "hsort.h"
+
+namespace {
+
+using namespace hs;
+
+constexpr int LMAX = 96;  // cap on global partition levels per call
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HS_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) return fail(HS_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define HS_LAUNCHED()                                                                   \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess) return fail(HS_EHIP, "kernel launch: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- per-device state
+
+struct DevState {
+    bool probed = false;
+    bool supported = false;
+    int ncu = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    Ctl *h_ctl = nullptr;        // pinned host mirror of the control block
+    hipEvent_t last = nullptr;   // end of the last call that used the cached workspace
+    hipEvent_t ev[2 * LMAX + 4] = {};  // timing events (stats only)
+    std::mutex mu;               // one call at a time per device
+};
+
+constexpr int MAXDEV = 64;
+DevState g_dev[MAXDEV];
+std::mutex g_probe_mu;
+
+int get_device(DevState **out)
+{
+    int dev = 0;
+    HS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAXDEV) return fail(HS_EUNSUPPORTED, "device index %d out of range", dev);
+    DevState &d = g_dev[dev];
+    std::lock_guard<std::mutex> lk(g_probe_mu);
+    if (!d.probed) {
+        hipDeviceProp_t prop;
+        HS_HIP(hipGetDeviceProperties(&prop, dev));
+        d.supported = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        d.ncu = prop.multiProcessorCount;
+        if (d.supported) {
+            HS_HIP(hipHostMalloc((void **)&d.h_ctl, sizeof(Ctl), hipHostMallocDefault));
+            HS_HIP(hipEventCreateWithFlags(&d.last, hipEventDisableTiming));
+            for (auto &e : d.ev) HS_HIP(hipEventCreate(&e));
+        }
+        d.probed = true;
+        if (!d.supported) return fail(HS_EUNSUPPORTED, "device %d is %s, this library is built for gfx950", dev,
+                                      prop.gcnArchName);
+    }
+    if (!d.supported) return fail(HS_EUNSUPPORTED, "device %d is not gfx950", dev);
+    *out = &d;
+    return HS_OK;
+}
+
+// ---------------------------------------------------------------- workspace layout
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+    size_t buf0 = 0, buf1 = 0, segA = 0, segB = 0, cur = 0, tasks = 0, ctl = 0, total = 0;
+    uint32_t cand_cap = 0, task_cap = 0;
+};
+
+template <typename K>
+Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T)
+{
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t sk = sizeof(K);
+    if (op == HS_OP_PARTITION_I32) {
+        L.cand_cap = 1;
+        L.task_cap = 1;
+        L.buf1 = take((size_t)n * 4);
+    } else {
+        L.cand_cap = (uint32_t)(n / ((int64_t)T + 1) + 2);
+        L.task_cap = (uint32_t)((op == HS_OP_SORT_SEGMENTED_I32 ? nseg : 1) + 2ll * LMAX * L.cand_cap + 4);
+        L.buf1 = take((size_t)n * sk);
+        if (op == HS_OP_SORT_KV_I32) L.buf0 = take((size_t)n * sk);
+    }
+    L.segA = take((size_t)L.cand_cap * sizeof(Seg<K>));
+    L.segB = take((size_t)L.cand_cap * sizeof(Seg<K>));
+    L.cur = take((size_t)L.cand_cap * 8);
+    L.tasks = take((size_t)L.task_cap * sizeof(Task<K>));
+    L.ctl = take(sizeof(Ctl));
+    L.total = off;
+    return L;
+}
+
+template <typename K> uint32_t local_limit(const hs_opts *o)
+{
+    const uint32_t Tmax = (uint32_t)LocalCfg<K>::T;
+    if (!o || o->local_T <= 0) return Tmax;
+    return (uint32_t)o->local_T < Tmax ? (uint32_t)o->local_T : Tmax;
+}
+
+int pivot_rule(const hs_opts *o) { return (o && o->pivot_rule > 0) ? o->pivot_rule : PIVOT_SAMPLE; }
+
+int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
+{
+    switch (op) {
+    case HS_OP_SORT_I32:
+    case HS_OP_SORT_SEGMENTED_I32:
+        *L = make_layout<uint32_t>(op, n, nseg, local_limit<uint32_t>(o));
+        return HS_OK;
+    case HS_OP_PARTITION_I32:
+        *L = make_layout<uint32_t>(op, n, nseg, 0);
+        return HS_OK;
+    case HS_OP_SORT_F64:
+    case HS_OP_SORT_KV_I32:
+        *L = make_layout<uint64_t>(op, n, nseg, local_limit<uint64_t>(o));
+        return HS_OK;
+    default:
+        return fail(HS_EINVAL, "unknown op %d", op);
+    }
+}
+
+// Bind the workspace: the caller's, or the cached one grown to fit.
+int bind_workspace(DevState *d, const hs_opts *o, const Layout &L, char **base)
+{
+    if (o && o->workspace) {
+        if (o->workspace_bytes < L.total)
+            return fail(HS_EWORKSPACE, "workspace of %zu bytes, %zu needed", o->workspace_bytes, L.total);
+        if ((uintptr_t)o->workspace % 256)
+            return fail(HS_EINVAL, "workspace must be 256-byte aligned");
+        *base = (char *)o->workspace;
+        return HS_OK;
+    }
+    if (d->ws_bytes < L.total) {
+        if (d->ws) {
+            HS_HIP(hipDeviceSynchronize());
+            HS_HIP(hipFree(d->ws));
+            d->ws = nullptr;
+            d->ws_bytes = 0;
+        }
+        size_t want = L.total + L.total / 8;
+        if (hipMalloc(&d->ws, want) != hipSuccess) {
+            (void)hipGetLastError();
+            d->ws = nullptr;
+            return fail(HS_ENOMEM, "hipMalloc of %zu workspace bytes failed", want);
+        }
+        d->ws_bytes = want;
+    }
+    *base = (char *)d->ws;
+    return HS_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// ---------------------------------------------------------------- driver
+
+template <int F>
+int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
+             hs_stats *st, hipStream_t stream)
+{
+    using K = typename KeyOf<F>::type;
+    const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
+                         : (F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : HS_OP_SORT_KV_I32);
+    const uint32_t T = local_limit<K>(o);
+    const int rule = pivot_rule(o);
+    const int local_rule = (o && o->pivot_rule > 0) ? o->pivot_rule : PIVOT_NINTHER;
+    Layout L;
+    int rc = layout_for(op, n, nseg, o, &L);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(d->mu);
+    char *ws = nullptr;
+    rc = bind_workspace(d, o, L, &ws);
+    if (rc) return rc;
+    const bool shared_ws = !(o && o->workspace);
+    if (shared_ws) HS_HIP(hipStreamWaitEvent(stream, d->last, 0));
+
+    K *buf[2];
+    buf[0] = F == FMT_KV ? (K *)(ws + L.buf0) : (K *)raw.keys;
+    buf[1] = (K *)(ws + L.buf1);
+    Seg<K> *segs[2] = {(Seg<K> *)(ws + L.segA), (Seg<K> *)(ws + L.segB)};
+    unsigned long long *cur = (unsigned long long *)(ws + L.cur);
+    Task<K> *tasks = (Task<K> *)(ws + L.tasks);
+    Ctl *ctl = (Ctl *)(ws + L.ctl);
+    Ctl *h = d->h_ctl;
+    const int aligned = aligned16(raw.keys) && (F != FMT_KV || aligned16(raw.vals)) ? 1 : 0;
+
+    HS_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), stream));
+    if (d_off) {
+        const uint32_t g = (uint32_t)((nseg + 255) / 256);
+        k_init_segmented<F><<<g, 256, 0, stream>>>(ctl, segs[0], tasks, raw, d_off, (uint32_t)nseg, (uint32_t)n, T,
+                                                   rule, L.cand_cap, L.task_cap);
+    } else {
+        k_init_single<F><<<1, 64, 0, stream>>>(ctl, segs[0], tasks, raw, (uint32_t)n, T, rule, 0, K(0));
+    }
+    HS_LAUNCHED();
+    k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[0], cur, L.cand_cap);
+    HS_LAUNCHED();
+    HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HS_HIP(hipStreamSynchronize(stream));
+    if (h->err) return fail(HS_EINTERNAL, "init reported error bits 0x%x", h->err);
+
+    int64_t levels = 0, keys_part = 0;
+    int cur_list = 0;
+    const int maxg = d->ncu * 8;
+    int lrule = rule;
+    int guard = 2;
+    for (int64_t x = n; x > 1; x >>= 1) ++guard;  // 2 + log2(n)
+    for (int level = 0; h->nseg > 0; ++level) {
+        if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
+        if (level > guard) lrule = PIVOT_SAMPLE;  // depth guard
+        const uint32_t nsegs = h->nseg, ntiles = h->ntiles;
+        keys_part += (int64_t)h->level_keys;
+        const int g = (int)(ntiles < (uint32_t)maxg ? ntiles : (uint32_t)maxg);
+        const uint32_t out_id = (uint32_t)((level + 1) & 1);
+        if (st) HS_HIP(hipEventRecord(d->ev[2 * level], stream));
+        if (level == 0)
+            k_partition<F, true, false><<<g, PartCfg<K>::NT, 0, stream>>>(ctl, segs[cur_list], cur, nullptr, raw,
+                                                                          buf[out_id], Raw{}, aligned);
+        else
+            k_partition<F, false, false><<<g, PartCfg<K>::NT, 0, stream>>>(
+                ctl, segs[cur_list], cur, buf[level & 1], raw, buf[out_id], Raw{},
+                (F == FMT_KV || aligned) ? 1 : 0);
+        HS_LAUNCHED();
+        if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
+        k_finalize<F><<<(nsegs + 255) / 256, 256, 0, stream>>>(ctl, segs[cur_list], cur, segs[1 - cur_list],
+                                                               tasks, buf[out_id], out_id, T, lrule,
+                                                               L.cand_cap, L.task_cap);
+        HS_LAUNCHED();
+        cur_list = 1 - cur_list;
+        k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[cur_list], cur, L.cand_cap);
+        HS_LAUNCHED();
+        HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HS_HIP(hipStreamSynchronize(stream));
+        if (h->err) return fail(HS_EINTERNAL, "level %d reported error bits 0x%x", level, h->err);
+        ++levels;
+    }
+    const uint32_t ntask = h->ntask;
+    hipEvent_t *lev = &d->ev[2 * LMAX];
+    if (ntask > 0) {
+        const int g = (int)(ntask < (uint32_t)(d->ncu * 2) ? ntask : (uint32_t)(d->ncu * 2));
+        if (st) HS_HIP(hipEventRecord(lev[0], stream));
+        k_local<F><<<g, LocalCfg<K>::NT, 0, stream>>>(ctl, tasks, buf[0], buf[1], raw, local_rule, L.task_cap);
+        HS_LAUNCHED();
+        if (st) HS_HIP(hipEventRecord(lev[1], stream));
+    }
+    if (shared_ws) HS_HIP(hipEventRecord(d->last, stream));
+    if (st) {
+        HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HS_HIP(hipStreamSynchronize(stream));
+        std::memset(st, 0, sizeof *st);
+        st->passes = levels;
+        st->keys_partitioned = keys_part;
+        st->tasks = ntask;
+        st->max_depth = levels;
+        st->bytes_alg = (int64_t)(2 * sizeof(K)) * (keys_part + (int64_t)h->local_keys) +
+                        (int64_t)sizeof(K) * (int64_t)h->fill_keys;
+        st->partition_launches = levels;
+        for (int64_t l = 0; l < levels; ++l) {
+            float ms = 0.f;
+            HS_HIP(hipEventElapsedTime(&ms, d->ev[2 * l], d->ev[2 * l + 1]));
+            st->partition_ms += ms;
+        }
+        if (ntask > 0) {
+            float ms = 0.f;
+            HS_HIP(hipEventElapsedTime(&ms, lev[0], lev[1]));
+            st->local_ms = ms;
+        }
+        if (h->err) return fail(HS_EINTERNAL, "error bits 0x%x", h->err);
+    }
+    return HS_OK;
+}
+
+int check_n(int64_t n)
+{
+    if (n < 0) return fail(HS_EINVAL, "n = %lld is negative", (long long)n);
+    if (n >= ((int64_t)1 << 31)) return fail(HS_EINVAL, "n = %lld exceeds 2^31 - 1", (long long)n);
+    return HS_OK;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+int hs_version(void) { return 100; }
+
+const char *hs_last_error(void) { return g_err.c_str(); }
+
+int hs_workspace_size(int op, int64_t n, int64_t nseg, const hs_opts *opts, size_t *bytes)
+{
+    if (!bytes) return fail(HS_EINVAL, "bytes is NULL");
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (nseg < 0) return fail(HS_EINVAL, "nseg is negative");
+    Layout L;
+    rc = layout_for(op, n, nseg, opts, &L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return HS_OK;
+}
+
+int hs_sort_i32(int32_t *keys, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n > 0 && !keys) return fail(HS_EINVAL, "keys is NULL");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n <= 1) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    return run_sort<FMT_I32>(d, Raw{keys, nullptr}, n, nullptr, 0, opts, stats, (hipStream_t)stream);
+}
+
+int hs_sort_f64(double *keys, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n > 0 && !keys) return fail(HS_EINVAL, "keys is NULL");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n <= 1) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    return run_sort<FMT_F64>(d, Raw{keys, nullptr}, n, nullptr, 0, opts, stats, (hipStream_t)stream);
+}
+
+int hs_sort_kv_i32(int32_t *keys, int32_t *vals, int64_t n, const hs_opts *opts, hs_stats *stats,
+                   void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n > 0 && (!keys || !vals)) return fail(HS_EINVAL, "keys or vals is NULL");
+    if (n > 0 && overlap(keys, (size_t)n * 4, vals, (size_t)n * 4))
+        return fail(HS_EINVAL, "keys and vals overlap");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n <= 1) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    return run_sort<FMT_KV>(d, Raw{keys, vals}, n, nullptr, 0, opts, stats, (hipStream_t)stream);
+}
+
+int hs_sort_segmented_i32(int32_t *keys, int64_t n_total, const int64_t *d_offsets, int64_t nseg,
+                          const hs_opts *opts, hs_stats *stats, void *stream)
+{
+    int rc = check_n(n_total);
+    if (rc) return rc;
+    if (nseg < 0 || nseg >= ((int64_t)1 << 31)) return fail(HS_EINVAL, "nseg = %lld out of range", (long long)nseg);
+    if (nseg > 0 && !d_offsets) return fail(HS_EINVAL, "d_offsets is NULL");
+    if (n_total > 0 && !keys) return fail(HS_EINVAL, "keys is NULL");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n_total <= 1 || nseg == 0) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    return run_sort<FMT_I32>(d, Raw{keys, nullptr}, n_total, d_offsets, nseg, opts, stats, (hipStream_t)stream);
+}
+
+int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_le, const hs_opts *opts,
+                     void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (!d_count_le) return fail(HS_EINVAL, "d_count_le is NULL");
+    if (n > 0 && !keys) return fail(HS_EINVAL, "keys is NULL");
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        HS_HIP(hipMemsetAsync(d_count_le, 0, sizeof(int64_t), s));
+        return HS_OK;
+    }
+    Layout L;
+    if ((rc = layout_for(HS_OP_PARTITION_I32, n, 1, opts, &L))) return rc;
+    std::lock_guard<std::mutex> lk(d->mu);
+    char *ws = nullptr;
+    if ((rc = bind_workspace(d, opts, L, &ws))) return rc;
+    const bool shared_ws = !(opts && opts->workspace);
+    if (shared_ws) HS_HIP(hipStreamWaitEvent(s, d->last, 0));
+    int32_t *copy = (int32_t *)(ws + L.buf1);
+    Seg<uint32_t> *segs = (Seg<uint32_t> *)(ws + L.segA);
+    unsigned long long *cur = (unsigned long long *)(ws + L.cur);
+    Task<uint32_t> *tasks = (Task<uint32_t> *)(ws + L.tasks);
+    Ctl *ctl = (Ctl *)(ws + L.ctl);
+    // The pass is out of place: stage the input in the workspace, then
+    // partition it back into the caller's array.
+    HS_HIP(hipMemcpyAsync(copy, keys, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    HS_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
+    const uint32_t upiv = (uint32_t)pivot ^ 0x80000000u;
+    k_init_single<FMT_I32><<<1, 64, 0, s>>>(ctl, segs, tasks, Raw{copy, nullptr}, (uint32_t)n, 0, PIVOT_MEDIAN3, 1,
+                                            upiv);
+    HS_LAUNCHED();
+    k_plan<uint32_t><<<1, 1024, 0, s>>>(ctl, segs, cur, L.cand_cap);
+    HS_LAUNCHED();
+    const uint32_t ntiles = seg_tiles<uint32_t>(0, (uint32_t)n);
+    const uint32_t maxg = (uint32_t)d->ncu * 8;
+    const int g = (int)(ntiles < maxg ? ntiles : maxg);
+    k_partition<FMT_I32, true, true><<<g, PartCfg<uint32_t>::NT, 0, s>>>(
+        ctl, segs, cur, nullptr, Raw{copy, nullptr}, nullptr, Raw{keys, nullptr}, 1);
+    HS_LAUNCHED();
+    k_write_count<<<1, 64, 0, s>>>(cur, d_count_le);
+    HS_LAUNCHED();
+    if (shared_ws) HS_HIP(hipEventRecord(d->last, s));
+    return HS_OK;
+}
+
+}  // extern "C"
