@@ -85,24 +85,79 @@ template <typename K> __device__ __forceinline__ constexpr K key_max() { return 
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-__device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int m) { return (uint32_t)__shfl_xor((int)v, m); }
-__device__ __forceinline__ uint64_t shfl_xor(uint64_t v, int m)
+// Lane exchanges.  xor_lanes<ML>(v) returns v from lane (lane ^ ML).  The
+// masks used by the bitonic network map onto cheap gfx950 forms:
+//   ML = 1, 2, 3     DPP quad_perm
+//   ML = 7, 15       DPP row_half_mirror / row_mirror
+//   ML = 4, 8        two DPP moves (lane^7^3, lane^15^7)
+//   ML = 16, 31      ds_swizzle in bit-mask mode (xor within 32 lanes)
+//   ML = 32          v_permlane32_swap
+//   ML = 63          ds_swizzle xor 31, then v_permlane32_swap
+// and everything else falls back to ds_bpermute.
+template <int CTRL> __device__ __forceinline__ uint32_t dpp_mov(uint32_t v)
 {
-    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
-    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+
+constexpr int DPP_QP_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int DPP_QP_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_QP_XOR3 = 0x1B;  // quad_perm [3,2,1,0]
+constexpr int DPP_ROW_MIRROR = 0x140;
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+
+__device__ __forceinline__ uint32_t swap32_partner(uint32_t v, int lane)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return lane < 32 ? (uint32_t)r[1] : (uint32_t)r[0];
+}
+
+template <int ML> __device__ __forceinline__ uint32_t xor_lanes(uint32_t v, int lane)
+{
+    if constexpr (ML == 1) return dpp_mov<DPP_QP_XOR1>(v);
+    else if constexpr (ML == 2) return dpp_mov<DPP_QP_XOR2>(v);
+    else if constexpr (ML == 3) return dpp_mov<DPP_QP_XOR3>(v);
+    else if constexpr (ML == 4) return dpp_mov<DPP_QP_XOR3>(dpp_mov<DPP_ROW_HALF_MIRROR>(v));
+    else if constexpr (ML == 7) return dpp_mov<DPP_ROW_HALF_MIRROR>(v);
+    else if constexpr (ML == 8) return dpp_mov<DPP_ROW_HALF_MIRROR>(dpp_mov<DPP_ROW_MIRROR>(v));
+    else if constexpr (ML == 15) return dpp_mov<DPP_ROW_MIRROR>(v);
+    else if constexpr (ML == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (16 << 10) | 0x1F);
+    else if constexpr (ML == 31) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (31 << 10) | 0x1F);
+    else if constexpr (ML == 32) return swap32_partner(v, lane);
+    else if constexpr (ML == 63)
+        return swap32_partner((uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (31 << 10) | 0x1F), lane);
+    else return (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ ML) << 2, (int)v);
+}
+
+template <int ML> __device__ __forceinline__ uint64_t xor_lanes(uint64_t v, int lane)
+{
+    const uint32_t lo = xor_lanes<ML>((uint32_t)v, lane);
+    const uint32_t hi = xor_lanes<ML>((uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave.
+// Inclusive prefix sum over the 64 lanes of a wave: four DPP row shifts
+// give the scan inside each row of 16 lanes, then two row broadcasts carry
+// row totals forward (rows 1 and 3 from lane 15 / 47, rows 2 and 3 from
+// lane 31).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint32_t t = (uint32_t)__shfl_up((int)v, d);
-        if (lane >= d) v += t;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return v;
+}
+
+// Broadcast lane `src` (wave-uniform) to every lane.
+__device__ __forceinline__ uint32_t lane_bcast(uint32_t v, int src)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+__device__ __forceinline__ uint64_t lane_bcast(uint64_t v, int src)
+{
+    return ((uint64_t)lane_bcast((uint32_t)(v >> 32), src) << 32) | lane_bcast((uint32_t)v, src);
 }
 
 // Number of set bits of a 64-bit lane mask below the calling lane.
@@ -157,7 +212,7 @@ __device__ __forceinline__ void cmpx_layer(K (&x)[KPL], int lane)
         const bool lower = (lane & HB) == 0;
         K y[KPL];
 #pragma unroll
-        for (int j = 0; j < KPL; ++j) y[j] = shfl_xor(x[j ^ MR], ML);
+        for (int j = 0; j < KPL; ++j) y[j] = xor_lanes<ML>(x[j ^ MR], lane);
 #pragma unroll
         for (int j = 0; j < KPL; ++j) {
             const K a = x[j], b = y[j];

@@ -57,25 +57,60 @@ template <typename K> struct Task {
     K fill;
 };
 
-// Control block of one call, in device memory.
+// Control block of one call, in device memory.  Every counter that many
+// waves update atomically sits on a 256-byte line of its own: atomics on one
+// line serialize.
 struct Ctl {
-    uint32_t nseg;       // segments in the current level list
-    uint32_t ntiles;     // tiles of the current level
-    uint32_t ncand;      // segments written for the next level
-    uint32_t ntask;      // tasks written
-    uint32_t task_next;  // dynamic task counter of k_local
-    uint32_t err;        // ERR_* bits
-    unsigned long long level_keys;  // keys in the current level's segments
-    unsigned long long local_keys;  // keys handed to local tasks
-    unsigned long long fill_keys;   // keys handed to fill tasks
-    unsigned long long pad[2];
+    // written by k_plan, read by the kernels of the level
+    uint32_t nseg;                   // segments in the current level list
+    uint32_t ntiles;                 // tiles of the current level
+    uint32_t levels;                 // levels that had at least one segment
+    uint32_t max_seg;                // largest segment of the current level
+    unsigned long long level_keys;   // keys in the current level's segments
+    unsigned long long part_keys;    // sum of level_keys over the levels run
+    alignas(256) uint32_t ncand;     // segments written for the next level
+    alignas(256) uint32_t ntask;     // tasks written
+    alignas(256) uint32_t task_next; // dynamic task counter of k_local
+    alignas(256) uint32_t err;       // ERR_* bits
+    alignas(256) unsigned long long local_keys;  // keys handed to local tasks
+    unsigned long long fill_keys;                // keys handed to fill tasks
 };
+
+// Items a wave emits over a batch of up to 64 steps are parked one per lane
+// (lane k keeps what step k emitted) and appended to a device list with a
+// single atomic per wave.
+template <typename T>
+__device__ __forceinline__ void wave_flush(const T &item, bool has, uint32_t *counter, T *list, uint32_t cap,
+                                           Ctl *ctl, uint32_t errbit)
+{
+    const uint64_t m = __ballot(has);
+    if (m == 0) return;
+    const uint32_t total = (uint32_t)__popcll(m);
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, total);
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+    const uint32_t k = base + mask_below(m);
+    if (has) {
+        if (k < cap) list[k] = item;
+        else atomicOr(&ctl->err, errbit);
+    }
+}
+
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
+{
+    for (int d = 1; d < WAVE; d <<= 1) v += __shfl_xor(v, d);
+    return v;
+}
 
 // ---------------------------------------------------------------- tile geometry
 
 template <typename K> struct PartCfg;
-template <> struct PartCfg<uint32_t> { static constexpr int NT = 256, TILE = 4096; };
-template <> struct PartCfg<uint64_t> { static constexpr int NT = 256, TILE = 2048; };
+template <> struct PartCfg<uint32_t> { static constexpr int NT = 256, TILE = 8192; };
+template <> struct PartCfg<uint64_t> { static constexpr int NT = 256, TILE = 4096; };
+
+// Write-cursor words of different segments sit 256 bytes apart: atomics on
+// one cache line serialize, so neighbouring segments must not share one.
+constexpr uint32_t CUR_STRIDE = 32;
 
 // Tiles are aligned to absolute multiples of TILE, so the interior tiles of a
 // segment are full and 16-byte aligned (for 16-byte-aligned buffers).
@@ -105,35 +140,34 @@ template <typename K> __device__ __forceinline__ K med3(K a, K b, K c)
     return b;
 }
 
-// Pivot of [b, e) (e - b >= 2).  MEDIAN3 takes the first, middle and last
-// key (the 3-value median of Sec. IV-A at the positions of Appendix A's
-// middle rule); NINTHER the median of three such medians over nine evenly
-// spaced keys; SAMPLE the median of 31 evenly spaced keys.  The choice only
-// changes how many levels run, never the output.
+// Pivot of [b, e) (e - b >= 2) computed by one thread.  MEDIAN3 takes the
+// first, middle and last key (the 3-value median of Sec. IV-A at the
+// positions of Appendix A's middle rule); any other rule takes the ninther,
+// the median of three such medians over nine evenly spaced keys.  The
+// choice only changes how many levels run, never the output.
 template <typename K, typename Rd>
 __device__ K pick_pivot(const Rd &rd, uint32_t b, uint32_t e, int rule)
 {
     const uint32_t m = e - b;
     if (rule == PIVOT_MEDIAN3 || m < 64) return med3<K>(rd(b), rd(b + (m - 1) / 2), rd(e - 1));
-    if (rule == PIVOT_NINTHER) {
-        K v[9];
+    K v[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) v[i] = rd(b + (uint32_t)(((uint64_t)(m - 1) * i) / 8));
-        return med3<K>(med3<K>(v[0], v[1], v[2]), med3<K>(v[3], v[4], v[5]), med3<K>(v[6], v[7], v[8]));
-    }
-    constexpr int NS = 31;
-    K v[NS];
-    for (int i = 0; i < NS; ++i) v[i] = rd(b + (uint32_t)(((uint64_t)(m - 1) * i) / (NS - 1)));
-    for (int i = 1; i < NS; ++i) {  // insertion sort of the sample
-        K x = v[i];
-        int j = i - 1;
-        while (j >= 0 && v[j] > x) {
-            v[j + 1] = v[j];
-            --j;
-        }
-        v[j + 1] = x;
-    }
-    return v[NS / 2];
+    for (int i = 0; i < 9; ++i) v[i] = rd(b + (uint32_t)(((uint64_t)(m - 1) * i) / 8));
+    return med3<K>(med3<K>(v[0], v[1], v[2]), med3<K>(v[3], v[4], v[5]), med3<K>(v[6], v[7], v[8]));
+}
+
+// Pivot of [b, e) computed by a whole wave (every lane gets the result).
+// SAMPLE: lane i reads the key at b + i*(m-1)/63, the 64 samples are sorted
+// with the in-register bitonic network and the lower median is taken.
+template <typename K, typename Rd>
+__device__ K wave_pick_pivot(const Rd &rd, uint32_t b, uint32_t e, int rule, int lane)
+{
+    const uint32_t m = e - b;
+    if (rule != PIVOT_SAMPLE || m < 256) return pick_pivot<K>(rd, b, e, rule);
+    K x[1];
+    x[0] = rd(b + (uint32_t)(((uint64_t)(m - 1) * (uint32_t)lane) / (WAVE - 1)));
+    bitonic_wave<1>(x, lane);
+    return lane_bcast(x[0], WAVE / 2 - 1);
 }
 
 // ---------------------------------------------------------------- init
@@ -146,9 +180,10 @@ __global__ void k_init_single(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand, Task
                               typename KeyOf<F>::type user_pivot)
 {
     using K = typename KeyOf<F>::type;
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0 || threadIdx.x >= WAVE) return;
+    const int lane = lane_id();
     if (n <= T && !has_pivot) {
-        if (n >= 2) {
+        if (n >= 2 && lane == 0) {
             Task<K> t;
             t.b = 0;
             t.e = n;
@@ -171,60 +206,68 @@ __global__ void k_init_single(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand, Task
         s.piv = user_pivot;
     } else {
         SrcReader<F> rd{nullptr, raw, true};
-        s.piv = pick_pivot<K>(rd, 0, n, rule);
+        s.piv = wave_pick_pivot<K>(rd, 0, n, rule, lane);
     }
-    cand[0] = s;
-    ctl->ncand = 1;
+    if (lane == 0) {
+        cand[0] = s;
+        ctl->ncand = 1;
+    }
 }
 
-// Many arrays: thread i routes segment i [off[i], off[i+1]).
+// Many arrays: each wave routes 64 consecutive segments, lane i segment
+// [off[i], off[i+1]).  Segments of at most T keys become local tasks, larger
+// ones level-0 segments (their pivots are picked by the whole wave, one
+// segment after the other).
 template <int F>
-__global__ void k_init_segmented(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand,
-                                 Task<typename KeyOf<F>::type> *tasks, Raw raw, const int64_t *off,
-                                 uint32_t nseg, uint32_t n_total, uint32_t T, int rule, uint32_t cand_cap,
-                                 uint32_t task_cap)
+__global__ __launch_bounds__(256) void k_init_segmented(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand,
+                                                        Task<typename KeyOf<F>::type> *tasks, Raw raw,
+                                                        const int64_t *off, uint32_t nseg, uint32_t n_total,
+                                                        uint32_t T, int rule, uint32_t cand_cap, uint32_t task_cap)
 {
     using K = typename KeyOf<F>::type;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nseg) return;
-    const int64_t b64 = off[i], e64 = off[i + 1];
-    if (b64 < 0 || e64 > (int64_t)n_total || e64 < b64) {  // malformed offsets: skip and flag
-        atomicOr(&ctl->err, ERR_OFFSETS);
-        return;
-    }
-    const uint32_t b = (uint32_t)b64, e = (uint32_t)e64;
-    if (e <= b + 1) return;  // empty or single key: already in place
-    const uint32_t m = e - b;
-    if (m <= T) {
-        const uint32_t k = atomicAdd(&ctl->ntask, 1u);
-        if (k >= task_cap) {
-            atomicOr(&ctl->err, ERR_TASK_CAP);
-            return;
+    const int lane = lane_id();
+    const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t i = w * WAVE + (uint32_t)lane;
+    uint32_t b = 0, e = 0;
+    bool bad = false;
+    if (i < nseg) {
+        const int64_t b64 = off[i], e64 = off[i + 1];
+        bad = b64 < 0 || e64 > (int64_t)n_total || e64 < b64;  // malformed offsets: skip and flag
+        if (!bad) {
+            b = (uint32_t)b64;
+            e = (uint32_t)e64;
         }
-        Task<K> t;
-        t.b = b;
-        t.e = e;
-        t.src = SRC_RAW;
-        t.kind = TASK_LOCAL;
-        t.fill = 0;
-        tasks[k] = t;
-        atomicAdd(&ctl->local_keys, (unsigned long long)m);
-        return;
     }
-    Seg<K> s;
-    s.b = b;
-    s.e = e;
-    s.tile0 = 0;
-    s.flags = 0;
-    s.ub = 0;
+    if (__ballot(bad) && lane == 0) atomicOr(&ctl->err, ERR_OFFSETS);
+    const uint32_t m = e - b;
+    const bool is_task = m >= 2 && m <= T;
+    const bool is_big = m > T;
+    Task<K> t;
+    t.b = b;
+    t.e = e;
+    t.src = SRC_RAW;
+    t.kind = TASK_LOCAL;
+    t.fill = 0;
+    wave_flush(t, is_task, &ctl->ntask, tasks, task_cap, ctl, ERR_TASK_CAP);
+    const unsigned long long lk = wave_sum64(is_task ? (unsigned long long)m : 0ull);
+    if (lane == 0 && lk) atomicAdd(&ctl->local_keys, lk);
+
+    Seg<K> sg;
+    sg.b = b;
+    sg.e = e;
+    sg.tile0 = 0;
+    sg.flags = 0;
+    sg.ub = 0;
+    sg.piv = 0;
     SrcReader<F> rd{nullptr, raw, true};
-    s.piv = pick_pivot<K>(rd, b, e, rule);
-    const uint32_t k = atomicAdd(&ctl->ncand, 1u);
-    if (k >= cand_cap) {
-        atomicOr(&ctl->err, ERR_CAND_CAP);
-        return;
+    for (uint64_t big = __ballot(is_big); big; big &= big - 1) {
+        const int src = __builtin_ctzll(big);
+        const uint32_t bb = (uint32_t)__builtin_amdgcn_readlane((int)b, src);
+        const uint32_t ee = (uint32_t)__builtin_amdgcn_readlane((int)e, src);
+        const K p = wave_pick_pivot<K>(rd, bb, ee, rule, lane);
+        if (lane == src) sg.piv = p;
     }
-    cand[k] = s;
+    wave_flush(sg, is_big, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
 }
 
 // ---------------------------------------------------------------- plan
@@ -236,10 +279,11 @@ __global__ __launch_bounds__(1024) void k_plan(Ctl *ctl, Seg<K> *segs, unsigned 
 {
     __shared__ uint32_t wsum[16];
     __shared__ unsigned long long wkeys[16];
+    __shared__ uint32_t wmax[16];
     const uint32_t n = min(ctl->ncand, cap);  // an overflow is flagged in err; never read past the list
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     const int nw = blockDim.x / WAVE;
-    uint32_t carry = 0;
+    uint32_t carry = 0, mx = 0;
     unsigned long long keys = 0;
     for (uint32_t base = 0; base < n; base += blockDim.x) {
         const uint32_t i = base + tid;
@@ -249,10 +293,14 @@ __global__ __launch_bounds__(1024) void k_plan(Ctl *ctl, Seg<K> *segs, unsigned 
             sz = segs[i].e - segs[i].b;
         }
         const uint32_t incl = wave_incl_scan(nt);
-        unsigned long long ks = sz;
-        for (int d = 1; d < WAVE; d <<= 1) ks += __shfl_xor(ks, d);
+        const unsigned long long ks = wave_sum64(sz);
+        uint32_t wm = sz;
+        for (int d = 1; d < WAVE; d <<= 1) wm = max(wm, (uint32_t)__shfl_xor((int)wm, d));
         if (lane == WAVE - 1) wsum[wave] = incl;
-        if (lane == 0) wkeys[wave] = ks;
+        if (lane == 0) {
+            wkeys[wave] = ks;
+            wmax[wave] = wm;
+        }
         __syncthreads();
         uint32_t pre = 0, tot = 0;
         unsigned long long ksum = 0;
@@ -260,10 +308,11 @@ __global__ __launch_bounds__(1024) void k_plan(Ctl *ctl, Seg<K> *segs, unsigned 
             if (w < wave) pre += wsum[w];
             tot += wsum[w];
             ksum += wkeys[w];
+            mx = max(mx, wmax[w]);
         }
         if (i < n) {
             segs[i].tile0 = carry + pre + incl - nt;
-            cur[i] = 0ull;
+            cur[(size_t)i * CUR_STRIDE] = 0ull;
         }
         carry += tot;
         keys += ksum;
@@ -274,18 +323,28 @@ __global__ __launch_bounds__(1024) void k_plan(Ctl *ctl, Seg<K> *segs, unsigned 
         ctl->ntiles = carry;
         ctl->ncand = 0;
         ctl->level_keys = keys;
+        ctl->max_seg = mx;
+        ctl->part_keys += keys;
+        if (n) ctl->levels += 1;
     }
 }
 
 // ---------------------------------------------------------------- partition pass
 
+// Where one tile of the level lies: segment index, first key, key count.
+template <typename K> struct TileLoc {
+    uint32_t s, p0, cnt;
+    bool full;
+};
+
 // One level of out-of-place partitioning.  Workgroup g owns a contiguous run
-// of the level's tiles.  Per tile: load (16 B per lane per load, coalesced),
-// compare with the segment's pivot, count the <= side and the > side per
-// thread, scan the counts across the workgroup, reserve both slot runs with
-// one 64-bit atomic on the segment's cursor word (low half: front cursor,
-// high half: back cursor), compact the tile in LDS (<= keys first), and
-// write both runs out with consecutive lanes on consecutive addresses.
+// of the level's tiles and keeps the next tile's loads in flight while it
+// processes the current one.  Per tile: compare with the segment's pivot,
+// count the <= side and the > side per thread, scan the counts across the
+// workgroup, reserve both slot runs with one 64-bit atomic on the segment's
+// cursor word (low half: front cursor, high half: back cursor -- Algorithm
+// 3's left_w and right_w), compact the tile in LDS (<= keys first) and write
+// both runs out with consecutive lanes on consecutive addresses.
 template <int F, bool SRC_IS_RAW, bool DST_IS_RAW>
 __global__ __launch_bounds__(256) void k_partition(const Ctl *ctl, const Seg<typename KeyOf<F>::type> *segs,
                                                    unsigned long long *cur, const typename KeyOf<F>::type *src,
@@ -296,6 +355,7 @@ __global__ __launch_bounds__(256) void k_partition(const Ctl *ctl, const Seg<typ
     constexpr int NT = PartCfg<K>::NT, TILE = PartCfg<K>::TILE, ITEMS = TILE / NT;
     constexpr int NW = NT / WAVE;
     static_assert(ITEMS <= 32, "item masks are 32-bit");
+    static_assert(TILE < 65536, "per-tile counts are 16-bit");
     __shared__ K stage[TILE];
     __shared__ uint32_t wsum[NW];
     __shared__ uint32_t sbase[2];
@@ -307,31 +367,36 @@ __global__ __launch_bounds__(256) void k_partition(const Ctl *ctl, const Seg<typ
     if (t >= tend) return;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
 
+    // segment of the first tile, and a look-ahead copy of the one after it
     uint32_t lo = 0, hi = nseg;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (segs[mid].tile0 <= t) lo = mid; else hi = mid;
     }
-    uint32_t s = lo;
-    Seg<K> sg = segs[s];
-    uint32_t next0 = (s + 1 < nseg) ? segs[s + 1].tile0 : ntiles;
+    uint32_t s_next = lo;
+    Seg<K> sg_next = segs[s_next];
+    Seg<K> sg_after = (s_next + 1 < nseg) ? segs[s_next + 1] : sg_next;
 
-    for (; t < tend; ++t) {
-        while (t >= next0) {
-            ++s;
-            sg = segs[s];
-            next0 = (s + 1 < nseg) ? segs[s + 1].tile0 : ntiles;
+    auto locate = [&](uint32_t tt, Seg<K> &sg_out) {
+        while (s_next + 1 < nseg && tt >= sg_after.tile0) {
+            ++s_next;
+            sg_next = sg_after;
+            sg_after = (s_next + 1 < nseg) ? segs[s_next + 1] : sg_next;
         }
-        const uint32_t a = sg.b / TILE + (t - sg.tile0);
-        const uint32_t p0 = max(sg.b, a * TILE);
-        const uint32_t cnt = min(sg.e, (a + 1) * TILE) - p0;
-        const bool full = aligned && cnt == (uint32_t)TILE;
-
-        K x[ITEMS];
-        if (full) {
+        sg_out = sg_next;
+        TileLoc<K> L;
+        L.s = s_next;
+        const uint32_t a = sg_next.b / TILE + (tt - sg_next.tile0);
+        L.p0 = max(sg_next.b, a * TILE);
+        L.cnt = min(sg_next.e, (a + 1) * TILE) - L.p0;
+        L.full = aligned && L.cnt == (uint32_t)TILE;
+        return L;
+    };
+    auto load = [&](const TileLoc<K> &L, K (&x)[ITEMS]) {
+        if (L.full) {
             if constexpr (F == FMT_KV && SRC_IS_RAW) {
-                const uint4 *kp = (const uint4 *)((const uint32_t *)raw.keys + p0);
-                const uint4 *vp = (const uint4 *)((const uint32_t *)raw.vals + p0);
+                const uint4 *kp = (const uint4 *)((const uint32_t *)raw.keys + L.p0);
+                const uint4 *vp = (const uint4 *)((const uint32_t *)raw.vals + L.p0);
 #pragma unroll
                 for (int j = 0; j < ITEMS / 4; ++j) {
                     const uint4 kk = kp[j * NT + tid], vv = vp[j * NT + tid];
@@ -341,7 +406,7 @@ __global__ __launch_bounds__(256) void k_partition(const Ctl *ctl, const Seg<typ
                     x[4 * j + 3] = enc_kv(kk.w, vv.w);
                 }
             } else if constexpr (sizeof(K) == 4) {
-                const uint4 *pp = (const uint4 *)((SRC_IS_RAW ? (const K *)raw.keys : src) + p0);
+                const uint4 *pp = (const uint4 *)((SRC_IS_RAW ? (const K *)raw.keys : src) + L.p0);
 #pragma unroll
                 for (int j = 0; j < ITEMS / 4; ++j) {
                     const uint4 v = pp[j * NT + tid];
@@ -355,7 +420,7 @@ __global__ __launch_bounds__(256) void k_partition(const Ctl *ctl, const Seg<typ
                     for (int j = 0; j < ITEMS; ++j) x[j] = (K)enc_i32((uint32_t)x[j]);
                 }
             } else {
-                const ulonglong2 *pp = (const ulonglong2 *)((SRC_IS_RAW ? (const K *)raw.keys : src) + p0);
+                const ulonglong2 *pp = (const ulonglong2 *)((SRC_IS_RAW ? (const K *)raw.keys : src) + L.p0);
 #pragma unroll
                 for (int j = 0; j < ITEMS / 2; ++j) {
                     const ulonglong2 v = pp[j * NT + tid];
@@ -371,31 +436,46 @@ __global__ __launch_bounds__(256) void k_partition(const Ctl *ctl, const Seg<typ
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t i = (uint32_t)(j * NT + tid);
-                if (i < cnt) {
-                    if constexpr (SRC_IS_RAW) x[j] = raw_load<F>(raw, p0 + i);
-                    else x[j] = src[p0 + i];
+                if (i < L.cnt) {
+                    if constexpr (SRC_IS_RAW) x[j] = raw_load<F>(raw, L.p0 + i);
+                    else x[j] = src[L.p0 + i];
                 } else {
                     x[j] = 0;
                 }
             }
         }
+    };
+
+    Seg<K> sg;
+    TileLoc<K> L = locate(t, sg);
+    K x[ITEMS];
+    load(L, x);
+
+    for (; t < tend; ++t) {
+        // issue the next tile's loads before working on this one
+        Seg<K> sgn;
+        TileLoc<K> Ln = L;
+        K xn[ITEMS];
+        const bool more = t + 1 < tend;
+        if (more) {
+            Ln = locate(t + 1, sgn);
+            load(Ln, xn);
+        }
 
         const bool strict = (sg.flags & SEG_STRICT) != 0;
         const K piv = sg.piv;
-        uint32_t lemask = 0, cle = 0, cgt = 0;
+        uint32_t lemask = 0, vmask = 0;
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
-            const bool valid = full || (uint32_t)(j * NT + tid) < cnt;
+            const bool valid = L.full || (uint32_t)(j * NT + tid) < L.cnt;
             const bool le = strict ? (x[j] < piv) : (x[j] <= piv);
             if (valid) {
-                if (le) {
-                    lemask |= 1u << j;
-                    ++cle;
-                } else {
-                    ++cgt;
-                }
+                vmask |= 1u << j;
+                if (le) lemask |= 1u << j;
             }
         }
+        const uint32_t cle = (uint32_t)__builtin_popcount(lemask);
+        const uint32_t cgt = (uint32_t)__builtin_popcount(vmask) - cle;
         const uint32_t code = cle | (cgt << 16);
         const uint32_t incl = wave_incl_scan(code);
         if (lane == WAVE - 1) wsum[wave] = incl;
@@ -409,40 +489,50 @@ __global__ __launch_bounds__(256) void k_partition(const Ctl *ctl, const Seg<typ
         }
         const uint32_t excl = pre + incl - code;
         const uint32_t tot_le = tot & 0xFFFFu, tot_gt = tot >> 16;
-        if (tid == 0) {
-            const unsigned long long old =
-                atomicAdd(&cur[s], (unsigned long long)tot_le | ((unsigned long long)tot_gt << 32));
-            sbase[0] = sg.b + (uint32_t)old;
-            sbase[1] = sg.e - (uint32_t)(old >> 32) - tot_gt;
-        }
+        unsigned long long old = 0;
+        if (tid == 0)
+            old = atomicAdd(&cur[(size_t)L.s * CUR_STRIDE],
+                            (unsigned long long)tot_le | ((unsigned long long)tot_gt << 32));
         uint32_t lp = excl & 0xFFFFu, gp = tot_le + (excl >> 16);
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
-            const bool valid = full || (uint32_t)(j * NT + tid) < cnt;
-            if (valid) {
+            if (vmask & (1u << j)) {
                 if (lemask & (1u << j)) stage[lp++] = x[j];
                 else stage[gp++] = x[j];
             }
         }
+        if (tid == 0) {
+            sbase[0] = sg.b + (uint32_t)old;
+            sbase[1] = sg.e - (uint32_t)(old >> 32) - tot_gt;
+        }
         __syncthreads();
+        // No barrier after the write-out: the next tile's LDS writes come
+        // after its first barrier, which every wave reaches only once done here.
         const uint32_t lt_base = sbase[0], gt_base = sbase[1];
-        for (uint32_t i = tid; i < cnt; i += NT) {
+        for (uint32_t i = tid; i < L.cnt; i += NT) {
             const K v = stage[i];
             const uint32_t pos = i < tot_le ? lt_base + i : gt_base + (i - tot_le);
             if constexpr (DST_IS_RAW) raw_store<F>(raw_dst, pos, v);
             else dst[pos] = v;
         }
-        __syncthreads();
+        if (more) {
+            L = Ln;
+            sg = sgn;
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) x[j] = xn[j];
+        }
     }
 }
 
 // ---------------------------------------------------------------- finalize
 
-// One thread per segment of the level: split it at its front cursor (the
-// count of the <= side, Algorithm 3's left_w) and route both children.  A
-// child larger than T becomes a segment of the next level with its own
-// pivot; a smaller child becomes a local task; the ">=" child of a strict
-// split holds only keys equal to the pivot and becomes a fill task.
+// Split every segment of the level at its front cursor (the count of the <=
+// side, Algorithm 3's left_w) and route both children.  A child larger than
+// T becomes a segment of the next level with its own pivot; a smaller child
+// becomes a local task; the ">=" child of a strict split holds only keys
+// equal to the pivot and becomes a fill task.  Waves take segments in a
+// grid-stride loop, 64 at a time, and append what they emit with one atomic
+// per list and batch.
 //
 // Equal keys: a left child inherits its parent's pivot as an upper bound.
 // When a segment's pivot equals that bound, the segment is split with "<"
@@ -457,77 +547,101 @@ __global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, const Seg<typename K
                                                   uint32_t T, int rule, uint32_t cand_cap, uint32_t task_cap)
 {
     using K = typename KeyOf<F>::type;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ctl->nseg) return;
-    const Seg<K> sg = segs[i];
-    const unsigned long long c = cur[i];
-    const uint32_t nle = (uint32_t)c, ngt = (uint32_t)(c >> 32);
-    if (nle + ngt != sg.e - sg.b) {
-        atomicOr(&ctl->err, ERR_CURSOR);
-        return;
-    }
-    const uint32_t mid = sg.b + nle;
-    const bool strict = (sg.flags & SEG_STRICT) != 0;
+    const int lane = lane_id();
+    const uint32_t nseg = ctl->nseg;
+    const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
+    const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     SrcReader<F> rd{out, Raw{nullptr, nullptr}, false};
+    unsigned long long lkeys = 0, fkeys = 0;
 
-    auto emit_task = [&](uint32_t b, uint32_t e, uint32_t kind, K fill) {
-        const uint32_t k = atomicAdd(&ctl->ntask, 1u);
-        if (k >= task_cap) {
-            atomicOr(&ctl->err, ERR_TASK_CAP);
-            return;
+    for (uint32_t step0 = 0; w + (uint64_t)step0 * nwaves < nseg; step0 += WAVE) {
+        // parked items of this batch (lane k: batch step k)
+        Seg<K> c0, c1;
+        Task<K> t0, t1;
+        bool h_c0 = false, h_c1 = false, h_t0 = false, h_t1 = false;
+        c0.tile0 = c1.tile0 = 0;
+        for (uint32_t k = 0; k < (uint32_t)WAVE; ++k) {
+            const uint64_t i64 = w + (uint64_t)(step0 + k) * nwaves;
+            if (i64 >= nseg) break;
+            const uint32_t i = (uint32_t)i64;
+            const Seg<K> sg = segs[i];
+            const unsigned long long c = cur[(size_t)i * CUR_STRIDE];
+            const uint32_t nle = (uint32_t)c, ngt = (uint32_t)(c >> 32);
+            if (nle + ngt != sg.e - sg.b) {
+                if (lane == 0) atomicOr(&ctl->err, ERR_CURSOR);
+                continue;
+            }
+            const uint32_t mid = sg.b + nle;
+            const bool strict = (sg.flags & SEG_STRICT) != 0;
+            // child ranges, with the bound each inherits
+            const uint32_t cb[2] = {sg.b, mid}, ce[2] = {mid, sg.e};
+            const uint32_t cfl[2] = {strict ? 0u : SEG_UB, sg.flags & SEG_UB};
+            const K cub[2] = {sg.piv, sg.ub};
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const uint32_t b = cb[side], e = ce[side], m = e - b;
+                if (m == 0) continue;
+                Task<K> t;
+                t.b = b;
+                t.e = e;
+                t.src = out_id;
+                t.fill = 0;
+                bool is_task = false;
+                if (side == 1 && strict) {  // keys == pivot: final
+                    t.kind = TASK_FILL;
+                    t.fill = sg.piv;
+                    is_task = true;
+                    fkeys += m;
+                } else if (m <= T) {
+                    t.kind = TASK_LOCAL;
+                    is_task = true;
+                    lkeys += m;
+                }
+                if (is_task) {
+                    if (lane == (int)k) {
+                        if (side == 0) { t0 = t; h_t0 = true; } else { t1 = t; h_t1 = true; }
+                    }
+                    continue;
+                }
+                Seg<K> ch;
+                ch.b = b;
+                ch.e = e;
+                ch.tile0 = 0;
+                ch.ub = cub[side];
+                ch.piv = wave_pick_pivot<K>(rd, b, e, rule, lane);
+                ch.flags = cfl[side];
+                if ((ch.flags & SEG_UB) && ch.piv == ch.ub) ch.flags |= SEG_STRICT;
+                if (lane == (int)k) {
+                    if (side == 0) { c0 = ch; h_c0 = true; } else { c1 = ch; h_c1 = true; }
+                }
+            }
         }
-        Task<K> t;
-        t.b = b;
-        t.e = e;
-        t.src = out_id;
-        t.kind = kind;
-        t.fill = fill;
-        tasks[k] = t;
-        atomicAdd(kind == TASK_FILL ? &ctl->fill_keys : &ctl->local_keys, (unsigned long long)(e - b));
-    };
-    auto emit_child = [&](uint32_t b, uint32_t e, uint32_t flags, K ub) {
-        const uint32_t m = e - b;
-        if (m == 0) return;
-        if (m <= T) {
-            emit_task(b, e, TASK_LOCAL, 0);
-            return;
-        }
-        Seg<K> ch;
-        ch.b = b;
-        ch.e = e;
-        ch.tile0 = 0;
-        ch.ub = ub;
-        ch.piv = pick_pivot<K>(rd, b, e, rule);
-        ch.flags = flags;
-        if ((flags & SEG_UB) && ch.piv == ub) ch.flags |= SEG_STRICT;
-        const uint32_t k = atomicAdd(&ctl->ncand, 1u);
-        if (k >= cand_cap) {
-            atomicOr(&ctl->err, ERR_CAND_CAP);
-            return;
-        }
-        cand[k] = ch;
-    };
-
-    if (strict) {
-        emit_child(sg.b, mid, 0u, 0);                        // keys < pivot
-        if (sg.e > mid) emit_task(mid, sg.e, TASK_FILL, sg.piv);  // keys == pivot
-    } else {
-        emit_child(sg.b, mid, SEG_UB, sg.piv);               // keys <= pivot
-        emit_child(mid, sg.e, sg.flags & SEG_UB, sg.ub);     // keys > pivot
+        wave_flush(c0, h_c0, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
+        wave_flush(c1, h_c1, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
+        wave_flush(t0, h_t0, &ctl->ntask, tasks, task_cap, ctl, ERR_TASK_CAP);
+        wave_flush(t1, h_t1, &ctl->ntask, tasks, task_cap, ctl, ERR_TASK_CAP);
+    }
+    if (lane == 0) {
+        if (lkeys) atomicAdd(&ctl->local_keys, lkeys);
+        if (fkeys) atomicAdd(&ctl->fill_keys, fkeys);
     }
 }
 
 // Count of the <= side after a single-segment pass (partition entry point).
 __global__ void k_write_count(const unsigned long long *cur, int64_t *d_count)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *d_count = (int64_t)(uint32_t)cur[0];
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d_count = (int64_t)(uint32_t)cur[0];  // segment 0
 }
 
 // ---------------------------------------------------------------- on-chip sort
 
+// T: the on-chip segment limit (keys per task); NT: threads per workgroup;
+// LEAF: the largest range handed to the bitonic network; WPC: workgroups
+// resident per CU (LDS: 160 KB per CU; registers: 16 waves per CU keep the
+// 128-VGPR budget that the chunk of keys per thread needs).
 template <typename K> struct LocalCfg;
-template <> struct LocalCfg<uint32_t> { static constexpr int T = 16384, NT = 1024, KPT = 16, LEAF = 256; };
-template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 1024, KPT = 8, LEAF = 256; };
+template <> struct LocalCfg<uint32_t> { static constexpr int T = 16384, NT = 1024, LEAF = 256, WPC = 1; };
+template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 512, LEAF = 256, WPC = 2; };
 
 // Sort the keys of one wave's registers (any load order) with the smallest
 // network that holds `sz` keys, and hand back key i of the sorted order to
@@ -549,250 +663,292 @@ __device__ __forceinline__ void wave_sort_n(uint32_t sz, int lane, const Ld &ld,
     }
 }
 
-template <typename K, typename Ld, typename St>
+// The paper's wrapper (Sec. III-A, "Sorting Small Arrays"): pad to the next
+// network size with the greatest key and pick the network by size.
+template <int LEAF, typename K, typename Ld, typename St>
 __device__ __forceinline__ void wave_sort(uint32_t sz, int lane, const Ld &ld, const St &st)
 {
     if (sz <= 64) wave_sort_n<1, K>(sz, lane, ld, st);
     else if (sz <= 128) wave_sort_n<2, K>(sz, lane, ld, st);
-    else wave_sort_n<4, K>(sz, lane, ld, st);
+    else if (LEAF <= 256 || sz <= 256) wave_sort_n<4, K>(sz, lane, ld, st);
+    else if constexpr (LEAF >= 512) {
+        if (LEAF <= 512 || sz <= 512) wave_sort_n<8, K>(sz, lane, ld, st);
+        else if constexpr (LEAF >= 1024) wave_sort_n<16, K>(sz, lane, ld, st);
+    }
 }
 
-// One workgroup per task (claimed dynamically).  The task's keys are loaded
-// into LDS; every level partitions all live sub-ranges at once, three ways
-// (< pivot, == pivot, > pivot), with positions from one workgroup-wide scan
-// of packed (lt, eq) counts; thread t owns the contiguous chunk
-// [t*KPT, (t+1)*KPT) and LDS keeps one pad slot per chunk so chunk reads are
-// free of bank conflicts.  Sub-ranges of at most LEAF keys go to the bitonic
-// network (one wave each) as soon as they appear; runs equal to a pivot are
-// final.  The sorted range is stored back in the caller's format.
-template <int F>
-__global__ __launch_bounds__(1024, 8) void k_local(Ctl *ctl, const Task<typename KeyOf<F>::type> *tasks,
-                                                   typename KeyOf<F>::type *buf0,
-                                                   typename KeyOf<F>::type *buf1, Raw raw, int rule,
-                                                   uint32_t task_cap)
+// One workgroup per task (claimed dynamically; the next claim is issued at
+// the start of a task so its latency hides behind the task).  The task's
+// keys are loaded into LDS; every level partitions all live sub-ranges at
+// once, three ways (< pivot, == pivot, > pivot), with positions from one
+// workgroup-wide scan of packed (lt, eq) counts.  Thread t owns the
+// contiguous chunk [t*KPT, (t+1)*KPT) and LDS keeps one pad slot per chunk,
+// so chunk reads are free of bank conflicts.  Sub-ranges of at most LEAF keys
+// are queued and sorted by the bitonic network after the last level, one
+// wave per range; runs equal to a pivot are final.  The sorted range is
+// stored back in the caller's format.
+template <int F, int NT, int T, int LEAF, int WPC>
+__global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Task<typename KeyOf<F>::type> *tasks,
+                                              typename KeyOf<F>::type *buf0, typename KeyOf<F>::type *buf1,
+                                              Raw raw, int rule, uint32_t task_cap)
 {
     using K = typename KeyOf<F>::type;
-    using C = LocalCfg<K>;
-    static_assert(C::NT * C::KPT == C::T, "one chunk of KPT keys per thread");
-    constexpr int T = C::T, NT = C::NT, KPT = C::KPT, LEAF = C::LEAF;
+    constexpr int KPT = T / NT;
     constexpr int NW = NT / WAVE;
     constexpr int MAXACT = T / (LEAF + 1) + 1;
-    constexpr int MAXLEAF = 2 * MAXACT;
+    constexpr int MAXLEAF = 256;
+    static_assert(NT * KPT == T, "one chunk of KPT keys per thread");
     static_assert(MAXACT <= WAVE, "one wave builds the range list");
     static_assert(KPT <= 32, "per-key masks are 32-bit");
 
     __shared__ K sk[T + T / KPT];
-    __shared__ uint32_t act_b[2][MAXACT], act_e[2][MAXACT];
-    __shared__ K act_p[2][MAXACT];
+    __shared__ uint32_t act_b[MAXACT], act_e[MAXACT];
+    __shared__ K act_p[MAXACT];
     __shared__ uint32_t SB[MAXACT], SE[MAXACT];
     __shared__ uint32_t leaf_b[MAXLEAF], leaf_e[MAXLEAF];
     __shared__ uint32_t wsum[NW];
-    __shared__ uint32_t s_nact, s_nleaf, s_list, s_task;
+    __shared__ uint32_t s_nact, s_nleaf, s_task[2];
 
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     const uint32_t ntask = min(ctl->ntask, task_cap);
     auto E = [](uint32_t p) { return p + p / KPT; };
+    auto lds_rd = [&](uint32_t p) { return sk[E(p)]; };
 
-    for (;;) {
-        if (tid == 0) s_task = atomicAdd(&ctl->task_next, 1u);
-        __syncthreads();
-        const uint32_t ti = s_task;
-        __syncthreads();
+    if (tid == 0) s_task[0] = atomicAdd(&ctl->task_next, 1u);
+    __syncthreads();
+    uint32_t ti = s_task[0];
+    for (int par = 1;; par ^= 1) {
         if (ti >= ntask) break;
+        uint32_t next = 0;
+        if (tid == 0) next = atomicAdd(&ctl->task_next, 1u);  // consumed at the end of the task
         const Task<K> tk = tasks[ti];
         const uint32_t b = tk.b, m = tk.e - tk.b;
+        const K *sbuf = tk.src == SRC_BUF0 ? buf0 : buf1;
+        const bool sraw = tk.src == SRC_RAW;
 
         if (tk.kind == TASK_FILL) {
             for (uint32_t i = tid; i < m; i += NT) raw_store<F>(raw, b + i, tk.fill);
-            continue;
-        }
-        const K *sbuf = tk.src == SRC_BUF0 ? buf0 : buf1;
-        const bool sraw = tk.src == SRC_RAW;
-        auto gload = [&](uint32_t i) -> K { return sraw ? raw_load<F>(raw, i) : sbuf[i]; };
-
-        if (m <= (uint32_t)LEAF) {
+        } else if (m <= (uint32_t)LEAF) {
             if (wave == 0) {
-                wave_sort<K>(m, lane, [&](uint32_t p) { return gload(b + p); },
-                             [&](uint32_t i, K v) { raw_store<F>(raw, b + i, v); });
+                if (sraw)
+                    wave_sort<LEAF, K>(m, lane, [&](uint32_t p) { return raw_load<F>(raw, b + p); },
+                                       [&](uint32_t i, K v) { raw_store<F>(raw, b + i, v); });
+                else
+                    wave_sort<LEAF, K>(m, lane, [&](uint32_t p) { return sbuf[b + p]; },
+                                       [&](uint32_t i, K v) { raw_store<F>(raw, b + i, v); });
             }
-            continue;
-        }
-
-        for (uint32_t i = tid; i < m; i += NT) sk[E(i)] = gload(b + i);
-        __syncthreads();
-        if (tid == 0) {
-            act_b[0][0] = 0;
-            act_e[0][0] = m;
-            auto rd = [&](uint32_t p) { return sk[E(p)]; };
-            act_p[0][0] = pick_pivot<K>(rd, 0, m, rule);
-            s_nact = 1;
-            s_list = 0;
-        }
-        __syncthreads();
-
-        for (;;) {
-            const uint32_t na = s_nact, L = s_list;
-            if (na == 0) break;
-            // ---- load my chunk and classify against my sub-range's pivot
-            const uint32_t t0 = (uint32_t)tid * KPT;
-            K x[KPT];
+        } else {
+            {  // global -> registers -> LDS, all loads in flight at once
+                K x[KPT];
+                if (sraw) {
 #pragma unroll
-            for (int j = 0; j < KPT; ++j) x[j] = (t0 + j < m) ? sk[t0 + j + tid] : K(0);
-            int s0 = -1;
-            {
-                int lo = 0, hi = (int)na;  // largest s with act_b[s] <= t0
-                while (lo < hi) {
-                    const int md = (lo + hi) >> 1;
-                    if (act_b[L][md] <= t0) lo = md + 1; else hi = md;
+                    for (int j = 0; j < KPT; ++j) {
+                        const uint32_t i = (uint32_t)(j * NT + tid);
+                        x[j] = i < m ? raw_load<F>(raw, b + i) : K(0);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < KPT; ++j) {
+                        const uint32_t i = (uint32_t)(j * NT + tid);
+                        x[j] = i < m ? sbuf[b + i] : K(0);
+                    }
                 }
-                s0 = lo - 1;
+#pragma unroll
+                for (int j = 0; j < KPT; ++j) {
+                    const uint32_t i = (uint32_t)(j * NT + tid);
+                    if (i < m) sk[E(i)] = x[j];
+                }
             }
-            uint32_t ltm = 0, eqm = 0, inm = 0, cl = 0, ce = 0;
-            {
-                int s = s0;
-                uint32_t se = s >= 0 ? act_e[L][s] : 0u;
-                K sp = s >= 0 ? act_p[L][s] : K(0);
-                uint32_t nb = (s + 1 < (int)na) ? act_b[L][s + 1] : 0xFFFFFFFFu;
+            __syncthreads();
+            if (tid == 0) {
+                act_b[0] = 0;
+                act_e[0] = m;
+                act_p[0] = pick_pivot<K>(lds_rd, 0, m, rule);
+                s_nact = 1;
+                s_nleaf = 0;
+            }
+            __syncthreads();
+
+            for (;;) {
+                const uint32_t na = s_nact;
+                if (na == 0) break;
+                // ---- load my chunk and classify it.  A live range is longer than a
+                //      chunk, so the chunk meets at most two: range A holds the keys
+                //      before index jb, range B the keys from jb on.
+                const uint32_t t0 = (uint32_t)tid * KPT;
+                K x[KPT];
+#pragma unroll
+                for (int j = 0; j < KPT; ++j) x[j] = (t0 + j < m) ? sk[t0 + j + tid] : K(0);
+                int sA;
+                {
+                    int lo = 0, hi = (int)na;  // first s with act_b[s] > t0
+                    while (lo < hi) {
+                        const int md = (lo + hi) >> 1;
+                        if (act_b[md] <= t0) lo = md + 1; else hi = md;
+                    }
+                    sA = lo - 1;
+                }
+                const int sB = sA + 1;
+                const bool hasB = sB < (int)na && act_b[sB] < t0 + KPT;
+                const uint32_t jb = hasB ? act_b[sB] - t0 : (uint32_t)KPT;
+                const uint32_t bA = sA >= 0 ? act_b[sA] : 0u, eA = sA >= 0 ? act_e[sA] : 0u;
+                const K pA = sA >= 0 ? act_p[sA] : K(0);
+                const uint32_t bB = hasB ? act_b[sB] : 0u, eB = hasB ? act_e[sB] : 0u;
+                const K pB = hasB ? act_p[sB] : K(0);
+                uint32_t ltm = 0, eqm = 0, inm = 0;
 #pragma unroll
                 for (int j = 0; j < KPT; ++j) {
                     const uint32_t p = t0 + j;
-                    if (p >= nb) {
-                        ++s;
-                        se = act_e[L][s];
-                        sp = act_p[L][s];
-                        nb = (s + 1 < (int)na) ? act_b[L][s + 1] : 0xFFFFFFFFu;
-                    }
-                    if (s >= 0 && p < se) {
+                    const bool inB = (uint32_t)j >= jb;
+                    const bool in = inB ? true : (p < eA);  // sA < 0 gives eA = 0
+                    const K sp = inB ? pB : pA;
+                    if (in) {
                         inm |= 1u << j;
-                        if (x[j] < sp) {
-                            ltm |= 1u << j;
-                            ++cl;
-                        } else if (x[j] == sp) {
-                            eqm |= 1u << j;
-                            ++ce;
+                        if (x[j] < sp) ltm |= 1u << j;
+                        else if (x[j] == sp) eqm |= 1u << j;
+                    }
+                }
+                const uint32_t code = (uint32_t)__builtin_popcount(ltm) | ((uint32_t)__builtin_popcount(eqm) << 16);
+                const uint32_t incl = wave_incl_scan(code);
+                if (lane == WAVE - 1) wsum[wave] = incl;
+                __syncthreads();
+                uint32_t pre = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) pre += (w < wave) ? wsum[w] : 0u;
+                const uint32_t excl = pre + incl - code;
+                // prefix (packed lt | eq << 16) before chunk key j
+                auto pre_at = [&](uint32_t j) {
+                    const uint32_t below = j >= 32u ? 0xFFFFFFFFu : ((1u << j) - 1u);
+                    return excl + (uint32_t)__builtin_popcount(ltm & below) +
+                           ((uint32_t)__builtin_popcount(eqm & below) << 16);
+                };
+                // ---- prefix at the first and last key of every live range
+                if (sA >= 0 && bA >= t0) SB[sA] = pre_at(bA - t0);
+                if (sA >= 0 && eA > t0 && eA <= t0 + jb) SE[sA] = pre_at(eA - t0);
+                if (hasB) {
+                    SB[sB] = pre_at(jb);
+                    if (eB <= t0 + KPT) SE[sB] = pre_at(eB - t0);
+                }
+                __syncthreads();
+                // ---- scatter to the new positions (every key of the pass is in registers)
+                {
+                    const uint32_t sbA = sA >= 0 ? SB[sA] : 0u, tlA = sA >= 0 ? SE[sA] - sbA : 0u;
+                    const uint32_t sbB = hasB ? SB[sB] : 0u, tlB = hasB ? SE[sB] - sbB : 0u;
+                    uint32_t run = excl;
+#pragma unroll
+                    for (int j = 0; j < KPT; ++j) {
+                        const uint32_t p = t0 + j;
+                        const bool inB = (uint32_t)j >= jb;
+                        if (inm & (1u << j)) {
+                            const uint32_t sb = inB ? bB : bA;
+                            const uint32_t r = run - (inB ? sbB : sbA);
+                            const uint32_t tl = inB ? tlB : tlA;
+                            const uint32_t rl = r & 0xFFFFu, re = r >> 16;
+                            const uint32_t nl = tl & 0xFFFFu, ne = tl >> 16;
+                            uint32_t np;
+                            if (ltm & (1u << j)) np = sb + rl;
+                            else if (eqm & (1u << j)) np = sb + nl + re;
+                            else np = sb + nl + ne + (p - sb - rl - re);
+                            sk[E(np)] = x[j];
+                            run += (ltm >> j & 1u) | ((eqm >> j & 1u) << 16);
                         }
                     }
                 }
-            }
-            const uint32_t code = cl | (ce << 16);
-            const uint32_t incl = wave_incl_scan(code);
-            if (lane == WAVE - 1) wsum[wave] = incl;
-            __syncthreads();
-            uint32_t pre = 0;
-            for (int w = 0; w < wave; ++w) pre += wsum[w];
-            const uint32_t excl = pre + incl - code;
-            // ---- sub-range boundary prefixes
-            {
-                int s = s0;
-                uint32_t sb = s >= 0 ? act_b[L][s] : 0u, se = s >= 0 ? act_e[L][s] : 0u;
-                uint32_t nb = (s + 1 < (int)na) ? act_b[L][s + 1] : 0xFFFFFFFFu;
-                uint32_t run = excl;
-#pragma unroll
-                for (int j = 0; j < KPT; ++j) {
-                    const uint32_t p = t0 + j;
-                    if (p >= nb) {
-                        ++s;
-                        sb = act_b[L][s];
-                        se = act_e[L][s];
-                        nb = (s + 1 < (int)na) ? act_b[L][s + 1] : 0xFFFFFFFFu;
-                    }
-                    if (inm & (1u << j)) {
-                        if (p == sb) SB[s] = run;
-                        run += (ltm >> j & 1u) | ((eqm >> j & 1u) << 16);
-                        if (p + 1 == se) SE[s] = run;
-                    }
-                }
-            }
-            __syncthreads();
-            // ---- scatter to the new positions (every key of the pass is in registers)
-            {
-                int s = s0;
-                uint32_t sb = s >= 0 ? act_b[L][s] : 0u, sbp = s >= 0 ? SB[s] : 0u;
-                uint32_t tl = s >= 0 ? SE[s] - SB[s] : 0u;
-                uint32_t nb = (s + 1 < (int)na) ? act_b[L][s + 1] : 0xFFFFFFFFu;
-                uint32_t run = excl;
-#pragma unroll
-                for (int j = 0; j < KPT; ++j) {
-                    const uint32_t p = t0 + j;
-                    if (p >= nb) {
-                        ++s;
-                        sb = act_b[L][s];
-                        sbp = SB[s];
-                        tl = SE[s] - SB[s];
-                        nb = (s + 1 < (int)na) ? act_b[L][s + 1] : 0xFFFFFFFFu;
-                    }
-                    if (inm & (1u << j)) {
-                        const uint32_t r = run - sbp;
-                        const uint32_t rl = r & 0xFFFFu, re = r >> 16;
+                __syncthreads();
+                // ---- next list (in place): children larger than LEAF stay live,
+                //      children of 2..LEAF keys are queued for the network
+                if (wave == 0) {
+                    const uint32_t s = (uint32_t)lane;
+                    uint32_t lb = 0, le = 0, rb = 0, re = 0;
+                    if (s < na) {
+                        const uint32_t b0 = act_b[s], e0 = act_e[s];
+                        const uint32_t tl = SE[s] - SB[s];
                         const uint32_t nl = tl & 0xFFFFu, ne = tl >> 16;
-                        uint32_t np;
-                        if (ltm & (1u << j)) np = sb + rl;
-                        else if (eqm & (1u << j)) np = sb + nl + re;
-                        else np = sb + nl + ne + (p - sb - rl - re);
-                        sk[E(np)] = x[j];
-                        run += (ltm >> j & 1u) | ((eqm >> j & 1u) << 16);
+                        lb = b0;
+                        le = b0 + nl;
+                        rb = b0 + nl + ne;
+                        re = e0;
+                    }
+                    const bool aL = le - lb > (uint32_t)LEAF, aR = re - rb > (uint32_t)LEAF;
+                    const bool fL = le - lb >= 2 && !aL, fR = re - rb >= 2 && !aR;
+                    K pl = 0, pr = 0;
+                    if (aL) pl = pick_pivot<K>(lds_rd, lb, le, rule);
+                    if (aR) pr = pick_pivot<K>(lds_rd, rb, re, rule);
+                    const uint32_t na_me = (uint32_t)aL + (uint32_t)aR, nf_me = (uint32_t)fL + (uint32_t)fR;
+                    const uint32_t ai = wave_incl_scan(na_me), fi = wave_incl_scan(nf_me);
+                    const uint32_t nleaf0 = s_nleaf;
+                    const uint32_t ntot = (uint32_t)__builtin_amdgcn_readlane((int)ai, WAVE - 1);
+                    const uint32_t ftot = (uint32_t)__builtin_amdgcn_readlane((int)fi, WAVE - 1);
+                    uint32_t ap = ai - na_me, fp = nleaf0 + fi - nf_me;
+                    // every lane has read the current list above: overwrite it in place
+                    if (aL) {
+                        act_b[ap] = lb;
+                        act_e[ap] = le;
+                        act_p[ap] = pl;
+                        ++ap;
+                    }
+                    if (aR) {
+                        act_b[ap] = rb;
+                        act_e[ap] = re;
+                        act_p[ap] = pr;
+                    }
+                    const bool room = nleaf0 + ftot <= (uint32_t)MAXLEAF;
+                    if (room) {
+                        if (fL) {
+                            leaf_b[fp] = lb;
+                            leaf_e[fp] = le;
+                            ++fp;
+                        }
+                        if (fR) {
+                            leaf_b[fp] = rb;
+                            leaf_e[fp] = re;
+                        }
+                    } else {  // queue full (rare): this wave sorts the new leaves now
+                        for (int src = 0; src < WAVE; ++src) {
+                            const uint32_t b1 = (uint32_t)__builtin_amdgcn_readlane((int)lb, src);
+                            const uint32_t e1 = (uint32_t)__builtin_amdgcn_readlane((int)le, src);
+                            const uint32_t b2 = (uint32_t)__builtin_amdgcn_readlane((int)rb, src);
+                            const uint32_t e2 = (uint32_t)__builtin_amdgcn_readlane((int)re, src);
+                            if (e1 - b1 >= 2 && e1 - b1 <= (uint32_t)LEAF)
+                                wave_sort<LEAF, K>(e1 - b1, lane, [&](uint32_t q) { return sk[E(b1 + q)]; },
+                                                   [&](uint32_t q, K v) { sk[E(b1 + q)] = v; });
+                            if (e2 - b2 >= 2 && e2 - b2 <= (uint32_t)LEAF)
+                                wave_sort<LEAF, K>(e2 - b2, lane, [&](uint32_t q) { return sk[E(b2 + q)]; },
+                                                   [&](uint32_t q, K v) { sk[E(b2 + q)] = v; });
+                        }
+                    }
+                    if (lane == 0) {
+                        s_nact = ntot;
+                        if (room) s_nleaf = nleaf0 + ftot;
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
-            // ---- next list: children larger than LEAF stay live, 2..LEAF become leaves
-            if (wave == 0) {
-                const uint32_t s = (uint32_t)lane;
-                uint32_t lb = 0, le = 0, rb = 0, re = 0;
-                if (s < na) {
-                    const uint32_t b0 = act_b[L][s], e0 = act_e[L][s];
-                    const uint32_t tl = SE[s] - SB[s];
-                    const uint32_t nl = tl & 0xFFFFu, ne = tl >> 16;
-                    lb = b0;
-                    le = b0 + nl;
-                    rb = b0 + nl + ne;
-                    re = e0;
-                }
-                const bool aL = le - lb > (uint32_t)LEAF, aR = re - rb > (uint32_t)LEAF;
-                const bool fL = le - lb >= 2 && !aL, fR = re - rb >= 2 && !aR;
-                const uint32_t na_me = (uint32_t)aL + (uint32_t)aR, nf_me = (uint32_t)fL + (uint32_t)fR;
-                const uint32_t ai = wave_incl_scan(na_me), fi = wave_incl_scan(nf_me);
-                uint32_t ap = ai - na_me, fp = fi - nf_me;
-                const uint32_t N = 1u - L;
-                auto rd = [&](uint32_t p) { return sk[E(p)]; };
-                if (aL) {
-                    act_b[N][ap] = lb;
-                    act_e[N][ap] = le;
-                    act_p[N][ap] = pick_pivot<K>(rd, lb, le, rule);
-                    ++ap;
-                }
-                if (aR) {
-                    act_b[N][ap] = rb;
-                    act_e[N][ap] = re;
-                    act_p[N][ap] = pick_pivot<K>(rd, rb, re, rule);
-                }
-                if (fL) {
-                    leaf_b[fp] = lb;
-                    leaf_e[fp] = le;
-                    ++fp;
-                }
-                if (fR) {
-                    leaf_b[fp] = rb;
-                    leaf_e[fp] = re;
-                }
-                if (lane == WAVE - 1) {
-                    s_nact = ai;
-                    s_nleaf = fi;
-                    s_list = N;
-                }
-            }
-            __syncthreads();
-            // ---- bitonic network on this level's leaves, one wave per leaf
+            // ---- bitonic network on every queued range, one wave per range
             const uint32_t nleaf = s_nleaf;
             for (uint32_t li = (uint32_t)wave; li < nleaf; li += NW) {
                 const uint32_t fb = leaf_b[li], fe = leaf_e[li];
-                wave_sort<K>(fe - fb, lane, [&](uint32_t p) { return sk[E(fb + p)]; },
-                             [&](uint32_t i, K v) { sk[E(fb + i)] = v; });
+                wave_sort<LEAF, K>(fe - fb, lane, [&](uint32_t q) { return sk[E(fb + q)]; },
+                                   [&](uint32_t q, K v) { sk[E(fb + q)] = v; });
             }
             __syncthreads();
+            {  // LDS -> registers -> global, in the caller's format
+                K x[KPT];
+#pragma unroll
+                for (int j = 0; j < KPT; ++j) {
+                    const uint32_t i = (uint32_t)(j * NT + tid);
+                    x[j] = i < m ? sk[E(i)] : K(0);
+                }
+#pragma unroll
+                for (int j = 0; j < KPT; ++j) {
+                    const uint32_t i = (uint32_t)(j * NT + tid);
+                    if (i < m) raw_store<F>(raw, b + i, x[j]);
+                }
+            }
         }
-        for (uint32_t i = tid; i < m; i += NT) raw_store<F>(raw, b + i, sk[E(i)]);
+        if (tid == 0) s_task[par] = next;
         __syncthreads();
+        ti = s_task[par];
     }
 }
 

@@ -121,7 +121,7 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T)
     }
     L.segA = take((size_t)L.cand_cap * sizeof(Seg<K>));
     L.segB = take((size_t)L.cand_cap * sizeof(Seg<K>));
-    L.cur = take((size_t)L.cand_cap * 8);
+    L.cur = take((size_t)L.cand_cap * 8 * CUR_STRIDE);
     L.tasks = take((size_t)L.task_cap * sizeof(Task<K>));
     L.ctl = take(sizeof(Ctl));
     L.total = off;
@@ -222,7 +222,7 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
 
     HS_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), stream));
     if (d_off) {
-        const uint32_t g = (uint32_t)((nseg + 255) / 256);
+        const uint32_t g = (uint32_t)((nseg + 255) / 256);  // one wave per 64 segments
         k_init_segmented<F><<<g, 256, 0, stream>>>(ctl, segs[0], tasks, raw, d_off, (uint32_t)nseg, (uint32_t)n, T,
                                                    rule, L.cand_cap, L.task_cap);
     } else {
@@ -231,51 +231,63 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
     HS_LAUNCHED();
     k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[0], cur, L.cand_cap);
     HS_LAUNCHED();
-    HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-    HS_HIP(hipStreamSynchronize(stream));
-    if (h->err) return fail(HS_EINTERNAL, "init reported error bits 0x%x", h->err);
 
-    int64_t levels = 0, keys_part = 0;
-    int cur_list = 0;
-    const int maxg = d->ncu * 8;
-    int lrule = rule;
+    // Levels are launched in batches with fixed grids (every kernel reads the
+    // level's size from the control block), and the host reads the control
+    // block back once per batch.  A batch covers the levels that the largest
+    // live segment needs with balanced splits, plus one.
+    auto levels_for = [&](uint64_t size) {
+        int l = 1;
+        while (size > T) {
+            size = (size + 1) / 2;
+            ++l;
+        }
+        return l;
+    };
+    const int part_grid = d->ncu * 8;
+    const int fin_grid = d->ncu * 4;
     int guard = 2;
-    for (int64_t x = n; x > 1; x >>= 1) ++guard;  // 2 + log2(n)
-    for (int level = 0; h->nseg > 0; ++level) {
-        if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
-        if (level > guard) lrule = PIVOT_SAMPLE;  // depth guard
-        const uint32_t nsegs = h->nseg, ntiles = h->ntiles;
-        keys_part += (int64_t)h->level_keys;
-        const int g = (int)(ntiles < (uint32_t)maxg ? ntiles : (uint32_t)maxg);
-        const uint32_t out_id = (uint32_t)((level + 1) & 1);
-        if (st) HS_HIP(hipEventRecord(d->ev[2 * level], stream));
-        if (level == 0)
-            k_partition<F, true, false><<<g, PartCfg<K>::NT, 0, stream>>>(ctl, segs[cur_list], cur, nullptr, raw,
-                                                                          buf[out_id], Raw{}, aligned);
-        else
-            k_partition<F, false, false><<<g, PartCfg<K>::NT, 0, stream>>>(
-                ctl, segs[cur_list], cur, buf[level & 1], raw, buf[out_id], Raw{},
-                (F == FMT_KV || aligned) ? 1 : 0);
-        HS_LAUNCHED();
-        if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
-        k_finalize<F><<<(nsegs + 255) / 256, 256, 0, stream>>>(ctl, segs[cur_list], cur, segs[1 - cur_list],
-                                                               tasks, buf[out_id], out_id, T, lrule,
-                                                               L.cand_cap, L.task_cap);
-        HS_LAUNCHED();
-        cur_list = 1 - cur_list;
-        k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[cur_list], cur, L.cand_cap);
-        HS_LAUNCHED();
+    for (int64_t x = n; x > 1; x >>= 1) ++guard;  // 2 + log2(n): beyond it, sample-median pivots
+    int level = 0, cur_list = 0;
+    int batch = d_off ? 1 : ((uint64_t)n > T ? levels_for((uint64_t)n) : 0);
+    for (;;) {
+        for (int bi = 0; bi < batch && level < LMAX; ++bi, ++level) {
+            const int lrule = level > guard ? PIVOT_SAMPLE : rule;
+            const uint32_t out_id = (uint32_t)((level + 1) & 1);
+            if (st) HS_HIP(hipEventRecord(d->ev[2 * level], stream));
+            if (level == 0)
+                k_partition<F, true, false><<<part_grid, PartCfg<K>::NT, 0, stream>>>(
+                    ctl, segs[cur_list], cur, nullptr, raw, buf[out_id], Raw{}, aligned);
+            else
+                k_partition<F, false, false><<<part_grid, PartCfg<K>::NT, 0, stream>>>(
+                    ctl, segs[cur_list], cur, buf[level & 1], raw, buf[out_id], Raw{},
+                    (F == FMT_KV || aligned) ? 1 : 0);
+            HS_LAUNCHED();
+            if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
+            k_finalize<F><<<fin_grid, 256, 0, stream>>>(ctl, segs[cur_list], cur, segs[1 - cur_list], tasks,
+                                                        buf[out_id], out_id, T, lrule, L.cand_cap, L.task_cap);
+            HS_LAUNCHED();
+            cur_list = 1 - cur_list;
+            k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[cur_list], cur, L.cand_cap);
+            HS_LAUNCHED();
+        }
         HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         HS_HIP(hipStreamSynchronize(stream));
-        if (h->err) return fail(HS_EINTERNAL, "level %d reported error bits 0x%x", level, h->err);
-        ++levels;
+        if (h->err) return fail(HS_EINTERNAL, "partition levels reported error bits 0x%x", h->err);
+        if (h->nseg == 0) break;
+        if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
+        batch = levels_for(h->max_seg);
     }
+    const int64_t levels = level;
     const uint32_t ntask = h->ntask;
     hipEvent_t *lev = &d->ev[2 * LMAX];
     if (ntask > 0) {
-        const int g = (int)(ntask < (uint32_t)(d->ncu * 2) ? ntask : (uint32_t)(d->ncu * 2));
+        using LC = LocalCfg<K>;
+        const uint32_t gmax = (uint32_t)(d->ncu * LC::WPC);
+        const int g = (int)(ntask < gmax ? ntask : gmax);
         if (st) HS_HIP(hipEventRecord(lev[0], stream));
-        k_local<F><<<g, LocalCfg<K>::NT, 0, stream>>>(ctl, tasks, buf[0], buf[1], raw, local_rule, L.task_cap);
+        k_local<F, LC::NT, LC::T, LC::LEAF, LC::WPC>
+            <<<g, LC::NT, 0, stream>>>(ctl, tasks, buf[0], buf[1], raw, local_rule, L.task_cap);
         HS_LAUNCHED();
         if (st) HS_HIP(hipEventRecord(lev[1], stream));
     }
@@ -284,11 +296,11 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
         HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         HS_HIP(hipStreamSynchronize(stream));
         std::memset(st, 0, sizeof *st);
-        st->passes = levels;
-        st->keys_partitioned = keys_part;
+        st->passes = h->levels;
+        st->keys_partitioned = (int64_t)h->part_keys;
         st->tasks = ntask;
-        st->max_depth = levels;
-        st->bytes_alg = (int64_t)(2 * sizeof(K)) * (keys_part + (int64_t)h->local_keys) +
+        st->max_depth = h->levels;
+        st->bytes_alg = (int64_t)(2 * sizeof(K)) * ((int64_t)h->part_keys + (int64_t)h->local_keys) +
                         (int64_t)sizeof(K) * (int64_t)h->fill_keys;
         st->partition_launches = levels;
         for (int64_t l = 0; l < levels; ++l) {
