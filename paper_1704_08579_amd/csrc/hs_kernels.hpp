@@ -69,7 +69,8 @@ struct Ctl {
     unsigned long long level_keys;   // keys in the current level's segments
     unsigned long long part_keys;    // sum of level_keys over the levels run
     alignas(256) uint32_t ncand;     // segments written for the next level
-    alignas(256) uint32_t ntask;     // tasks written
+    alignas(256) uint32_t ntask;     // tasks for k_local, written from the front of the task list
+    alignas(256) uint32_t nsmall;    // tasks for k_small, written from the back of the task list
     alignas(256) uint32_t task_next; // dynamic task counter of k_local
     alignas(256) uint32_t err;       // ERR_* bits
     alignas(256) unsigned long long local_keys;  // keys handed to local tasks
@@ -81,7 +82,7 @@ struct Ctl {
 // single atomic per wave.
 template <typename T>
 __device__ __forceinline__ void wave_flush(const T &item, bool has, uint32_t *counter, T *list, uint32_t cap,
-                                           Ctl *ctl, uint32_t errbit)
+                                           Ctl *ctl, uint32_t errbit, bool from_back = false)
 {
     const uint64_t m = __ballot(has);
     if (m == 0) return;
@@ -91,9 +92,21 @@ __device__ __forceinline__ void wave_flush(const T &item, bool has, uint32_t *co
     base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
     const uint32_t k = base + mask_below(m);
     if (has) {
-        if (k < cap) list[k] = item;
+        if (k < cap) list[from_back ? cap - 1 - k : k] = item;
         else atomicOr(&ctl->err, errbit);
     }
+}
+
+// The task list holds on-chip tasks (sorted by k_local, one workgroup each)
+// from the front and small tasks (at most LEAF keys, or fills: one wave each
+// in k_small) from the back.  The two counts together never exceed its
+// capacity; an overflow sets ERR_TASK_CAP.
+template <typename T>
+__device__ __forceinline__ void wave_flush_task(const T &item, bool has, bool small, T *list, uint32_t cap,
+                                                Ctl *ctl)
+{
+    wave_flush(item, has && !small, &ctl->ntask, list, cap, ctl, ERR_TASK_CAP, false);
+    wave_flush(item, has && small, &ctl->nsmall, list, cap, ctl, ERR_TASK_CAP, true);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
@@ -105,7 +118,7 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
 // ---------------------------------------------------------------- tile geometry
 
 template <typename K> struct PartCfg;
-template <> struct PartCfg<uint32_t> { static constexpr int NT = 256, TILE = 8192; };
+template <> struct PartCfg<uint32_t> { static constexpr int NT = 512, TILE = 8192; };
 template <> struct PartCfg<uint64_t> { static constexpr int NT = 256, TILE = 4096; };
 
 // Write-cursor words of different segments sit 256 bytes apart: atomics on
@@ -176,8 +189,8 @@ __device__ K wave_pick_pivot(const Rd &rd, uint32_t b, uint32_t e, int rule, int
 // task when it fits on chip.
 template <int F>
 __global__ void k_init_single(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand, Task<typename KeyOf<F>::type> *tasks,
-                              Raw raw, uint32_t n, uint32_t T, int rule, int has_pivot,
-                              typename KeyOf<F>::type user_pivot)
+                              Raw raw, uint32_t n, uint32_t T, uint32_t leaf, uint32_t task_cap, int rule,
+                              int has_pivot, typename KeyOf<F>::type user_pivot)
 {
     using K = typename KeyOf<F>::type;
     if (blockIdx.x != 0 || threadIdx.x >= WAVE) return;
@@ -190,8 +203,13 @@ __global__ void k_init_single(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand, Task
             t.src = SRC_RAW;
             t.kind = TASK_LOCAL;
             t.fill = 0;
-            tasks[0] = t;
-            ctl->ntask = 1;
+            if (n > leaf) {
+                tasks[0] = t;
+                ctl->ntask = 1;
+            } else {
+                tasks[task_cap - 1] = t;
+                ctl->nsmall = 1;
+            }
             ctl->local_keys = n;
         }
         return;
@@ -222,7 +240,8 @@ template <int F>
 __global__ __launch_bounds__(256) void k_init_segmented(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand,
                                                         Task<typename KeyOf<F>::type> *tasks, Raw raw,
                                                         const int64_t *off, uint32_t nseg, uint32_t n_total,
-                                                        uint32_t T, int rule, uint32_t cand_cap, uint32_t task_cap)
+                                                        uint32_t T, uint32_t leaf, int rule, uint32_t cand_cap,
+                                                        uint32_t task_cap)
 {
     using K = typename KeyOf<F>::type;
     const int lane = lane_id();
@@ -248,7 +267,7 @@ __global__ __launch_bounds__(256) void k_init_segmented(Ctl *ctl, Seg<typename K
     t.src = SRC_RAW;
     t.kind = TASK_LOCAL;
     t.fill = 0;
-    wave_flush(t, is_task, &ctl->ntask, tasks, task_cap, ctl, ERR_TASK_CAP);
+    wave_flush_task(t, is_task, m <= leaf, tasks, task_cap, ctl);
     const unsigned long long lk = wave_sum64(is_task ? (unsigned long long)m : 0ull);
     if (lane == 0 && lk) atomicAdd(&ctl->local_keys, lk);
 
@@ -346,7 +365,7 @@ template <typename K> struct TileLoc {
 // 3's left_w and right_w), compact the tile in LDS (<= keys first) and write
 // both runs out with consecutive lanes on consecutive addresses.
 template <int F, bool SRC_IS_RAW, bool DST_IS_RAW>
-__global__ __launch_bounds__(256) void k_partition(const Ctl *ctl, const Seg<typename KeyOf<F>::type> *segs,
+__global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partition(const Ctl *ctl, const Seg<typename KeyOf<F>::type> *segs,
                                                    unsigned long long *cur, const typename KeyOf<F>::type *src,
                                                    Raw raw, typename KeyOf<F>::type *dst, Raw raw_dst,
                                                    int aligned)
@@ -544,7 +563,8 @@ __global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, const Seg<typename K
                                                   Seg<typename KeyOf<F>::type> *cand,
                                                   Task<typename KeyOf<F>::type> *tasks,
                                                   const typename KeyOf<F>::type *out, uint32_t out_id,
-                                                  uint32_t T, int rule, uint32_t cand_cap, uint32_t task_cap)
+                                                  uint32_t T, uint32_t leaf, int rule, uint32_t cand_cap,
+                                                  uint32_t task_cap)
 {
     using K = typename KeyOf<F>::type;
     const int lane = lane_id();
@@ -560,6 +580,8 @@ __global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, const Seg<typename K
         Task<K> t0, t1;
         bool h_c0 = false, h_c1 = false, h_t0 = false, h_t1 = false;
         c0.tile0 = c1.tile0 = 0;
+        t0.kind = t1.kind = TASK_LOCAL;
+        t0.b = t0.e = t1.b = t1.e = 0;
         for (uint32_t k = 0; k < (uint32_t)WAVE; ++k) {
             const uint64_t i64 = w + (uint64_t)(step0 + k) * nwaves;
             if (i64 >= nseg) break;
@@ -618,8 +640,8 @@ __global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, const Seg<typename K
         }
         wave_flush(c0, h_c0, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
         wave_flush(c1, h_c1, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
-        wave_flush(t0, h_t0, &ctl->ntask, tasks, task_cap, ctl, ERR_TASK_CAP);
-        wave_flush(t1, h_t1, &ctl->ntask, tasks, task_cap, ctl, ERR_TASK_CAP);
+        wave_flush_task(t0, h_t0, t0.kind == TASK_FILL || t0.e - t0.b <= leaf, tasks, task_cap, ctl);
+        wave_flush_task(t1, h_t1, t1.kind == TASK_FILL || t1.e - t1.b <= leaf, tasks, task_cap, ctl);
     }
     if (lane == 0) {
         if (lkeys) atomicAdd(&ctl->local_keys, lkeys);
@@ -640,8 +662,8 @@ __global__ void k_write_count(const unsigned long long *cur, int64_t *d_count)
 // resident per CU (LDS: 160 KB per CU; registers: 16 waves per CU keep the
 // 128-VGPR budget that the chunk of keys per thread needs).
 template <typename K> struct LocalCfg;
-template <> struct LocalCfg<uint32_t> { static constexpr int T = 16384, NT = 1024, LEAF = 256, WPC = 1; };
-template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 512, LEAF = 256, WPC = 2; };
+template <> struct LocalCfg<uint32_t> { static constexpr int T = 8192, NT = 512, LEAF = 512, WPC = 2; };
+template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 512, LEAF = 512, WPC = 2; };
 
 // Sort the keys of one wave's registers (any load order) with the smallest
 // network that holds `sz` keys, and hand back key i of the sorted order to
@@ -677,9 +699,9 @@ __device__ __forceinline__ void wave_sort(uint32_t sz, int lane, const Ld &ld, c
     }
 }
 
-// One workgroup per task (claimed dynamically; the next claim is issued at
-// the start of a task so its latency hides behind the task).  The task's
-// keys are loaded into LDS; every level partitions all live sub-ranges at
+// One workgroup per task of LEAF+1 .. T keys (claimed dynamically; the next
+// claim is issued at the start of a task so its latency hides behind the
+// task).  The task's keys are loaded into LDS; every level partitions all live sub-ranges at
 // once, three ways (< pivot, == pivot, > pivot), with positions from one
 // workgroup-wide scan of packed (lt, eq) counts.  Thread t owns the
 // contiguous chunk [t*KPT, (t+1)*KPT) and LDS keeps one pad slot per chunk,
@@ -726,18 +748,7 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
         const K *sbuf = tk.src == SRC_BUF0 ? buf0 : buf1;
         const bool sraw = tk.src == SRC_RAW;
 
-        if (tk.kind == TASK_FILL) {
-            for (uint32_t i = tid; i < m; i += NT) raw_store<F>(raw, b + i, tk.fill);
-        } else if (m <= (uint32_t)LEAF) {
-            if (wave == 0) {
-                if (sraw)
-                    wave_sort<LEAF, K>(m, lane, [&](uint32_t p) { return raw_load<F>(raw, b + p); },
-                                       [&](uint32_t i, K v) { raw_store<F>(raw, b + i, v); });
-                else
-                    wave_sort<LEAF, K>(m, lane, [&](uint32_t p) { return sbuf[b + p]; },
-                                       [&](uint32_t i, K v) { raw_store<F>(raw, b + i, v); });
-            }
-        } else {
+        {
             {  // global -> registers -> LDS, all loads in flight at once
                 K x[KPT];
                 if (sraw) {
@@ -949,6 +960,35 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
         if (tid == 0) s_task[par] = next;
         __syncthreads();
         ti = s_task[par];
+    }
+}
+
+// Small tasks, one wave each (waves take tasks in a grid-stride loop from
+// the back of the task list): a range of at most LEAF keys goes straight from
+// HBM through the bitonic network to the caller's array, and a fill task
+// writes its key over its range.
+template <int F, int LEAF>
+__global__ __launch_bounds__(256) void k_small(const Ctl *ctl, const Task<typename KeyOf<F>::type> *tasks,
+                                               const typename KeyOf<F>::type *buf0,
+                                               const typename KeyOf<F>::type *buf1, Raw raw, uint32_t task_cap)
+{
+    using K = typename KeyOf<F>::type;
+    const int lane = lane_id();
+    const uint32_t nsmall = min(ctl->nsmall, task_cap);
+    const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
+    for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < nsmall; i += nwaves) {
+        const Task<K> tk = tasks[task_cap - 1 - i];
+        const uint32_t b = tk.b, m = tk.e - tk.b;
+        if (tk.kind == TASK_FILL) {
+            for (uint32_t j = (uint32_t)lane; j < m; j += WAVE) raw_store<F>(raw, b + j, tk.fill);
+        } else if (tk.src == SRC_RAW) {
+            wave_sort<LEAF, K>(m, lane, [&](uint32_t p) { return raw_load<F>(raw, b + p); },
+                               [&](uint32_t j, K v) { raw_store<F>(raw, b + j, v); });
+        } else {
+            const K *sbuf = tk.src == SRC_BUF0 ? buf0 : buf1;
+            wave_sort<LEAF, K>(m, lane, [&](uint32_t p) { return sbuf[b + p]; },
+                               [&](uint32_t j, K v) { raw_store<F>(raw, b + j, v); });
+        }
     }
 }
 

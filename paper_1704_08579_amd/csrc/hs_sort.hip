@@ -198,6 +198,7 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
     const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
                          : (F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : HS_OP_SORT_KV_I32);
     const uint32_t T = local_limit<K>(o);
+    const uint32_t LEAF = (uint32_t)LocalCfg<K>::LEAF;
     const int rule = pivot_rule(o);
     const int local_rule = (o && o->pivot_rule > 0) ? o->pivot_rule : PIVOT_NINTHER;
     Layout L;
@@ -224,9 +225,10 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
     if (d_off) {
         const uint32_t g = (uint32_t)((nseg + 255) / 256);  // one wave per 64 segments
         k_init_segmented<F><<<g, 256, 0, stream>>>(ctl, segs[0], tasks, raw, d_off, (uint32_t)nseg, (uint32_t)n, T,
-                                                   rule, L.cand_cap, L.task_cap);
+                                                   LEAF, rule, L.cand_cap, L.task_cap);
     } else {
-        k_init_single<F><<<1, 64, 0, stream>>>(ctl, segs[0], tasks, raw, (uint32_t)n, T, rule, 0, K(0));
+        k_init_single<F><<<1, 64, 0, stream>>>(ctl, segs[0], tasks, raw, (uint32_t)n, T, LEAF, L.task_cap, rule, 0,
+                                               K(0));
     }
     HS_LAUNCHED();
     k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[0], cur, L.cand_cap);
@@ -244,7 +246,11 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
         }
         return l;
     };
-    const int part_grid = d->ncu * 8;
+    // one partition workgroup per resident slot: no partly filled last round
+    int occ = 0;
+    HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_partition<F, false, false>, PartCfg<K>::NT, 0));
+    if (occ < 1) occ = 1;
+    const int part_grid = d->ncu * occ;
     const int fin_grid = d->ncu * 4;
     int guard = 2;
     for (int64_t x = n; x > 1; x >>= 1) ++guard;  // 2 + log2(n): beyond it, sample-median pivots
@@ -265,7 +271,8 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
             HS_LAUNCHED();
             if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
             k_finalize<F><<<fin_grid, 256, 0, stream>>>(ctl, segs[cur_list], cur, segs[1 - cur_list], tasks,
-                                                        buf[out_id], out_id, T, lrule, L.cand_cap, L.task_cap);
+                                                        buf[out_id], out_id, T, LEAF, lrule, L.cand_cap,
+                                                        L.task_cap);
             HS_LAUNCHED();
             cur_list = 1 - cur_list;
             k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[cur_list], cur, L.cand_cap);
@@ -279,16 +286,24 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
         batch = levels_for(h->max_seg);
     }
     const int64_t levels = level;
-    const uint32_t ntask = h->ntask;
+    const uint32_t ntask = h->ntask, nsmall = h->nsmall;
+    if ((uint64_t)ntask + nsmall > L.task_cap) return fail(HS_EINTERNAL, "task list overflow");
     hipEvent_t *lev = &d->ev[2 * LMAX];
-    if (ntask > 0) {
+    if (ntask + nsmall > 0) {
         using LC = LocalCfg<K>;
-        const uint32_t gmax = (uint32_t)(d->ncu * LC::WPC);
-        const int g = (int)(ntask < gmax ? ntask : gmax);
         if (st) HS_HIP(hipEventRecord(lev[0], stream));
-        k_local<F, LC::NT, LC::T, LC::LEAF, LC::WPC>
-            <<<g, LC::NT, 0, stream>>>(ctl, tasks, buf[0], buf[1], raw, local_rule, L.task_cap);
-        HS_LAUNCHED();
+        if (nsmall > 0) {
+            const uint32_t gs = (nsmall + 3) / 4 < (uint32_t)(d->ncu * 8) ? (nsmall + 3) / 4 : (uint32_t)(d->ncu * 8);
+            k_small<F, LC::LEAF><<<gs, 256, 0, stream>>>(ctl, tasks, buf[0], buf[1], raw, L.task_cap);
+            HS_LAUNCHED();
+        }
+        if (ntask > 0) {
+            const uint32_t gmax = (uint32_t)(d->ncu * LC::WPC);
+            const int g = (int)(ntask < gmax ? ntask : gmax);
+            k_local<F, LC::NT, LC::T, LC::LEAF, LC::WPC>
+                <<<g, LC::NT, 0, stream>>>(ctl, tasks, buf[0], buf[1], raw, local_rule, L.task_cap);
+            HS_LAUNCHED();
+        }
         if (st) HS_HIP(hipEventRecord(lev[1], stream));
     }
     if (shared_ws) HS_HIP(hipEventRecord(d->last, stream));
@@ -298,7 +313,7 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
         std::memset(st, 0, sizeof *st);
         st->passes = h->levels;
         st->keys_partitioned = (int64_t)h->part_keys;
-        st->tasks = ntask;
+        st->tasks = ntask + nsmall;
         st->max_depth = h->levels;
         st->bytes_alg = (int64_t)(2 * sizeof(K)) * ((int64_t)h->part_keys + (int64_t)h->local_keys) +
                         (int64_t)sizeof(K) * (int64_t)h->fill_keys;
@@ -308,7 +323,7 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
             HS_HIP(hipEventElapsedTime(&ms, d->ev[2 * l], d->ev[2 * l + 1]));
             st->partition_ms += ms;
         }
-        if (ntask > 0) {
+        if (ntask + nsmall > 0) {
             float ms = 0.f;
             HS_HIP(hipEventElapsedTime(&ms, lev[0], lev[1]));
             st->local_ms = ms;
@@ -439,8 +454,8 @@ int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_l
     HS_HIP(hipMemcpyAsync(copy, keys, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
     HS_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
     const uint32_t upiv = (uint32_t)pivot ^ 0x80000000u;
-    k_init_single<FMT_I32><<<1, 64, 0, s>>>(ctl, segs, tasks, Raw{copy, nullptr}, (uint32_t)n, 0, PIVOT_MEDIAN3, 1,
-                                            upiv);
+    k_init_single<FMT_I32><<<1, 64, 0, s>>>(ctl, segs, tasks, Raw{copy, nullptr}, (uint32_t)n, 0, 0, L.task_cap,
+                                            PIVOT_MEDIAN3, 1, upiv);
     HS_LAUNCHED();
     k_plan<uint32_t><<<1, 1024, 0, s>>>(ctl, segs, cur, L.cand_cap);
     HS_LAUNCHED();
