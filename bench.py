@@ -163,6 +163,26 @@ def run_gpu(name, steps, warmup):
     )
 
 
+def measured_traffic(name):
+    """HBM traffic per launch of the partition kernel from the committed
+    rocprofv3 --pmc summary for this workload, or None when there is none or
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"k_partition_{name}.md")
+    src = os.path.join(ROOT, "paper_1704_08579_amd", "csrc", "hs_kernels.hpp")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    sha = re.search(r"^source_sha256: ([0-9a-f]+)", txt, re.M)
+    val = re.search(r"^traffic_bytes_per_launch: ([0-9]+)", txt, re.M)
+    if not sha or not val:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != sha.group(1):
+        return None
+    return int(val.group(1))
+
+
 def cpu_baseline(name):
     """The oracle (single thread, as written) on a bounded sample of the
     workload: the first 2^26 keys of the first array of the step."""
@@ -250,7 +270,7 @@ def main():
                    "partition_launches_per_step": p["launches_per_step"]},
         "roofline": {"bound": "hbm", "kernel": "k_partition (global partition pass)",
                      "achieved": round(p["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.config),
                      "bytes_per_launch": round(p["bytes_per_launch"]),
                      "avg_launch_ms": round(p["avg_launch_ms"], 4)},
         "cpu_baseline": cpu,
