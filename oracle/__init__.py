@@ -17,7 +17,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "hsort_oracle.c")
+_SRCS = [os.path.join(_HERE, "hsort_oracle.c"), os.path.join(_HERE, "learned_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _I64 = ctypes.c_int64
@@ -26,10 +26,10 @@ _P = ctypes.c_void_p
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C11, -O2, no intrinsics)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(map(os.path.getmtime, _SRCS)):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC",
-                               "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC",
+                               "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -40,7 +40,7 @@ _lib = None
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(map(os.path.getmtime, _SRCS)):
             build(force=True)
         L = ctypes.CDLL(_LIB)
         for name, args, res in [
@@ -56,6 +56,20 @@ def lib() -> ctypes.CDLL:
             ("oracle_bitonic_merger_failures", [ctypes.c_int], _I64),
             ("oracle_key_f64", [ctypes.c_uint64], ctypes.c_uint64),
             ("oracle_unkey_f64", [ctypes.c_uint64], ctypes.c_uint64),
+            ("oracle_splitmix64_at", [ctypes.c_uint64, ctypes.c_uint64], ctypes.c_uint64),
+            ("oracle_sample_indices", [ctypes.c_uint64, _I64, _I64, _P], None),
+            ("oracle_mlp_nparam", [], _I64),
+            ("oracle_mlp_init", [ctypes.c_uint64, _P], None),
+            ("oracle_mlp_forward", [_P, _P, _I64, _P], None),
+            ("oracle_mlp_loss_grad", [_P, _P, _P, _I64, _P], ctypes.c_double),
+            ("oracle_adam_step", [_P, _P, _P, _P, _I64, ctypes.c_double], None),
+            ("oracle_feature_stats", [_P, _I64, _P, _P], None),
+            ("oracle_mlp_train", [ctypes.c_uint64, _P, _P, _I64, _I64, ctypes.c_double, _P, _P], None),
+            ("oracle_invert_f64", [_P, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                   ctypes.c_int, _P], None),
+            ("oracle_dedupe", [_P, _I64, _P], _I64),
+            ("oracle_bucket_hist", [_P, _I64, _P, _I64, _P], None),
+            ("oracle_keys_f64", [_P, _I64, _P], None),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -152,3 +166,96 @@ def key_f64(bits: int) -> int:
 
 def unkey_f64(key: int) -> int:
     return int(lib().oracle_unkey_f64(key))
+
+
+# ---------------------------------------------------------------- learned splitters
+
+NPARAM = 1153
+
+
+def splitmix64_at(seed: int, k: int) -> int:
+    return int(lib().oracle_splitmix64_at(seed & (2 ** 64 - 1), k))
+
+
+def sample_indices(seed: int, n: int, m: int) -> np.ndarray:
+    idx = np.empty(m, dtype=np.int64)
+    lib().oracle_sample_indices(seed & (2 ** 64 - 1), n, m, _ptr(idx))
+    return idx
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    p = np.empty(NPARAM, dtype=np.float64)
+    lib().oracle_mlp_init(seed & (2 ** 64 - 1), _ptr(p))
+    return p
+
+
+def mlp_forward(p, z) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.empty(z.size, dtype=np.float64)
+    lib().oracle_mlp_forward(_ptr(p), _ptr(z), z.size, _ptr(out))
+    return out
+
+
+def mlp_loss_grad(p, z, y):
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = np.empty(NPARAM, dtype=np.float64)
+    loss = lib().oracle_mlp_loss_grad(_ptr(p), _ptr(z), _ptr(y), z.size, _ptr(g))
+    return float(loss), g
+
+
+def adam_step(p, mom, vel, grad, t: int, lr: float):
+    """In-place Adam update of float64 arrays p, mom, vel."""
+    for a in (p, mom, vel):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    lib().oracle_adam_step(_ptr(p), _ptr(mom), _ptr(vel), _ptr(g), int(t), float(lr))
+
+
+def feature_stats(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    mu = ctypes.c_double()
+    sd = ctypes.c_double()
+    lib().oracle_feature_stats(_ptr(x), x.size, ctypes.addressof(mu), ctypes.addressof(sd))
+    return mu.value, sd.value
+
+
+def mlp_train(seed: int, z, y, steps: int, lr: float):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    p = np.empty(NPARAM, dtype=np.float64)
+    losses = np.empty(steps, dtype=np.float64)
+    lib().oracle_mlp_train(seed & (2 ** 64 - 1), _ptr(z), _ptr(y), z.size, steps, lr, _ptr(p), _ptr(losses))
+    return p, losses
+
+
+def invert_f64(p, mu: float, sd: float, kmin: int, kmax: int, nb: int = 256) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.empty(nb - 1, dtype=np.uint64)
+    lib().oracle_invert_f64(_ptr(p), mu, sd, kmin, kmax, nb, _ptr(out))
+    return out
+
+
+def dedupe(s) -> np.ndarray:
+    s = np.ascontiguousarray(s, dtype=np.uint64)
+    d = np.empty(max(1, s.size), dtype=np.uint64)
+    k = lib().oracle_dedupe(_ptr(s), s.size, _ptr(d))
+    return d[:k].copy()
+
+
+def bucket_hist(keys, d) -> np.ndarray:
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    d = np.ascontiguousarray(d, dtype=np.uint64)
+    counts = np.empty(2 * d.size + 1, dtype=np.int64)
+    lib().oracle_bucket_hist(_ptr(keys), keys.size, _ptr(d) if d.size else None, d.size, _ptr(counts))
+    return counts
+
+
+def f64_order_keys(x) -> np.ndarray:
+    """Order words (IEEE totalOrder keys) of float64 values."""
+    bits = np.ascontiguousarray(x, dtype=np.float64).view(np.uint64)
+    out = np.empty(bits.size, dtype=np.uint64)
+    lib().oracle_keys_f64(_ptr(bits), bits.size, _ptr(out))
+    return out
