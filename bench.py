@@ -40,7 +40,18 @@ CONFIGS = {
               "sort_segmented_i32, 200,000 int32 arrays, sizes log-uniform in [16, 2^13]"),
     "seg_B": ("seg", 2840, (16, 1 << 20), 5,
               "sort_segmented_i32, 2,840 int32 arrays, sizes log-uniform in [16, 2^20]"),
+    "learned_2e28": ("f64", 1 << 28, ["lognormal", "zipf", "mixture"], 6,
+                     "sort_f64 with learned splitters (training included), 2^28 float64 keys x 3 distributions "
+                     "(lognormal(0,2), Zipf s=1.1 over 2^24, 8-Gaussian mixture)"),
+    "sampled_2e28_learned_inputs": ("f64", 1 << 28, ["lognormal", "zipf", "mixture"], 6,
+                                    "sort_f64 with the multiway pass driven by the sample's order statistics "
+                                    "(no training) on the inputs of learned_2e28"),
+    "plain_2e28_learned_inputs": ("f64", 1 << 28, ["lognormal", "zipf", "mixture"], 6,
+                                  "sort_f64 (plain method) on the inputs of learned_2e28"),
 }
+
+# configurations sorted with the learned-splitter method: name -> learn_flags
+LEARNED = {"learned_2e28": 0, "sampled_2e28_learned_inputs": 2}
 
 
 def log(msg):
@@ -98,9 +109,9 @@ class Case:
         if self.kind == "kv":
             self.vwork.copy_(self.vsrc)
 
-    def sort(self, hs):
+    def sort(self, hs, opts=None):
         if self.kind in ("f64", "i32"):
-            return hs.sort_(self.work, stats=True)
+            return hs.sort_(self.work, opts=opts, stats=True)
         if self.kind == "kv":
             return hs.sort_kv_(self.work, self.vwork, stats=True)
         return hs.sort_segmented_(self.work, self.off, stats=True)
@@ -111,7 +122,12 @@ def run_gpu(name, steps, warmup):
 
     import paper_1704_08579_amd as hs
     hs.lib()
-    cases = [Case(k, d, torch) for k, d in make_inputs(name)]
+    inputs = make_inputs(name)
+    dists = CONFIGS[name][2] if CONFIGS[name][0] == "f64" else [None] * len(inputs)
+    cases = [Case(k, d, torch) for k, d in inputs]
+    del inputs
+    opts = hs.learned_opts(seed=100, flags=LEARNED[name]) if name in LEARNED else None
+    learn = {d: [] for d in dists} if name in LEARNED else None
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -123,13 +139,19 @@ def run_gpu(name, steps, warmup):
             torch.cuda.synchronize()
             t_wall = time.perf_counter()
         ms_step = 0.0
-        for c in cases:
+        for c, dist in zip(cases, dists):
             c.restore()
             ev0.record()
-            st = c.sort(hs)
+            st = c.sort(hs, opts)
             ev1.record()
             ev1.synchronize()
             ms_step += ev0.elapsed_time(ev1)
+            if timed and learn is not None:
+                learn[dist].append(dict(ms=ev0.elapsed_time(ev1), learn_ms=st["learn_ms"],
+                                        multiway_ms=st["multiway_ms"], fallback_used=st["fallback_used"],
+                                        splitters=st["splitters"], model_imbalance=st["model_imbalance"],
+                                        sample_imbalance=st["sample_imbalance"], final_loss=st["final_loss"],
+                                        bytes_per_key=st["bytes_alg"] / c.n))
             if timed:
                 acc["bytes_alg"] += st["bytes_alg"]
                 acc["keys_part"] += st["keys_partitioned"]
@@ -160,6 +182,8 @@ def run_gpu(name, steps, warmup):
                        avg_launch_ms=acc["part_ms"] / max(1, acc["part_launches"])),
         local=dict(gbs=local_gbs, ms_per_step=acc["local_ms"] / steps),
         elem_bytes=s,
+        learned=None if learn is None else {
+            d: {k: round(sum(r[k] for r in v) / len(v), 4) for k in v[0]} for d, v in learn.items()},
     )
 
 
@@ -232,7 +256,8 @@ def main():
     r = run_gpu(args.config, args.steps, args.warmup)
     extra = {}
     if args.extra:
-        for nm in ["i32_2e28", "kv_2e28", "seg_A", "seg_B", "i32_2e20"]:
+        for nm in ["i32_2e28", "kv_2e28", "seg_A", "seg_B", "i32_2e20", "learned_2e28",
+                   "sampled_2e28_learned_inputs", "plain_2e28_learned_inputs"]:
             if nm == args.config:
                 continue
             e = run_gpu(nm, max(3, args.steps // 2), 1)
@@ -241,6 +266,8 @@ def main():
                          "partition_gbs": round(e["partition"]["gbs"], 1),
                          "whole_sort_roofline_frac": round(e["whole_sort_roofline"], 4),
                          "workload": CONFIGS[nm][4]}
+            if e["learned"]:
+                extra[nm]["per_distribution"] = e["learned"]
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.config)
@@ -275,6 +302,8 @@ def main():
                      "avg_launch_ms": round(p["avg_launch_ms"], 4)},
         "cpu_baseline": cpu,
     }
+    if r["learned"]:
+        out["config"]["learned_per_distribution"] = r["learned"]
     if extra:
         out["extra"] = extra
     print(json.dumps(out), flush=True)

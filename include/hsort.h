@@ -66,6 +66,14 @@ enum { HS_PIVOT_AUTO = 0,     /* the tuned default */
        HS_PIVOT_NINTHER = 2,  /* median of three medians of three */
        HS_PIVOT_SAMPLE = 3 }; /* median of a 31-element strided sample */
 
+/* Sort methods (hs_opts.method). */
+enum { HS_METHOD_PLAIN = 0,     /* the paper's method: one pivot per partition */
+       HS_METHOD_LEARNED = 1 }; /* a 256-way split by learned splitters first (see below) */
+
+/* Flags of the learned method (hs_opts.learn_flags). */
+enum { HS_LEARN_FORCE_MODEL = 1,    /* use the model's splitters whatever the judge says */
+       HS_LEARN_FORCE_SAMPLE = 2 }; /* use the sample's order statistics (skip the model) */
+
 /* Optional per-call statistics (host memory).  Filling it costs one extra
  * stream synchronisation. */
 typedef struct hs_stats {
@@ -74,14 +82,20 @@ typedef struct hs_stats {
     int64_t keys_partitioned; /* sum over levels of the keys in partitioned segments */
     int64_t tasks;         /* on-chip (local sort / fill) tasks */
     int64_t max_depth;     /* deepest global level that partitioned */
-    int32_t fallback_used; /* reserved: 1 if a fallback driver ran */
-    int32_t reserved;
-    double bucket_imbalance; /* reserved for the multiway forms */
+    int32_t fallback_used; /* learned method: 1 if the judge chose the sample's order statistics */
+    int32_t splitters;     /* learned method: distinct splitters used */
+    double bucket_imbalance; /* learned method: imbalance of the splitters used (held-out sample) */
     /* Kernel times measured with HIP events on `stream` around each launch
      * (filled only when stats are requested). */
     double partition_ms;   /* sum over the partition-pass launches */
-    double local_ms;       /* the on-chip sort launch */
+    double local_ms;       /* the on-chip sort launches */
     int64_t partition_launches;
+    /* learned method only */
+    double model_imbalance;  /* largest non-equality bucket / (n/256), model splitters, held-out sample */
+    double sample_imbalance; /* the same for the sample's order statistics */
+    double learn_ms;         /* sampling, sample sort, training, inversion and judge */
+    double multiway_ms;      /* the multiway partition pass */
+    double final_loss;       /* training loss after the last step */
 } hs_stats;
 
 /* Optional tuning knobs.  A NULL hs_opts*, or 0 in a field, selects the
@@ -89,9 +103,13 @@ typedef struct hs_stats {
 typedef struct hs_opts {
     int32_t pivot_rule;   /* HS_PIVOT_* */
     int32_t local_T;      /* on-chip segment limit; a power of two <= the type's maximum */
-    int32_t reserved0;
-    int32_t reserved1;
-    uint64_t seed;        /* reserved */
+    int32_t method;       /* HS_METHOD_* */
+    int32_t learn_flags;  /* HS_LEARN_* */
+    int32_t train_steps;  /* learned method: Adam steps (default 300) */
+    int32_t sample_log2;  /* learned method: log2 of the training sample (default 16, range 10..20) */
+    float learning_rate;  /* learned method: Adam learning rate (default 1e-2) */
+    int32_t reserved;
+    uint64_t seed;        /* learned method: seed of the sample draws and the initial weights */
     void *workspace;      /* caller-owned device scratch, or NULL */
     size_t workspace_bytes;
 } hs_opts;
@@ -123,6 +141,53 @@ HS_API int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_
  * read-back is needed). */
 HS_API int hs_sort_segmented_i32(int32_t *keys, int64_t n_total, const int64_t *d_offsets,
                           int64_t nseg, const hs_opts *opts, hs_stats *stats, void *stream);
+
+/* ---- The learned-splitter method (HS_METHOD_LEARNED) -------------------
+ *
+ * Not in the paper, which partitions around one pivot at a time (Sec. III-B,
+ * Algorithm 3).  A sample of 2^sample_log2 keys (drawn with splitmix64) is
+ * sorted; an fp32 MLP 1-32-32-1 (tanh, tanh, sigmoid) is trained on the GPU
+ * by these kernels to the sample's empirical CDF (input (asinh(x) - mu)/sd,
+ * target (rank + 0.5)/m, mean squared error, full-batch Adam); 255 splitters
+ * are read off the model by search, and a judge compares the model's bucket
+ * imbalance on a held-out sample with that of the sample's order statistics
+ * (the sampled-pivot fallback), keeping the model unless it is more than
+ * 1.25 times worse.  One multiway pass then splits the keys into 2k+1
+ * buckets (k distinct splitters; keys equal to a splitter form a final
+ * bucket) by exact comparisons, and every bucket continues through the
+ * plain method.  The output is the same as the plain method's.
+ * sort_i32, sort_f64 and sort_kv_i32 accept it; the segmented sort does not.
+ *
+ * The model parameters are 1153 fp32 values laid out as
+ * [W1(32) b1(32) W2(32x32, row = output unit) b2(32) w3(32) b3(1)];
+ * F(z) = sigmoid(w3 . tanh(W2 tanh(W1 z + b1) + b2) + b3).  The calls below
+ * expose the model's kernels and the multiway pass on their own (device
+ * pointers; asynchronous on `stream`). */
+
+/* out[i] = F(z[i]) for i < m. */
+HS_API int hs_mlp_forward_f32(const float *d_params, const float *d_z, int64_t m, float *d_out, void *stream);
+
+/* Gradient of the mean squared error (1/m) sum_i (F(z_i) - y_i)^2 with
+ * respect to the 1153 parameters, summed over samples in a fixed order (so
+ * repeated calls give identical bits); m <= 2^20. */
+HS_API int hs_mlp_grad_f32(const float *d_params, const float *d_z, const float *d_y, int64_t m, float *d_grad,
+                           void *stream);
+
+/* Xavier-uniform initialisation from `seed` (splitmix64 draws) followed by
+ * `steps` full-batch Adam steps at learning rate `lr`; the trained
+ * parameters go to d_params (1153 floats); d_loss (optional, `steps` floats)
+ * receives the loss before each step.  m <= 2^20. */
+HS_API int hs_mlp_train_f32(const float *d_z, const float *d_y, int64_t m, int32_t steps, float lr, uint64_t seed,
+                            float *d_params, float *d_loss, void *stream);
+
+/* Split n float64 keys (IEEE totalOrder) in place into the 2k+1 buckets of
+ * k distinct, increasing splitters given as totalOrder keys (the unsigned
+ * word bits ^ (sign ? ~0 : 1 << 63)) in device memory (k <= 255): bucket 2r
+ * holds the keys strictly between splitters r-1 and r, bucket 2r+1 the keys
+ * equal to splitter r.  d_start (2k+2 uint32) receives the bucket starts
+ * (d_start[2k+1] = n).  The order inside a bucket is unspecified. */
+HS_API int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_splitters, int32_t k,
+                                     uint32_t *d_start, void *stream);
 
 /* Bytes of workspace that operation `op` needs for n keys (and nseg
  * segments) with the given options. */

@@ -37,21 +37,30 @@ class HSortError(RuntimeError):
         self.code = code
 
 
+METHOD_PLAIN, METHOD_LEARNED = 0, 1
+LEARN_FORCE_MODEL, LEARN_FORCE_SAMPLE = 1, 2
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int64), ("bytes_alg", ctypes.c_int64),
                 ("keys_partitioned", ctypes.c_int64), ("tasks", ctypes.c_int64),
                 ("max_depth", ctypes.c_int64), ("fallback_used", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("bucket_imbalance", ctypes.c_double),
+                ("splitters", ctypes.c_int32), ("bucket_imbalance", ctypes.c_double),
                 ("partition_ms", ctypes.c_double), ("local_ms", ctypes.c_double),
-                ("partition_launches", ctypes.c_int64)]
+                ("partition_launches", ctypes.c_int64),
+                ("model_imbalance", ctypes.c_double), ("sample_imbalance", ctypes.c_double),
+                ("learn_ms", ctypes.c_double), ("multiway_ms", ctypes.c_double),
+                ("final_loss", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("pivot_rule", ctypes.c_int32), ("local_T", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("learn_flags", ctypes.c_int32),
+                ("train_steps", ctypes.c_int32), ("sample_log2", ctypes.c_int32),
+                ("learning_rate", ctypes.c_float), ("reserved", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
@@ -67,6 +76,11 @@ _SIGS = {
     "hs_partition_i32": ([_P, _I64, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
     "hs_sort_segmented_i32": ([_P, _I64, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_workspace_size": ([ctypes.c_int, _I64, _I64, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hs_mlp_forward_f32": ([_P, _P, _I64, _P, _P], ctypes.c_int),
+    "hs_mlp_grad_f32": ([_P, _P, _P, _I64, _P, _P], ctypes.c_int),
+    "hs_mlp_train_f32": ([_P, _P, _I64, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64, _P, _P, _P],
+                         ctypes.c_int),
+    "hs_multiway_partition_f64": ([_P, _I64, _P, ctypes.c_int32, _P, _P], ctypes.c_int),
     "hs_last_error": ([], ctypes.c_char_p),
     "hs_version": ([], ctypes.c_int),
 }
@@ -181,3 +195,72 @@ def workspace_size(op: int, n: int, nseg: int = 0, opts: Opts | None = None) -> 
     out = ctypes.c_size_t(0)
     _check(lib().hs_workspace_size(op, n, nseg, _opts_ptr(opts), ctypes.byref(out)))
     return int(out.value)
+
+
+# ---------------------------------------------------------------- learned splitters
+
+MLP_NPARAM = 1153
+
+
+def learned_opts(steps: int = 0, sample_log2: int = 0, lr: float = 0.0, seed: int = 0, flags: int = 0) -> Opts:
+    """Options selecting the learned-splitter method."""
+    o = Opts()
+    o.method = METHOD_LEARNED
+    o.train_steps = steps
+    o.sample_log2 = sample_log2
+    o.learning_rate = lr
+    o.seed = seed
+    o.learn_flags = flags
+    return o
+
+
+def mlp_forward(params, z):
+    """F(z) for a float32 CUDA tensor z with the 1153 float32 parameters."""
+    torch = _torch()
+    _require(params, (torch.float32,), "params")
+    _require(z, (torch.float32,), "z")
+    out = torch.empty_like(z)
+    with torch.cuda.device(z.device):
+        _check(lib().hs_mlp_forward_f32(params.data_ptr(), z.data_ptr(), z.numel(), out.data_ptr(),
+                                        _stream_handle(z)))
+    return out
+
+
+def mlp_grad(params, z, y):
+    """Gradient of the mean squared error over (z, y) (1153 float32 values)."""
+    torch = _torch()
+    for t, nm in ((params, "params"), (z, "z"), (y, "y")):
+        _require(t, (torch.float32,), nm)
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=z.device)
+    with torch.cuda.device(z.device):
+        _check(lib().hs_mlp_grad_f32(params.data_ptr(), z.data_ptr(), y.data_ptr(), z.numel(), g.data_ptr(),
+                                     _stream_handle(z)))
+    return g
+
+
+def mlp_train(z, y, steps: int, lr: float, seed: int):
+    """Train from the seeded initialisation; returns (params, per-step losses)."""
+    torch = _torch()
+    _require(z, (torch.float32,), "z")
+    _require(y, (torch.float32,), "y")
+    p = torch.empty(MLP_NPARAM, dtype=torch.float32, device=z.device)
+    loss = torch.empty(max(1, steps), dtype=torch.float32, device=z.device)
+    with torch.cuda.device(z.device):
+        _check(lib().hs_mlp_train_f32(z.data_ptr(), y.data_ptr(), z.numel(), steps, lr, seed, p.data_ptr(),
+                                      loss.data_ptr(), _stream_handle(z)))
+    return p, loss[:steps]
+
+
+def multiway_partition_(keys, splitters):
+    """Split a float64 tensor in place by distinct increasing splitters (a
+    uint64-valued int64 tensor of totalOrder keys); returns the bucket starts
+    (int32 tensor of 2k+2 entries, read as uint32)."""
+    torch = _torch()
+    _require(keys, (torch.float64,), "keys")
+    _require(splitters, (torch.int64,), "splitters")
+    k = splitters.numel()
+    starts = torch.empty(2 * k + 2, dtype=torch.int32, device=keys.device)
+    with torch.cuda.device(keys.device):
+        _check(lib().hs_multiway_partition_f64(keys.data_ptr(), keys.numel(), splitters.data_ptr(), k,
+                                               starts.data_ptr(), _stream_handle(keys)))
+    return starts

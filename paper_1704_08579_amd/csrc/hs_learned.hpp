@@ -1,0 +1,765 @@
+// hs_learned.hpp -- learned splitters and the multiway partition pass.
+//
+// The paper partitions around one pivot per pass (Sec. III-B, Alg. 3).  This
+// front end replaces sampled pivots by a learned model of the key
+// distribution that places 255 splitters at once, and partitions the keys
+// into the resulting buckets in one pass (histogram + scatter); each bucket
+// then continues through the paper's method (partition levels, on-chip sort,
+// bitonic network).  The steps:
+//
+//   sample      m keys drawn with splitmix64 (output k of splitmix64(seed),
+//               scaled to [0, n) by a 64x64 high multiply), sorted by the
+//               library's own sort;
+//   model       an fp32 MLP 1-32-32-1 (tanh, tanh, sigmoid) fitted to the
+//               sample's empirical CDF: input z = (asinh(x) - mu) / sd over the
+//               sample, target (rank + 0.5) / m, mean squared error, Adam;
+//               forward, backward and update are this file's kernels;
+//   splitters   for j = 1..255 the smallest key K with F(K) >= j/256, by a
+//               64-ary search over the key's order word (one wave per
+//               splitter), then running maximum and de-duplication;
+//   judge       the model's bucket imbalance (largest non-equality bucket over
+//               the ideal n/256) on a held-out sample is compared with that of
+//               the sample's order statistics (the sampled-pivot fallback);
+//               the model is used unless its imbalance exceeds 1.25 times the
+//               fallback's;
+//   multiway    distinct splitters d_0 < ... < d_{k-1} define 2k+1 buckets: key
+//               x with r = #{d_i < x} goes to bucket 2r+1 if d_r == x (an
+//               equality bucket, final) and to bucket 2r otherwise; every
+//               comparison is an exact comparison of order words, so the
+//               learned model never changes the integer arithmetic of the sort.
+#pragma once
+
+#include "hs_kernels.hpp"
+
+namespace hs {
+
+constexpr int MLP_H = 32;
+constexpr int MLP_NP = 1153;
+constexpr int MLP_PS = 1156;  // stride of the per-workgroup partial gradients (16-byte rows)
+constexpr int MLP_W1 = 0, MLP_B1 = 32, MLP_W2 = 64, MLP_B2 = 64 + 1024, MLP_W3 = 64 + 1024 + 32,
+              MLP_B3 = 64 + 1024 + 64;
+constexpr int NBUCKET = 256;           // buckets the splitters aim for
+constexpr int NSPLIT = NBUCKET - 1;    // splitters
+constexpr int NB_MAX = 2 * NSPLIT + 1; // buckets including the equality buckets
+constexpr int MW_NT = 256;             // threads of a multiway workgroup
+constexpr int MW_TILE = 2048;          // keys per multiway tile
+
+__device__ __host__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// The model's view of a key: the searched word S (the key's order word, or
+// its key half for key/value words) and the real value fed to the model.
+template <int F> struct LearnKey;
+template <> struct LearnKey<FMT_F64> {
+    using K = uint64_t;
+    using S = uint64_t;
+    static __device__ __forceinline__ S search(K k) { return k; }
+    static __device__ __forceinline__ K word(S s) { return s; }
+    // Non-finite values are fed to the model as the largest finite value of
+    // their sign, which keeps the feature finite and in totalOrder order.
+    static __device__ __forceinline__ double value(S s)
+    {
+        const double x = __longlong_as_double((long long)dec_f64(s));
+        if (__builtin_isfinite(x)) return x;
+        return (s >> 63) ? 1.7976931348623157e308 : -1.7976931348623157e308;
+    }
+};
+template <> struct LearnKey<FMT_I32> {
+    using K = uint32_t;
+    using S = uint32_t;
+    static __device__ __forceinline__ S search(K k) { return k; }
+    static __device__ __forceinline__ K word(S s) { return s; }
+    static __device__ __forceinline__ double value(S s) { return (double)(int32_t)dec_i32(s); }
+};
+template <> struct LearnKey<FMT_KV> {
+    using K = uint64_t;
+    using S = uint32_t;
+    static __device__ __forceinline__ S search(K k) { return (S)(k >> 32); }
+    static __device__ __forceinline__ K word(S s) { return (K)s << 32; }  // smallest word with that key
+    static __device__ __forceinline__ double value(S s) { return (double)(int32_t)dec_i32(s); }
+};
+
+// Scalars of the learned front end, in device memory.
+struct LearnCtl {
+    double mu, sd;                // feature normalisation
+    unsigned long long smin, smax;  // searched words of the sample's extremes
+    uint32_t k;                   // distinct splitters in use
+    uint32_t use_model;           // 1: the model's splitters, 0: the sample's order statistics
+    float model_imb, sample_imb;  // imbalance of both splitter sets on the held-out sample
+    uint32_t reserved[2];
+};
+
+// ---------------------------------------------------------------- sampling
+
+template <int F>
+__global__ void k_ls_sample(Raw raw, uint32_t n, uint64_t seed, uint32_t m, Raw out)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const uint32_t i = (uint32_t)__umul64hi(splitmix64_at(seed, k), (uint64_t)n);
+    if constexpr (F == FMT_F64) {
+        ((uint64_t *)out.keys)[k] = ((const uint64_t *)raw.keys)[i];
+    } else {
+        ((uint32_t *)out.keys)[k] = ((const uint32_t *)raw.keys)[i];
+        if constexpr (F == FMT_KV) out.vals[k] = raw.vals[i];
+    }
+}
+
+// Held-out sample as order words.
+template <int F>
+__global__ void k_ls_holdout(Raw raw, uint32_t n, uint64_t seed, uint32_t h, typename KeyOf<F>::type *out)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= h) return;
+    const uint32_t i = (uint32_t)__umul64hi(splitmix64_at(seed, k), (uint64_t)n);
+    out[k] = raw_load<F>(raw, i);
+}
+
+// ---------------------------------------------------------------- features
+
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE, nw = blockDim.x / WAVE;
+    for (int d = 1; d < WAVE; d <<= 1) v += __shfl_xor(v, d);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w];  // fixed order: deterministic
+    return s;
+}
+
+// One workgroup over the sorted sample: feature statistics, inputs z and
+// targets y, the order-statistic splitters (the fallback) and the extremes.
+template <int F>
+__global__ __launch_bounds__(1024) void k_ls_prep(Raw sorted, uint32_t m, float *z, float *y,
+                                                   typename KeyOf<F>::type *fallback, LearnCtl *lc)
+{
+    using LK = LearnKey<F>;
+    __shared__ double red[16];
+    const uint32_t tid = threadIdx.x;
+    double s = 0.0;
+    for (uint32_t k = tid; k < m; k += blockDim.x) s += asinh(LK::value(LK::search(raw_load<F>(sorted, k))));
+    const double mu = block_sum(s, red) / (double)m;
+    double v = 0.0;
+    for (uint32_t k = tid; k < m; k += blockDim.x) {
+        const double d = asinh(LK::value(LK::search(raw_load<F>(sorted, k)))) - mu;
+        v += d * d;
+    }
+    double sd = sqrt(block_sum(v, red) / (double)m);
+    if (!(sd > 0.0)) sd = 1.0;
+    for (uint32_t k = tid; k < m; k += blockDim.x) {
+        const double x = LK::value(LK::search(raw_load<F>(sorted, k)));
+        z[k] = (float)((asinh(x) - mu) / sd);
+        y[k] = (float)(((double)k + 0.5) / (double)m);
+    }
+    for (uint32_t j = tid; j < (uint32_t)NSPLIT; j += blockDim.x)
+        fallback[j] = raw_load<F>(sorted, (uint32_t)(((uint64_t)(j + 1) * m) / NBUCKET));
+    if (tid == 0) {
+        lc->mu = mu;
+        lc->sd = sd;
+        lc->smin = LK::search(raw_load<F>(sorted, 0));
+        lc->smax = LK::search(raw_load<F>(sorted, m - 1));
+    }
+}
+
+// ---------------------------------------------------------------- the model
+
+// Xavier-uniform initialisation from splitmix64 (53-bit uniforms): W1 takes
+// draws 0..31, W2 draws 32..1055, w3 draws 1056..1087; biases are zero.
+__global__ void k_mlp_init(float *p, float *mom, float *vel, uint64_t seed)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= MLP_NP) return;
+    mom[i] = 0.f;
+    vel[i] = 0.f;
+    double a = 0.0;
+    int64_t draw = -1;
+    if (i < MLP_B1) {
+        a = sqrt(6.0 / (1 + MLP_H));
+        draw = i;
+    } else if (i >= MLP_W2 && i < MLP_B2) {
+        a = sqrt(6.0 / (MLP_H + MLP_H));
+        draw = MLP_H + (i - MLP_W2);
+    } else if (i >= MLP_W3 && i < MLP_B3) {
+        a = sqrt(6.0 / (MLP_H + 1));
+        draw = MLP_H + MLP_H * MLP_H + (i - MLP_W3);
+    }
+    if (draw < 0) {
+        p[i] = 0.f;
+        return;
+    }
+    const double u = (double)(splitmix64_at(seed, (uint64_t)draw) >> 11) * (1.0 / 9007199254740992.0);
+    p[i] = (float)((2.0 * u - 1.0) * a);
+}
+
+// tanh(v) = 1 - 2 / (1 + e^(2v)) with the hardware exponential and
+// reciprocal: exact limits of +-1 for large |v|, absolute error a few fp32
+// ulps.
+__device__ __forceinline__ float tanh_fast(float v)
+{
+    return fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + __expf(2.f * v)), 1.f);
+}
+
+// Forward pass of one input with the parameters in LDS.
+__device__ __forceinline__ float mlp_forward1(const float *sp, float zf, float *h1, float *h2)
+{
+#pragma unroll
+    for (int i = 0; i < MLP_H; ++i) h1[i] = tanh_fast(fmaf(sp[MLP_W1 + i], zf, sp[MLP_B1 + i]));
+#pragma unroll
+    for (int o = 0; o < MLP_H; ++o) {
+        float s = sp[MLP_B2 + o];
+#pragma unroll
+        for (int i = 0; i < MLP_H; ++i) s = fmaf(sp[MLP_W2 + o * MLP_H + i], h1[i], s);
+        h2[o] = tanh_fast(s);
+    }
+    float s = sp[MLP_B3];
+#pragma unroll
+    for (int i = 0; i < MLP_H; ++i) s = fmaf(sp[MLP_W3 + i], h2[i], s);
+    return 1.f / (1.f + __expf(-s));
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *p, const float *z, uint32_t m, float *out)
+{
+    __shared__ float sp[MLP_NP];
+    for (int i = threadIdx.x; i < MLP_NP; i += blockDim.x) sp[i] = p[i];
+    __syncthreads();
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    float h1[MLP_H], h2[MLP_H];
+    out[k] = mlp_forward1(sp, z[k], h1, h2);
+}
+
+// Gradient of the mean squared error over samples [0, m) of (z, y), first
+// half: workgroup g writes the gradient sum of its 256 samples to
+// part[g * MLP_PS ...] and their squared error to loss_blk[g].  Every sum
+// over samples runs in a fixed order, so the result is deterministic.
+//   forward      each thread runs its sample through the net (weights in LDS);
+//   W2, b2       dW2 = D2^T H1 over the 256 samples: the rows of H1 and D2
+//                go through LDS; thread t owns row t/8, columns 4(t%8)..+3;
+//   W1, b1, w3, b3 and the loss: 98 sums, each split over two threads
+//                (samples 0..127 and 128..255) and combined in LDS.
+__global__ __launch_bounds__(256) void k_mlp_grad(const float *p, const float *z, const float *y, uint32_t m,
+                                                  float *part, float *loss_blk)
+{
+    constexpr int NT = 256, HS = 36;  // row stride of the per-sample rows: 16-byte aligned
+    __shared__ float sp[MLP_NP];
+    __shared__ __align__(16) float sa[NT * HS];
+    __shared__ __align__(16) float sb[NT * HS];
+    __shared__ float sz[NT], s3[NT], sl[NT];
+    __shared__ float red[2][128];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < MLP_NP; i += NT) sp[i] = p[i];
+    __syncthreads();
+    const uint32_t k = blockIdx.x * NT + tid;
+    const bool valid = k < m;
+    const float zf = valid ? z[k] : 0.f, yf = valid ? y[k] : 0.f;
+    float h1[MLP_H], h2[MLP_H], d2[MLP_H];
+    const float f = mlp_forward1(sp, zf, h1, h2);
+    const float e = valid ? f - yf : 0.f;
+    const float ds3 = 2.f * e / (float)m * f * (1.f - f);
+#pragma unroll
+    for (int o = 0; o < MLP_H; ++o) d2[o] = ds3 * sp[MLP_W3 + o] * (1.f - h2[o] * h2[o]);
+#pragma unroll
+    for (int i = 0; i < MLP_H; i += 4) {
+        *(float4 *)&sa[tid * HS + i] = make_float4(h1[i], h1[i + 1], h1[i + 2], h1[i + 3]);
+        *(float4 *)&sb[tid * HS + i] = make_float4(d2[i], d2[i + 1], d2[i + 2], d2[i + 3]);
+    }
+    sz[tid] = zf;
+    s3[tid] = ds3;
+    sl[tid] = e * e;
+    __syncthreads();
+    float *gout = part + (size_t)blockIdx.x * MLP_PS;
+    {
+        const int o = tid >> 3, i0 = (tid & 7) * 4;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, ab = 0.f;
+#pragma unroll 8
+        for (int s = 0; s < NT; ++s) {
+            const float dv = sb[s * HS + o];
+            const float4 hv = *(const float4 *)&sa[s * HS + i0];
+            a0 = fmaf(dv, hv.x, a0);
+            a1 = fmaf(dv, hv.y, a1);
+            a2 = fmaf(dv, hv.z, a2);
+            a3 = fmaf(dv, hv.w, a3);
+            ab += dv;
+        }
+        *(float4 *)&gout[MLP_W2 + o * MLP_H + i0] = make_float4(a0, a1, a2, a3);
+        if ((tid & 7) == 0) gout[MLP_B2 + o] = ab;
+    }
+    // back to layer 1: dh1 = W2^T d2, ds1 = dh1 (1 - h1^2)
+    float d1[MLP_H];
+#pragma unroll
+    for (int i = 0; i < MLP_H; ++i) d1[i] = 0.f;
+#pragma unroll
+    for (int o = 0; o < MLP_H; ++o) {
+#pragma unroll
+        for (int i = 0; i < MLP_H; ++i) d1[i] = fmaf(d2[o], sp[MLP_W2 + o * MLP_H + i], d1[i]);
+    }
+    __syncthreads();  // everyone is done reading sa/sb
+#pragma unroll
+    for (int i = 0; i < MLP_H; i += 4) {
+        *(float4 *)&sa[tid * HS + i] = make_float4(d1[i] * (1.f - h1[i] * h1[i]), d1[i + 1] * (1.f - h1[i + 1] * h1[i + 1]),
+                                                   d1[i + 2] * (1.f - h1[i + 2] * h1[i + 2]),
+                                                   d1[i + 3] * (1.f - h1[i + 3] * h1[i + 3]));
+        *(float4 *)&sb[tid * HS + i] = make_float4(h2[i], h2[i + 1], h2[i + 2], h2[i + 3]);
+    }
+    __syncthreads();
+    {
+        const int r = tid & 127, half = tid >> 7, s0 = half * (NT / 2);
+        float v = 0.f;
+        if (r < MLP_H) {  // W1[r] = sum ds1[s][r] z[s]
+#pragma unroll 8
+            for (int s = s0; s < s0 + NT / 2; ++s) v = fmaf(sa[s * HS + r], sz[s], v);
+        } else if (r < 2 * MLP_H) {  // b1
+#pragma unroll 8
+            for (int s = s0; s < s0 + NT / 2; ++s) v += sa[s * HS + r - MLP_H];
+        } else if (r < 3 * MLP_H) {  // w3 = sum ds3[s] h2[s]
+#pragma unroll 8
+            for (int s = s0; s < s0 + NT / 2; ++s) v = fmaf(s3[s], sb[s * HS + r - 2 * MLP_H], v);
+        } else if (r == 3 * MLP_H) {  // b3
+#pragma unroll 8
+            for (int s = s0; s < s0 + NT / 2; ++s) v += s3[s];
+        } else if (r == 3 * MLP_H + 1) {  // squared error
+#pragma unroll 8
+            for (int s = s0; s < s0 + NT / 2; ++s) v += sl[s];
+        }
+        red[half][r] = v;
+    }
+    __syncthreads();
+    if (tid < 3 * MLP_H + 2) {
+        const float v = red[0][tid] + red[1][tid];
+        if (tid < MLP_H) gout[MLP_W1 + tid] = v;
+        else if (tid < 2 * MLP_H) gout[MLP_B1 + tid - MLP_H] = v;
+        else if (tid < 3 * MLP_H) gout[MLP_W3 + tid - 2 * MLP_H] = v;
+        else if (tid == 3 * MLP_H) gout[MLP_B3] = v;
+        else if (loss_blk) loss_blk[blockIdx.x] = v;
+    }
+}
+
+// Second half: sum the G partial gradients of every parameter in a fixed
+// order (so a step gives the same bits every time), then either apply one
+// Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias correction) to p, mom
+// and vel, or write the gradient to grad_out.  Workgroup w owns parameters
+// 64w .. 64w+63; its four waves sum a quarter of the partials each.  With
+// `loss` set, workgroup 0 also writes the mean squared error of the step
+// (the loss before the update).
+__global__ __launch_bounds__(256) void k_mlp_update(float *p, float *mom, float *vel, const float *part, uint32_t G,
+                                                    int t, float lr, float *grad_out, const float *loss_blk,
+                                                    float *loss, uint32_t m)
+{
+    __shared__ float acc[4][WAVE];
+    const int lane = lane_id(), q = threadIdx.x / WAVE;
+    const uint32_t i = blockIdx.x * WAVE + lane;
+    const uint32_t b0 = (uint32_t)(((uint64_t)G * q) / 4), b1 = (uint32_t)(((uint64_t)G * (q + 1)) / 4);
+    float g = 0.f;
+    if (i < (uint32_t)MLP_NP) {
+        uint32_t b = b0;
+        for (; b + 8 <= b1; b += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(b + u) * MLP_PS + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) g += v[u];
+        }
+        for (; b < b1; ++b) g += part[(size_t)b * MLP_PS + i];
+    }
+    acc[q][lane] = g;
+    if (blockIdx.x == 0 && q == 1 && loss && loss_blk) {  // the step's loss, one wave, fixed order
+        float l = 0.f;
+        for (uint32_t b = (uint32_t)lane; b < G; b += WAVE) l += loss_blk[b];
+        for (int d = 1; d < WAVE; d <<= 1) l += __shfl_xor(l, d);
+        if (lane == 0) *loss = l / (float)m;
+    }
+    __syncthreads();
+    if (q != 0 || i >= (uint32_t)MLP_NP) return;
+    g = ((acc[0][lane] + acc[1][lane]) + acc[2][lane]) + acc[3][lane];
+    if (grad_out) {
+        grad_out[i] = g;
+        return;
+    }
+    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1c, (float)t), c2 = 1.f - powf(b2c, (float)t);
+    const float mo = b1c * mom[i] + (1.f - b1c) * g;
+    const float ve = b2c * vel[i] + (1.f - b2c) * g * g;
+    mom[i] = mo;
+    vel[i] = ve;
+    p[i] -= lr * (mo / c1) / (sqrtf(ve / c2) + eps);
+}
+
+constexpr int MLP_UPDATE_GRID = (MLP_NP + WAVE - 1) / WAVE;
+
+// ---------------------------------------------------------------- splitters
+
+// One wave per splitter j: the smallest searched word s in [smin, smax] with
+// F(value(s)) >= (j+1)/256, by a 64-ary search.  Lane l probes
+// lo + floor(span * l / 63), so lane 0 probes lo and lane 63 probes hi; a
+// ballot finds the first probe at or above the target and the interval
+// shrinks to (previous probe, that probe].  About 11 rounds cover 64 bits.
+// (The model is not monotone in general; the search then returns one
+// crossing, and the running maximum of the judge restores the order.)
+template <int F>
+__global__ __launch_bounds__(256) void k_ls_invert(const float *p, const LearnCtl *lc,
+                                                   typename KeyOf<F>::type *split)
+{
+    using LK = LearnKey<F>;
+    using S = typename LK::S;
+    __shared__ float sp[MLP_NP];
+    for (int i = threadIdx.x; i < MLP_NP; i += blockDim.x) sp[i] = p[i];
+    __syncthreads();
+    const int lane = lane_id();
+    const uint32_t j = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (j >= (uint32_t)NSPLIT) return;
+    const float q = (float)(j + 1) / (float)NBUCKET;
+    const double mu = lc->mu, sd = lc->sd;
+    S lo = (S)lc->smin, hi = (S)lc->smax;
+    float h1[MLP_H], h2[MLP_H];
+    while (lo < hi) {
+        const S span = hi - lo;
+        const S a = span / 63, r = span % 63;  // floor(span*l/63) without overflow
+        const S probe = lo + a * (S)lane + (r * (S)lane) / 63;
+        const float zf = (float)((asinh(LK::value(probe)) - mu) / sd);
+        const bool ge = mlp_forward1(sp, zf, h1, h2) >= q;
+        const uint64_t bal = __ballot(ge);
+        if (bal == 0) {  // F < q up to hi, which is then smax: answer smax
+            lo = hi;
+            break;
+        }
+        const int first = __builtin_ctzll(bal);
+        const S at = lane_bcast(probe, first);
+        if (first == 0) {
+            hi = lo;
+            break;
+        }
+        lo = lane_bcast(probe, first - 1) + 1;
+        hi = at;
+    }
+    if (lane == 0) split[j] = LK::word(lo);
+}
+
+// One workgroup: running maximum and de-duplication of the model's
+// splitters, de-duplication of the order statistics, bucket imbalance of
+// both on the held-out sample, and the choice.  Writes the chosen distinct
+// splitters to `chosen` and their count to lc->k.  mode: JUDGE_AUTO, or
+// JUDGE_MODEL / JUDGE_SAMPLE to force one set (JUDGE_SAMPLE does not read
+// the model's splitters and reports a model imbalance of -1).
+constexpr int JUDGE_AUTO = 0, JUDGE_MODEL = 1, JUDGE_SAMPLE = 2;
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_ls_judge(const K *model_split, const K *sample_split, const K *holdout,
+                                                  uint32_t h, K *chosen, LearnCtl *lc, int mode)
+{
+    __shared__ K dm[NSPLIT], ds[NSPLIT];
+    __shared__ uint32_t cm[NB_MAX], cs[NB_MAX];
+    __shared__ uint32_t km_s, ks_s, um_s;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        uint32_t km = 0, ks = 0;
+        K run = 0;
+        for (int j = 0; j < NSPLIT; ++j) {
+            if (mode != JUDGE_SAMPLE) {
+                const K v = j == 0 ? model_split[0] : (model_split[j] > run ? model_split[j] : run);
+                run = v;
+                if (km == 0 || dm[km - 1] != v) dm[km++] = v;
+            }
+            const K w = sample_split[j];
+            if (ks == 0 || ds[ks - 1] != w) ds[ks++] = w;
+        }
+        km_s = km;
+        ks_s = ks;
+    }
+    for (int i = tid; i < NB_MAX; i += blockDim.x) cm[i] = cs[i] = 0;
+    __syncthreads();
+    const uint32_t km = km_s, ks = ks_s;
+    auto bucket = [](const K *d, uint32_t k, K x) {
+        uint32_t lo = 0, hi = k;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (d[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        return (lo < k && d[lo] == x) ? 2 * lo + 1 : 2 * lo;
+    };
+    for (uint32_t i = tid; i < h; i += blockDim.x) {
+        const K x = holdout[i];
+        atomicAdd(&cm[bucket(dm, km, x)], 1u);
+        atomicAdd(&cs[bucket(ds, ks, x)], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t mm = 0, ms = 0;
+        for (uint32_t b = 0; b <= 2 * km; b += 2) mm = max(mm, cm[b]);
+        for (uint32_t b = 0; b <= 2 * ks; b += 2) ms = max(ms, cs[b]);
+        const float ideal = (float)h / (float)NBUCKET;
+        const float im = mode == JUDGE_SAMPLE ? -1.f : (float)mm / ideal, is = (float)ms / ideal;
+        const bool use_model = mode == JUDGE_MODEL || (mode == JUDGE_AUTO && im <= 1.25f * is);
+        lc->model_imb = im;
+        lc->sample_imb = is;
+        lc->use_model = use_model ? 1u : 0u;
+        lc->k = use_model ? km : ks;
+        um_s = use_model ? 1u : 0u;
+    }
+    __syncthreads();
+    const bool um = um_s != 0;
+    const uint32_t k = um ? km : ks;
+    for (uint32_t i = tid; i < k; i += blockDim.x) chosen[i] = um ? dm[i] : ds[i];
+}
+
+// ---------------------------------------------------------------- multiway partition
+
+// Workgroup w owns keys [w*chunk, (w+1)*chunk).  The splitters sit in LDS
+// padded to 256 entries with the largest word, which is never below a key,
+// so r = #{splitters < x} takes eight fixed steps with no branches; every
+// thread keeps several keys in flight.
+template <typename K>
+__device__ __forceinline__ void mw_load_splitters(K *sd, const K *dsplit, uint32_t k)
+{
+    for (uint32_t i = threadIdx.x; i < (uint32_t)NBUCKET; i += blockDim.x) sd[i] = i < k ? dsplit[i] : key_max<K>();
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t mw_bucket(const K *sd, uint32_t k, K x)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t step = NBUCKET / 2; step; step >>= 1)
+        if (sd[r + step - 1] < x) r += step;
+    return (r < k && sd[r] == x) ? 2 * r + 1 : 2 * r;
+}
+
+constexpr int MW_ITEMS = 8;  // keys per thread per round of the histogram pass
+
+// Pass 1: bucket sizes of every workgroup's chunk, bucket-major:
+// hist[b * G + w].
+template <int F, bool SRC_IS_RAW>
+__global__ __launch_bounds__(MW_NT) void k_mw_hist(Raw raw, const typename KeyOf<F>::type *src, uint32_t n,
+                                                   uint32_t chunk, const typename KeyOf<F>::type *dsplit,
+                                                   const LearnCtl *lc, uint32_t *hist)
+{
+    using K = typename KeyOf<F>::type;
+    __shared__ K sd[NBUCKET];
+    __shared__ uint32_t cnt[NB_MAX];
+    const uint32_t k = lc->k, nb = 2 * k + 1;
+    mw_load_splitters(sd, dsplit, k);
+    for (uint32_t i = threadIdx.x; i < nb; i += MW_NT) cnt[i] = 0;
+    __syncthreads();
+    const uint32_t b0 = blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+    for (uint32_t base = b0; base < b1; base += MW_NT * MW_ITEMS) {
+        K x[MW_ITEMS];
+#pragma unroll
+        for (int j = 0; j < MW_ITEMS; ++j) {
+            const uint32_t i = base + j * MW_NT + threadIdx.x;
+            x[j] = i < b1 ? (SRC_IS_RAW ? raw_load<F>(raw, i) : src[i]) : K(0);
+        }
+#pragma unroll
+        for (int j = 0; j < MW_ITEMS; ++j) {
+            const uint32_t i = base + j * MW_NT + threadIdx.x;
+            const uint32_t bk = mw_bucket(sd, k, x[j]);
+            if (i < b1) atomicAdd(&cnt[bk], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += MW_NT) hist[(size_t)b * gridDim.x + blockIdx.x] = cnt[b];
+}
+
+// Pass 2a: one workgroup per bucket scans its G workgroup counts
+// (exclusive, in place) and writes the bucket's total.
+__global__ __launch_bounds__(1024) void k_mw_scan_cols(uint32_t *hist, uint32_t G, const LearnCtl *lc,
+                                                       uint32_t *total)
+{
+    __shared__ uint32_t wsum[16];
+    const uint32_t b = blockIdx.x;
+    if (b >= 2 * lc->k + 1) return;
+    uint32_t *col = hist + (size_t)b * G;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE, nw = blockDim.x / WAVE;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < G; base += blockDim.x) {
+        const uint32_t i = base + tid;
+        const uint32_t v = i < G ? col[i] : 0u;
+        const uint32_t incl = wave_incl_scan(v);
+        if (lane == WAVE - 1) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            if (w < wave) pre += wsum[w];
+            tot += wsum[w];
+        }
+        if (i < G) col[i] = carry + pre + incl - v;
+        carry += tot;
+        __syncthreads();
+    }
+    if (tid == 0) total[b] = carry;
+}
+
+// Pass 2b: bucket starts (exclusive scan of the totals, one workgroup).
+__global__ __launch_bounds__(1024) void k_mw_scan_starts(const uint32_t *total, const LearnCtl *lc,
+                                                         uint32_t *start)
+{
+    __shared__ uint32_t wsum[16];
+    const uint32_t nb = 2 * lc->k + 1;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE, nw = blockDim.x / WAVE;
+    const uint32_t v = (uint32_t)tid < nb ? total[tid] : 0u;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane == WAVE - 1) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < nw; ++w)
+        if (w < wave) pre += wsum[w];
+    if ((uint32_t)tid <= nb) start[tid] = pre + incl - v;  // start[nb] = n
+}
+
+// Pass 3: every workgroup re-reads its chunk tile by tile, groups each tile
+// by bucket in LDS (LDS atomics give each key its rank in its bucket) and
+// writes every bucket's run at the workgroup's running offset for that
+// bucket, consecutive lanes on consecutive addresses.  DST_IS_RAW writes
+// the caller's format to `out` instead of order words to `dst`.
+template <int F, bool SRC_IS_RAW, bool DST_IS_RAW>
+__global__ __launch_bounds__(MW_NT) void k_mw_scatter(Raw raw, const typename KeyOf<F>::type *src, uint32_t n,
+                                                      uint32_t chunk, const typename KeyOf<F>::type *dsplit,
+                                                      const LearnCtl *lc, const uint32_t *hist,
+                                                      const uint32_t *start, typename KeyOf<F>::type *dst, Raw out)
+{
+    using K = typename KeyOf<F>::type;
+    constexpr int ITEMS = MW_TILE / MW_NT;
+    __shared__ K sd[NBUCKET];
+    __shared__ uint32_t cnt[NB_MAX], tbase[NB_MAX], run[NB_MAX];
+    __shared__ K stage[MW_TILE];
+    __shared__ uint16_t sbk[MW_TILE];
+    __shared__ uint32_t wsum[MW_NT / WAVE];
+    const uint32_t k = lc->k, nb = 2 * k + 1;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    mw_load_splitters(sd, dsplit, k);
+    for (uint32_t b = tid; b < nb; b += MW_NT) run[b] = start[b] + hist[(size_t)b * gridDim.x + blockIdx.x];
+    const uint32_t c0 = blockIdx.x * chunk, c1 = min(n, c0 + chunk);
+    for (uint32_t t0 = c0; t0 < c1; t0 += MW_TILE) {
+        const uint32_t cnt_t = min((uint32_t)MW_TILE, c1 - t0);
+        for (uint32_t b = tid; b < nb; b += MW_NT) cnt[b] = 0;
+        __syncthreads();
+        K x[ITEMS];
+        uint32_t bk[ITEMS], rk[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t i = (uint32_t)(j * MW_NT + tid);
+            if (i < cnt_t) {
+                x[j] = SRC_IS_RAW ? raw_load<F>(raw, t0 + i) : src[t0 + i];
+                bk[j] = mw_bucket(sd, k, x[j]);
+                rk[j] = atomicAdd(&cnt[bk[j]], 1u);
+            }
+        }
+        __syncthreads();
+        {  // exclusive scan of the tile's bucket counts: thread t owns buckets 2t, 2t+1
+            const uint32_t c0v = (uint32_t)(2 * tid) < nb ? cnt[2 * tid] : 0u;
+            const uint32_t c1v = (uint32_t)(2 * tid + 1) < nb ? cnt[2 * tid + 1] : 0u;
+            const uint32_t v = c0v + c1v;
+            const uint32_t incl = wave_incl_scan(v);
+            if (lane == WAVE - 1) wsum[wave] = incl;
+            __syncthreads();
+            uint32_t pre = 0;
+#pragma unroll
+            for (int w = 0; w < MW_NT / WAVE; ++w)
+                if (w < wave) pre += wsum[w];
+            const uint32_t base = pre + incl - v;
+            if ((uint32_t)(2 * tid) < nb) tbase[2 * tid] = base;
+            if ((uint32_t)(2 * tid + 1) < nb) tbase[2 * tid + 1] = base + c0v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t i = (uint32_t)(j * MW_NT + tid);
+            if (i < cnt_t) {
+                const uint32_t pos = tbase[bk[j]] + rk[j];
+                stage[pos] = x[j];
+                sbk[pos] = (uint16_t)bk[j];
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < cnt_t; i += MW_NT) {
+            const uint32_t b = sbk[i];
+            if constexpr (DST_IS_RAW) raw_store<F>(out, run[b] + (i - tbase[b]), stage[i]);
+            else dst[run[b] + (i - tbase[b])] = stage[i];
+        }
+        __syncthreads();
+        for (uint32_t b = tid; b < nb; b += MW_NT) run[b] += cnt[b];
+        __syncthreads();
+    }
+}
+
+// Splitter count of a caller-supplied splitter set.
+__global__ void k_ls_set_k(LearnCtl *lc, uint32_t k)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) lc->k = k;
+}
+
+// Route every bucket: equality buckets become fill tasks (split into chunks
+// so that one wave never fills more than FILL_CHUNK keys), open buckets of at
+// most T keys become local tasks, larger ones the first partition level's
+// segments.  One lane per bucket, wave-batched emission.
+constexpr uint32_t FILL_CHUNK = 1u << 16;
+
+template <int F>
+__global__ __launch_bounds__(256) void k_mw_route(Ctl *ctl, const LearnCtl *lc, const uint32_t *start,
+                                                  const typename KeyOf<F>::type *dsplit,
+                                                  const typename KeyOf<F>::type *buf, uint32_t buf_id,
+                                                  Seg<typename KeyOf<F>::type> *cand, Task<typename KeyOf<F>::type> *tasks,
+                                                  uint32_t T, uint32_t leaf, int rule, uint32_t cand_cap,
+                                                  uint32_t task_cap)
+{
+    using K = typename KeyOf<F>::type;
+    const int lane = lane_id();
+    const uint32_t nb = 2 * lc->k + 1;
+    const uint32_t b = (blockIdx.x * blockDim.x + threadIdx.x);
+    const bool valid = b < nb;
+    const uint32_t s0 = valid ? start[b] : 0u, s1 = valid ? start[b + 1] : 0u, m = s1 - s0;
+    const bool eq = valid && (b & 1u) && m > 0;
+    const bool is_local = valid && !(b & 1u) && m >= 1 && m <= T;
+    const bool big = valid && !(b & 1u) && m > T;
+    // fills, chunked
+    const uint32_t nchunk = eq ? (m + FILL_CHUNK - 1) / FILL_CHUNK : 0u;
+    uint32_t maxc = nchunk;
+    for (int d = 1; d < WAVE; d <<= 1) maxc = max(maxc, (uint32_t)__shfl_xor((int)maxc, d));
+    for (uint32_t c = 0; c < maxc; ++c) {
+        Task<K> t;
+        t.b = s0 + c * FILL_CHUNK;
+        t.e = min(s1, t.b + FILL_CHUNK);
+        t.src = buf_id;
+        t.kind = TASK_FILL;
+        t.fill = eq ? dsplit[(b - 1) / 2] : K(0);
+        wave_flush_task(t, c < nchunk, true, tasks, task_cap, ctl);
+    }
+    {
+        Task<K> t;
+        t.b = s0;
+        t.e = s1;
+        t.src = buf_id;
+        t.kind = TASK_LOCAL;
+        t.fill = 0;
+        wave_flush_task(t, is_local, m <= leaf, tasks, task_cap, ctl);
+    }
+    const unsigned long long lk = wave_sum64(is_local ? (unsigned long long)m : 0ull);
+    const unsigned long long fk = wave_sum64(eq ? (unsigned long long)m : 0ull);
+    if (lane == 0) {
+        if (lk) atomicAdd(&ctl->local_keys, lk);
+        if (fk) atomicAdd(&ctl->fill_keys, fk);
+    }
+    Seg<K> sg;
+    sg.b = s0;
+    sg.e = s1;
+    sg.tile0 = 0;
+    sg.flags = 0;
+    sg.ub = 0;
+    sg.piv = 0;
+    SrcReader<F> rd{buf, Raw{nullptr, nullptr}, false};
+    for (uint64_t bb = __ballot(big); bb; bb &= bb - 1) {
+        const int src = __builtin_ctzll(bb);
+        const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)s0, src);
+        const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)s1, src);
+        const K pv = wave_pick_pivot<K>(rd, x0, x1, rule, lane);
+        if (lane == src) sg.piv = pv;
+    }
+    wave_flush(sg, big, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
+}
+
+}  // namespace hs

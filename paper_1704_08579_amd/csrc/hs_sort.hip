@@ -12,6 +12,7 @@
 #include <string>
 
 #include "hs_kernels.hpp"
+#include "hs_learned.hpp"
 #include "hsort.h"
 
 namespace {
@@ -55,7 +56,8 @@ struct DevState {
     size_t ws_bytes = 0;
     Ctl *h_ctl = nullptr;        // pinned host mirror of the control block
     hipEvent_t last = nullptr;   // end of the last call that used the cached workspace
-    hipEvent_t ev[2 * LMAX + 4] = {};  // timing events (stats only)
+    hipEvent_t ev[2 * LMAX + 8] = {};  // timing events (stats only)
+    LearnCtl *h_lctl = nullptr;  // pinned host mirror of the learned front end's scalars
     std::mutex mu;               // one call at a time per device
 };
 
@@ -77,6 +79,7 @@ int get_device(DevState **out)
         d.ncu = prop.multiProcessorCount;
         if (d.supported) {
             HS_HIP(hipHostMalloc((void **)&d.h_ctl, sizeof(Ctl), hipHostMallocDefault));
+            HS_HIP(hipHostMalloc((void **)&d.h_lctl, sizeof(LearnCtl), hipHostMallocDefault));
             HS_HIP(hipEventCreateWithFlags(&d.last, hipEventDisableTiming));
             for (auto &e : d.ev) HS_HIP(hipEventCreate(&e));
         }
@@ -93,13 +96,52 @@ int get_device(DevState **out)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Parameters of the learned front end of one call.
+struct LearnParams {
+    bool on = false;
+    int mode = JUDGE_AUTO;
+    uint32_t m = 0;        // training sample
+    uint32_t h = 0;        // held-out sample
+    int steps = 0;
+    float lr = 0.f;
+    uint64_t seed = 0;
+};
+
+constexpr int LEARN_STEPS = 300;
+constexpr int LEARN_LOG2M = 16;
+constexpr float LEARN_LR = 1e-2f;
+constexpr uint32_t LEARN_HOLDOUT = 1u << 14;
+constexpr uint32_t MW_GMAX = 2048;  // multiway workgroups at most
+
+LearnParams learn_params(const hs_opts *o, int64_t n, int op)
+{
+    LearnParams P;
+    if (!o || o->method != HS_METHOD_LEARNED || op == HS_OP_SORT_SEGMENTED_I32 || op == HS_OP_PARTITION_I32)
+        return P;
+    P.on = true;
+    P.mode = (o->learn_flags & HS_LEARN_FORCE_SAMPLE) ? JUDGE_SAMPLE
+             : (o->learn_flags & HS_LEARN_FORCE_MODEL) ? JUDGE_MODEL : JUDGE_AUTO;
+    const int lg = o->sample_log2 > 0 ? o->sample_log2 : LEARN_LOG2M;
+    P.m = 1u << lg;
+    P.h = LEARN_HOLDOUT;
+    P.steps = o->train_steps > 0 ? o->train_steps : LEARN_STEPS;
+    P.lr = o->learning_rate > 0.f ? o->learning_rate : LEARN_LR;
+    P.seed = o->seed;
+    (void)n;
+    return P;
+}
+
 struct Layout {
     size_t buf0 = 0, buf1 = 0, segA = 0, segB = 0, cur = 0, tasks = 0, ctl = 0, total = 0;
     uint32_t cand_cap = 0, task_cap = 0;
+    // learned front end (LearnParams::on)
+    size_t smp_k = 0, smp_v = 0, sub = 0, z = 0, y = 0, par = 0, mom = 0, vel = 0, part = 0, lossb = 0,
+           msplit = 0, ssplit = 0, chosen = 0, hold = 0, lctl = 0, hist = 0, btot = 0, bstart = 0;
+    size_t sub_bytes = 0;
 };
 
 template <typename K>
-Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T)
+Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParams &P = LearnParams())
 {
     Layout L;
     size_t off = 0;
@@ -116,6 +158,8 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T)
     } else {
         L.cand_cap = (uint32_t)(n / ((int64_t)T + 1) + 2);
         L.task_cap = (uint32_t)((op == HS_OP_SORT_SEGMENTED_I32 ? nseg : 1) + 2ll * LMAX * L.cand_cap + 4);
+        // the multiway pass routes up to NB_MAX buckets, fills in chunks
+        if (P.on) L.task_cap += (uint32_t)(NB_MAX + n / FILL_CHUNK + 2);
         L.buf1 = take((size_t)n * sk);
         if (op == HS_OP_SORT_KV_I32) L.buf0 = take((size_t)n * sk);
     }
@@ -124,6 +168,32 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T)
     L.cur = take((size_t)L.cand_cap * 8 * CUR_STRIDE);
     L.tasks = take((size_t)L.task_cap * sizeof(Task<K>));
     L.ctl = take(sizeof(Ctl));
+    if (P.on) {
+        // The training sample is sorted by a nested plain sort with its own
+        // sub-workspace.
+        const Layout S = make_layout<K>(op, P.m, 1, T);
+        const size_t rk = op == HS_OP_SORT_F64 ? 8 : 4;
+        L.smp_k = take((size_t)P.m * rk);
+        if (op == HS_OP_SORT_KV_I32) L.smp_v = take((size_t)P.m * 4);
+        L.sub = take(S.total);
+        L.sub_bytes = S.total;
+        L.z = take((size_t)P.m * 4);
+        L.y = take((size_t)P.m * 4);
+        L.par = take(MLP_NP * 4);
+        L.mom = take(MLP_NP * 4);
+        L.vel = take(MLP_NP * 4);
+        const size_t gblk = (P.m + 255) / 256;
+        L.part = take(gblk * MLP_PS * 4);
+        L.lossb = take((gblk + 1) * 4);  // per-workgroup losses, then the mean
+        L.msplit = take(NSPLIT * sizeof(K));
+        L.ssplit = take(NSPLIT * sizeof(K));
+        L.chosen = take(NSPLIT * sizeof(K));
+        L.hold = take((size_t)P.h * sizeof(K));
+        L.lctl = take(sizeof(LearnCtl));
+        L.hist = take((size_t)NB_MAX * MW_GMAX * 4);
+        L.btot = take(NB_MAX * 4);
+        L.bstart = take((NB_MAX + 1) * 4);
+    }
     L.total = off;
     return L;
 }
@@ -137,19 +207,40 @@ template <typename K> uint32_t local_limit(const hs_opts *o)
 
 int pivot_rule(const hs_opts *o) { return (o && o->pivot_rule > 0) ? o->pivot_rule : PIVOT_SAMPLE; }
 
+int check_learn(const hs_opts *o)
+{
+    if (!o) return HS_OK;
+    if (o->method != HS_METHOD_PLAIN && o->method != HS_METHOD_LEARNED)
+        return fail(HS_EINVAL, "unknown method %d", o->method);
+    if (o->method == HS_METHOD_LEARNED) {
+        if (o->sample_log2 != 0 && (o->sample_log2 < 10 || o->sample_log2 > 20))
+            return fail(HS_EINVAL, "sample_log2 = %d outside 10..20", o->sample_log2);
+        if (o->train_steps < 0 || o->train_steps > 100000)
+            return fail(HS_EINVAL, "train_steps = %d outside 0..100000", o->train_steps);
+        if (!(o->learning_rate >= 0.f) || o->learning_rate > 1.f)
+            return fail(HS_EINVAL, "learning_rate outside [0, 1]");
+        if ((o->learn_flags & ~(HS_LEARN_FORCE_MODEL | HS_LEARN_FORCE_SAMPLE)) ||
+            o->learn_flags == (HS_LEARN_FORCE_MODEL | HS_LEARN_FORCE_SAMPLE))
+            return fail(HS_EINVAL, "learn_flags = 0x%x is invalid", o->learn_flags);
+    }
+    return HS_OK;
+}
+
 int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
 {
+    int rc = check_learn(o);
+    if (rc) return rc;
     switch (op) {
     case HS_OP_SORT_I32:
     case HS_OP_SORT_SEGMENTED_I32:
-        *L = make_layout<uint32_t>(op, n, nseg, local_limit<uint32_t>(o));
+        *L = make_layout<uint32_t>(op, n, nseg, local_limit<uint32_t>(o), learn_params(o, n, op));
         return HS_OK;
     case HS_OP_PARTITION_I32:
         *L = make_layout<uint32_t>(op, n, nseg, 0);
         return HS_OK;
     case HS_OP_SORT_F64:
     case HS_OP_SORT_KV_I32:
-        *L = make_layout<uint64_t>(op, n, nseg, local_limit<uint64_t>(o));
+        *L = make_layout<uint64_t>(op, n, nseg, local_limit<uint64_t>(o), learn_params(o, n, op));
         return HS_OK;
     default:
         return fail(HS_EINVAL, "unknown op %d", op);
@@ -190,26 +281,19 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
 // ---------------------------------------------------------------- driver
 
+// Sort n keys whose workspace `ws` (laid out as L) is already bound.  Does
+// not lock the device state: the learned front end calls it again for its
+// training sample with a sub-workspace.
 template <int F>
-int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
-             hs_stats *st, hipStream_t stream)
+int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg,
+              const hs_opts *o, const LearnParams &P, hs_stats *st, hipStream_t stream)
 {
     using K = typename KeyOf<F>::type;
-    const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
-                         : (F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : HS_OP_SORT_KV_I32);
     const uint32_t T = local_limit<K>(o);
     const uint32_t LEAF = (uint32_t)LocalCfg<K>::LEAF;
     const int rule = pivot_rule(o);
     const int local_rule = (o && o->pivot_rule > 0) ? o->pivot_rule : PIVOT_NINTHER;
-    Layout L;
-    int rc = layout_for(op, n, nseg, o, &L);
-    if (rc) return rc;
-    std::lock_guard<std::mutex> lk(d->mu);
-    char *ws = nullptr;
-    rc = bind_workspace(d, o, L, &ws);
-    if (rc) return rc;
-    const bool shared_ws = !(o && o->workspace);
-    if (shared_ws) HS_HIP(hipStreamWaitEvent(stream, d->last, 0));
+    const bool learned = P.on && (uint64_t)n > T;
 
     K *buf[2];
     buf[0] = F == FMT_KV ? (K *)(ws + L.buf0) : (K *)raw.keys;
@@ -220,19 +304,92 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
     Ctl *ctl = (Ctl *)(ws + L.ctl);
     Ctl *h = d->h_ctl;
     const int aligned = aligned16(raw.keys) && (F != FMT_KV || aligned16(raw.vals)) ? 1 : 0;
+    hipEvent_t *lev = &d->ev[2 * LMAX];  // [0,1] on-chip sort, [2..4] learned front end
 
     HS_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), stream));
-    if (d_off) {
-        const uint32_t g = (uint32_t)((nseg + 255) / 256);  // one wave per 64 segments
-        k_init_segmented<F><<<g, 256, 0, stream>>>(ctl, segs[0], tasks, raw, d_off, (uint32_t)nseg, (uint32_t)n, T,
-                                                   LEAF, rule, L.cand_cap, L.task_cap);
+    int level = 0, cur_list = 0, batch = 0;
+    LearnCtl *lctl = nullptr;
+    if (learned) {
+        // ---- learned splitters and the multiway pass
+        lctl = (LearnCtl *)(ws + L.lctl);
+        Raw smp{ws + L.smp_k, F == FMT_KV ? (int32_t *)(ws + L.smp_v) : nullptr};
+        float *z = (float *)(ws + L.z), *y = (float *)(ws + L.y);
+        float *par = (float *)(ws + L.par), *mom = (float *)(ws + L.mom), *vel = (float *)(ws + L.vel);
+        float *part = (float *)(ws + L.part), *lossb = (float *)(ws + L.lossb);
+        K *msplit = (K *)(ws + L.msplit), *ssplit = (K *)(ws + L.ssplit), *chosen = (K *)(ws + L.chosen);
+        K *hold = (K *)(ws + L.hold);
+        uint32_t *hist = (uint32_t *)(ws + L.hist), *btot = (uint32_t *)(ws + L.btot);
+        uint32_t *bstart = (uint32_t *)(ws + L.bstart);
+        if (st) HS_HIP(hipEventRecord(lev[2], stream));
+        HS_HIP(hipMemsetAsync(lctl, 0, sizeof(LearnCtl), stream));
+        // sample draws: the training sample from splitmix64(seed), the
+        // held-out sample from splitmix64(seed + 1), the weights from
+        // splitmix64(seed + 2)
+        k_ls_sample<F><<<(P.m + 255) / 256, 256, 0, stream>>>(raw, (uint32_t)n, P.seed, P.m, smp);
+        HS_LAUNCHED();
+        k_ls_holdout<F><<<(P.h + 255) / 256, 256, 0, stream>>>(raw, (uint32_t)n, P.seed + 1, P.h, hold);
+        HS_LAUNCHED();
+        const Layout S = make_layout<K>(F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64
+                                                                                       : HS_OP_SORT_KV_I32,
+                                        P.m, 1, T);
+        int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
+        if (rc) return rc;
+        k_ls_prep<F><<<1, 1024, 0, stream>>>(smp, P.m, z, y, ssplit, lctl);
+        HS_LAUNCHED();
+        const uint32_t gblk = (P.m + 255) / 256;
+        if (P.mode != JUDGE_SAMPLE) {
+            k_mlp_init<<<(MLP_NP + 255) / 256, 256, 0, stream>>>(par, mom, vel, P.seed + 2);
+            HS_LAUNCHED();
+            for (int t = 1; t <= P.steps; ++t) {
+                const bool last = t == P.steps;
+                k_mlp_grad<<<gblk, 256, 0, stream>>>(par, z, y, P.m, part, lossb);
+                HS_LAUNCHED();
+                k_mlp_update<<<MLP_UPDATE_GRID, 256, 0, stream>>>(par, mom, vel, part, gblk, t, P.lr, nullptr,
+                                                                 lossb, last ? lossb + gblk : nullptr, P.m);
+                HS_LAUNCHED();
+            }
+            k_ls_invert<F><<<(NSPLIT * WAVE + 255) / 256, 256, 0, stream>>>(par, lctl, msplit);
+            HS_LAUNCHED();
+        }
+        k_ls_judge<K><<<1, 256, 0, stream>>>(msplit, ssplit, hold, P.h, chosen, lctl, P.mode);
+        HS_LAUNCHED();
+        if (st) HS_HIP(hipEventRecord(lev[3], stream));
+        uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
+        const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 4 - 1) / ((uint64_t)d->ncu * 4));
+        if (chunk < cmin) chunk = cmin;
+        chunk = (chunk + MW_TILE - 1) / MW_TILE * MW_TILE;
+        const uint32_t G = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
+        k_mw_hist<F, true><<<G, MW_NT, 0, stream>>>(raw, nullptr, (uint32_t)n, chunk, chosen, lctl, hist);
+        HS_LAUNCHED();
+        k_mw_scan_cols<<<NB_MAX, 1024, 0, stream>>>(hist, G, lctl, btot);
+        HS_LAUNCHED();
+        k_mw_scan_starts<<<1, 1024, 0, stream>>>(btot, lctl, bstart);
+        HS_LAUNCHED();
+        k_mw_scatter<F, true, false><<<G, MW_NT, 0, stream>>>(raw, nullptr, (uint32_t)n, chunk, chosen, lctl, hist,
+                                                               bstart, buf[1], Raw{});
+        HS_LAUNCHED();
+        k_mw_route<F><<<(NB_MAX + 255) / 256, 256, 0, stream>>>(ctl, lctl, bstart, chosen, buf[1], SRC_BUF1,
+                                                                segs[0], tasks, T, LEAF, rule, L.cand_cap,
+                                                                L.task_cap);
+        HS_LAUNCHED();
+        if (st) HS_HIP(hipEventRecord(lev[4], stream));
+        k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[0], cur, L.cand_cap);
+        HS_LAUNCHED();
+        level = 1;  // the buckets are in buf[1], where level 1 reads
+        batch = 0;  // read the control block back before the first level
     } else {
-        k_init_single<F><<<1, 64, 0, stream>>>(ctl, segs[0], tasks, raw, (uint32_t)n, T, LEAF, L.task_cap, rule, 0,
-                                               K(0));
+        if (d_off) {
+            const uint32_t g = (uint32_t)((nseg + 255) / 256);  // one wave per 64 segments
+            k_init_segmented<F><<<g, 256, 0, stream>>>(ctl, segs[0], tasks, raw, d_off, (uint32_t)nseg, (uint32_t)n,
+                                                       T, LEAF, rule, L.cand_cap, L.task_cap);
+        } else {
+            k_init_single<F><<<1, 64, 0, stream>>>(ctl, segs[0], tasks, raw, (uint32_t)n, T, LEAF, L.task_cap, rule,
+                                                   0, K(0));
+        }
+        HS_LAUNCHED();
+        k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[0], cur, L.cand_cap);
+        HS_LAUNCHED();
     }
-    HS_LAUNCHED();
-    k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[0], cur, L.cand_cap);
-    HS_LAUNCHED();
 
     // Levels are launched in batches with fixed grids (every kernel reads the
     // level's size from the control block), and the host reads the control
@@ -254,8 +411,8 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
     const int fin_grid = d->ncu * 4;
     int guard = 2;
     for (int64_t x = n; x > 1; x >>= 1) ++guard;  // 2 + log2(n): beyond it, sample-median pivots
-    int level = 0, cur_list = 0;
-    int batch = d_off ? 1 : ((uint64_t)n > T ? levels_for((uint64_t)n) : 0);
+    const int level0 = level;
+    if (!learned) batch = d_off ? 1 : ((uint64_t)n > T ? levels_for((uint64_t)n) : 0);
     for (;;) {
         for (int bi = 0; bi < batch && level < LMAX; ++bi, ++level) {
             const int lrule = level > guard ? PIVOT_SAMPLE : rule;
@@ -285,10 +442,9 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
         if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
         batch = levels_for(h->max_seg);
     }
-    const int64_t levels = level;
+    const int64_t launches = level - level0;
     const uint32_t ntask = h->ntask, nsmall = h->nsmall;
     if ((uint64_t)ntask + nsmall > L.task_cap) return fail(HS_EINTERNAL, "task list overflow");
-    hipEvent_t *lev = &d->ev[2 * LMAX];
     if (ntask + nsmall > 0) {
         using LC = LocalCfg<K>;
         if (st) HS_HIP(hipEventRecord(lev[0], stream));
@@ -306,9 +462,15 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
         }
         if (st) HS_HIP(hipEventRecord(lev[1], stream));
     }
-    if (shared_ws) HS_HIP(hipEventRecord(d->last, stream));
     if (st) {
         HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        if (learned) HS_HIP(hipMemcpyAsync(d->h_lctl, lctl, sizeof(LearnCtl), hipMemcpyDeviceToHost, stream));
+        float loss = 0.f;
+        if (learned && P.mode != JUDGE_SAMPLE) {
+            const uint32_t gblk = (P.m + 255) / 256;
+            HS_HIP(hipMemcpyAsync(&loss, (float *)(ws + L.lossb) + gblk, sizeof(float), hipMemcpyDeviceToHost,
+                                  stream));
+        }
         HS_HIP(hipStreamSynchronize(stream));
         std::memset(st, 0, sizeof *st);
         st->passes = h->levels;
@@ -317,8 +479,8 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
         st->max_depth = h->levels;
         st->bytes_alg = (int64_t)(2 * sizeof(K)) * ((int64_t)h->part_keys + (int64_t)h->local_keys) +
                         (int64_t)sizeof(K) * (int64_t)h->fill_keys;
-        st->partition_launches = levels;
-        for (int64_t l = 0; l < levels; ++l) {
+        st->partition_launches = launches;
+        for (int64_t l = level0; l < level; ++l) {
             float ms = 0.f;
             HS_HIP(hipEventElapsedTime(&ms, d->ev[2 * l], d->ev[2 * l + 1]));
             st->partition_ms += ms;
@@ -328,9 +490,46 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
             HS_HIP(hipEventElapsedTime(&ms, lev[0], lev[1]));
             st->local_ms = ms;
         }
+        if (learned) {
+            const LearnCtl &lc = *d->h_lctl;
+            // the multiway pass reads the keys twice and writes them once
+            st->bytes_alg += 3 * (int64_t)sizeof(K) * n;
+            st->fallback_used = lc.use_model ? 0 : 1;
+            st->splitters = (int32_t)lc.k;
+            st->model_imbalance = lc.model_imb;
+            st->sample_imbalance = lc.sample_imb;
+            st->bucket_imbalance = lc.use_model ? lc.model_imb : lc.sample_imb;
+            st->final_loss = loss;
+            float ms = 0.f;
+            HS_HIP(hipEventElapsedTime(&ms, lev[2], lev[3]));
+            st->learn_ms = ms;
+            HS_HIP(hipEventElapsedTime(&ms, lev[3], lev[4]));
+            st->multiway_ms = ms;
+        }
         if (h->err) return fail(HS_EINTERNAL, "error bits 0x%x", h->err);
     }
     return HS_OK;
+}
+
+template <int F>
+int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
+             hs_stats *st, hipStream_t stream)
+{
+    const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
+                         : (F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : HS_OP_SORT_KV_I32);
+    Layout L;
+    int rc = layout_for(op, n, nseg, o, &L);
+    if (rc) return rc;
+    const LearnParams P = learn_params(o, n, op);
+    std::lock_guard<std::mutex> lk(d->mu);
+    char *ws = nullptr;
+    rc = bind_workspace(d, o, L, &ws);
+    if (rc) return rc;
+    const bool shared_ws = !(o && o->workspace);
+    if (shared_ws) HS_HIP(hipStreamWaitEvent(stream, d->last, 0));
+    rc = sort_body<F>(d, ws, L, raw, n, d_off, nseg, o, P, st, stream);
+    if (shared_ws) HS_HIP(hipEventRecord(d->last, stream));
+    return rc;
 }
 
 int check_n(int64_t n)
@@ -468,6 +667,171 @@ int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_l
     k_write_count<<<1, 64, 0, s>>>(cur, d_count_le);
     HS_LAUNCHED();
     if (shared_ws) HS_HIP(hipEventRecord(d->last, s));
+    return HS_OK;
+}
+
+// ---- the learned method's kernels on their own
+
+int hs_mlp_forward_f32(const float *d_params, const float *d_z, int64_t m, float *d_out, void *stream)
+{
+    if (m < 0 || m > ((int64_t)1 << 30)) return fail(HS_EINVAL, "m = %lld outside 0..2^30", (long long)m);
+    if (m > 0 && (!d_params || !d_z || !d_out)) return fail(HS_EINVAL, "NULL pointer");
+    if (m == 0) return HS_OK;
+    DevState *d;
+    int rc;
+    if ((rc = get_device(&d))) return rc;
+    k_mlp_forward<<<(uint32_t)((m + 255) / 256), 256, 0, (hipStream_t)stream>>>(d_params, d_z, (uint32_t)m, d_out);
+    HS_LAUNCHED();
+    return HS_OK;
+}
+
+namespace {
+
+// Scratch of the MLP entry points: partial gradients of every workgroup,
+// per-workgroup losses and the Adam moments.
+struct MlpScratch {
+    size_t part, lossb, mom, vel, total;
+};
+
+MlpScratch mlp_scratch(uint32_t m)
+{
+    MlpScratch S;
+    const size_t g = (m + 255) / 256;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    S.part = take(g * MLP_PS * 4);
+    S.lossb = take(g * 4);
+    S.mom = take(MLP_NP * 4);
+    S.vel = take(MLP_NP * 4);
+    S.total = off;
+    return S;
+}
+
+int mlp_args(const float *a, const float *b, int64_t m)
+{
+    if (m < 1 || m > ((int64_t)1 << 20)) return fail(HS_EINVAL, "m = %lld outside 1..2^20", (long long)m);
+    if (!a || !b) return fail(HS_EINVAL, "NULL pointer");
+    return HS_OK;
+}
+
+}  // namespace
+
+int hs_mlp_grad_f32(const float *d_params, const float *d_z, const float *d_y, int64_t m, float *d_grad,
+                    void *stream)
+{
+    int rc = mlp_args(d_z, d_y, m);
+    if (rc) return rc;
+    if (!d_params || !d_grad) return fail(HS_EINVAL, "NULL pointer");
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const MlpScratch S = mlp_scratch((uint32_t)m);
+    Layout L;
+    L.total = S.total;
+    std::lock_guard<std::mutex> lk(d->mu);
+    char *ws = nullptr;
+    if ((rc = bind_workspace(d, nullptr, L, &ws))) return rc;
+    HS_HIP(hipStreamWaitEvent(s, d->last, 0));
+    const uint32_t G = (uint32_t)((m + 255) / 256);
+    float *part = (float *)(ws + S.part);
+    k_mlp_grad<<<G, 256, 0, s>>>(d_params, d_z, d_y, (uint32_t)m, part, nullptr);
+    HS_LAUNCHED();
+    k_mlp_update<<<MLP_UPDATE_GRID, 256, 0, s>>>(nullptr, nullptr, nullptr, part, G, 1, 0.f, d_grad, nullptr, nullptr,
+                                                 (uint32_t)m);
+    HS_LAUNCHED();
+    HS_HIP(hipEventRecord(d->last, s));
+    return HS_OK;
+}
+
+int hs_mlp_train_f32(const float *d_z, const float *d_y, int64_t m, int32_t steps, float lr, uint64_t seed,
+                     float *d_params, float *d_loss, void *stream)
+{
+    int rc = mlp_args(d_z, d_y, m);
+    if (rc) return rc;
+    if (!d_params) return fail(HS_EINVAL, "d_params is NULL");
+    if (steps < 0 || steps > 100000) return fail(HS_EINVAL, "steps = %d outside 0..100000", steps);
+    if (!(lr > 0.f) || lr > 1.f) return fail(HS_EINVAL, "lr outside (0, 1]");
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const MlpScratch S = mlp_scratch((uint32_t)m);
+    Layout L;
+    L.total = S.total;
+    std::lock_guard<std::mutex> lk(d->mu);
+    char *ws = nullptr;
+    if ((rc = bind_workspace(d, nullptr, L, &ws))) return rc;
+    HS_HIP(hipStreamWaitEvent(s, d->last, 0));
+    float *mom = (float *)(ws + S.mom), *vel = (float *)(ws + S.vel);
+    float *part = (float *)(ws + S.part), *lossb = (float *)(ws + S.lossb);
+    const uint32_t G = (uint32_t)((m + 255) / 256);
+    k_mlp_init<<<(MLP_NP + 255) / 256, 256, 0, s>>>(d_params, mom, vel, seed);
+    HS_LAUNCHED();
+    for (int t = 1; t <= steps; ++t) {
+        k_mlp_grad<<<G, 256, 0, s>>>(d_params, d_z, d_y, (uint32_t)m, part, lossb);
+        HS_LAUNCHED();
+        k_mlp_update<<<MLP_UPDATE_GRID, 256, 0, s>>>(d_params, mom, vel, part, G, t, lr, nullptr, lossb,
+                                                     d_loss ? d_loss + (t - 1) : nullptr, (uint32_t)m);
+        HS_LAUNCHED();
+    }
+    HS_HIP(hipEventRecord(d->last, s));
+    return HS_OK;
+}
+
+int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_splitters, int32_t k, uint32_t *d_start,
+                              void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (k < 0 || k > NSPLIT) return fail(HS_EINVAL, "k = %d outside 0..%d", k, NSPLIT);
+    if (!d_start || (n > 0 && !keys) || (k > 0 && !d_splitters)) return fail(HS_EINVAL, "NULL pointer");
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t o_copy = take((size_t)n * 8), o_hist = take((size_t)NB_MAX * MW_GMAX * 4),
+                 o_tot = take(NB_MAX * 4), o_lctl = take(sizeof(LearnCtl));
+    Layout L;
+    L.total = off;
+    std::lock_guard<std::mutex> lk(d->mu);
+    char *ws = nullptr;
+    if ((rc = bind_workspace(d, nullptr, L, &ws))) return rc;
+    HS_HIP(hipStreamWaitEvent(s, d->last, 0));
+    LearnCtl *lc = (LearnCtl *)(ws + o_lctl);
+    uint32_t *hist = (uint32_t *)(ws + o_hist), *tot = (uint32_t *)(ws + o_tot);
+    k_ls_set_k<<<1, 1, 0, s>>>(lc, (uint32_t)k);
+    HS_LAUNCHED();
+    if (n > 0) {
+        // out of place: stage the input in the workspace, scatter back
+        HS_HIP(hipMemcpyAsync(ws + o_copy, keys, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+        uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
+        const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 4 - 1) / ((uint64_t)d->ncu * 4));
+        if (chunk < cmin) chunk = cmin;
+        chunk = (chunk + MW_TILE - 1) / MW_TILE * MW_TILE;
+        const uint32_t G = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
+        const Raw src{ws + o_copy, nullptr};
+        const uint64_t *sp = d_splitters;
+        k_mw_hist<FMT_F64, true><<<G, MW_NT, 0, s>>>(src, nullptr, (uint32_t)n, chunk, sp, lc, hist);
+        HS_LAUNCHED();
+        k_mw_scan_cols<<<NB_MAX, 1024, 0, s>>>(hist, G, lc, tot);
+        HS_LAUNCHED();
+        k_mw_scan_starts<<<1, 1024, 0, s>>>(tot, lc, d_start);
+        HS_LAUNCHED();
+        k_mw_scatter<FMT_F64, true, true><<<G, MW_NT, 0, s>>>(src, nullptr, (uint32_t)n, chunk, sp, lc, hist,
+                                                               d_start, nullptr, Raw{keys, nullptr});
+        HS_LAUNCHED();
+    } else {
+        HS_HIP(hipMemsetAsync(d_start, 0, (size_t)(2 * k + 2) * 4, s));  // no bucket has keys
+    }
+    HS_HIP(hipEventRecord(d->last, s));
     return HS_OK;
 }
 

@@ -106,3 +106,46 @@ def test_product_path_never_imports_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "liboracle" not in txt, f
+
+
+def test_header_declares_learned_entry_points():
+    names = set(_declared())
+    for n in ["hs_mlp_forward_f32", "hs_mlp_grad_f32", "hs_mlp_train_f32", "hs_multiway_partition_f64"]:
+        assert n in names
+
+
+def test_learned_options_validated(hs):
+    n = 1 << 20
+    plain = hs.workspace_size(hs.OP_SORT_F64, n)
+    learned = hs.workspace_size(hs.OP_SORT_F64, n, opts=hs.learned_opts())
+    # sample, nested sample workspace, model, partial gradients, histograms
+    assert learned > plain + (1 << 16) * 8
+    # the segmented sort ignores the learned method
+    seg = hs.workspace_size(hs.OP_SORT_SEGMENTED_I32, n, 10)
+    assert hs.workspace_size(hs.OP_SORT_SEGMENTED_I32, n, 10, opts=hs.learned_opts()) == seg
+    for bad in (hs.learned_opts(sample_log2=5), hs.learned_opts(sample_log2=21),
+                hs.learned_opts(flags=hs.LEARN_FORCE_MODEL | hs.LEARN_FORCE_SAMPLE), hs.learned_opts(flags=8),
+                hs.learned_opts(steps=-1), hs.learned_opts(lr=2.0)):
+        with pytest.raises(hs.HSortError):
+            hs.workspace_size(hs.OP_SORT_F64, n, opts=bad)
+    o = hs.Opts()
+    o.method = 7
+    with pytest.raises(hs.HSortError):
+        hs.workspace_size(hs.OP_SORT_F64, n, opts=o)
+
+
+def test_learned_argument_errors_before_launch(hs):
+    L = hs.lib()
+    p = ctypes.c_void_p(0x1000)
+    assert L.hs_mlp_forward_f32(None, None, 0, None, None) == 0
+    assert L.hs_mlp_forward_f32(None, p, 5, p, None) == -1
+    assert L.hs_mlp_grad_f32(p, p, p, 0, p, None) == -1
+    assert L.hs_mlp_grad_f32(p, p, p, (1 << 20) + 1, p, None) == -1
+    assert L.hs_mlp_grad_f32(None, p, p, 10, p, None) == -1
+    assert L.hs_mlp_train_f32(p, p, 10, -1, 0.01, 0, p, None, None) == -1
+    assert L.hs_mlp_train_f32(p, p, 10, 5, 0.0, 0, p, None, None) == -1
+    assert L.hs_mlp_train_f32(p, p, 10, 5, 0.01, 0, None, None, None) == -1
+    assert L.hs_multiway_partition_f64(p, 10, p, 256, p, None) == -1
+    assert L.hs_multiway_partition_f64(p, 10, p, -1, p, None) == -1
+    assert L.hs_multiway_partition_f64(p, 10, None, 3, p, None) == -1
+    assert L.hs_multiway_partition_f64(p, 10, p, 3, None, None) == -1
