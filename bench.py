@@ -117,7 +117,7 @@ class Case:
         return hs.sort_segmented_(self.work, self.off, stats=True)
 
 
-def run_gpu(name, steps, warmup):
+def run_gpu(name, steps, warmup, driver=0):
     import torch
 
     import paper_1704_08579_amd as hs
@@ -126,7 +126,8 @@ def run_gpu(name, steps, warmup):
     dists = CONFIGS[name][2] if CONFIGS[name][0] == "f64" else [None] * len(inputs)
     cases = [Case(k, d, torch) for k, d in inputs]
     del inputs
-    opts = hs.learned_opts(seed=100, flags=LEARNED[name]) if name in LEARNED else None
+    opts = hs.learned_opts(seed=100, flags=LEARNED[name]) if name in LEARNED else hs.Opts()
+    opts.driver = driver
     learn = {d: [] for d in dists} if name in LEARNED else None
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -187,13 +188,13 @@ def run_gpu(name, steps, warmup):
     )
 
 
-def measured_traffic(name):
-    """HBM traffic per launch of the partition kernel from the committed
+def measured_traffic(name, kernel):
+    """HBM traffic per launch of the dominant kernel from the committed
     rocprofv3 --pmc summary for this workload, or None when there is none or
     the kernel source has changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"k_partition_{name}.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}.md")
     src = os.path.join(ROOT, "paper_1704_08579_amd", "csrc", "hs_kernels.hpp")
     if not os.path.exists(path):
         return None
@@ -248,19 +249,22 @@ def main():
     ap.add_argument("--config", default="f64_2e27", choices=sorted(CONFIGS))
     ap.add_argument("--extra", action="store_true", help="also run the int32, key/value and batched configs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--driver", choices=["persistent", "host"], default="host",
+                    help="partition levels in one persistent launch, or one launch per level")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
 
-    r = run_gpu(args.config, args.steps, args.warmup)
+    driver = 2 if args.driver == "persistent" else 1
+    r = run_gpu(args.config, args.steps, args.warmup, driver)
     extra = {}
     if args.extra:
         for nm in ["i32_2e28", "kv_2e28", "seg_A", "seg_B", "i32_2e20", "learned_2e28",
                    "sampled_2e28_learned_inputs", "plain_2e28_learned_inputs"]:
             if nm == args.config:
                 continue
-            e = run_gpu(nm, max(3, args.steps // 2), 1)
+            e = run_gpu(nm, max(3, args.steps // 2), 1, driver)
             extra[nm] = {"gkeys_per_s": round(e["gkeys"], 3), "ms_per_step": round(e["ms_per_step"], 3),
                          "bytes_per_key": round(e["bytes_per_key"], 1),
                          "partition_gbs": round(e["partition"]["gbs"], 1),
@@ -295,9 +299,11 @@ def main():
                    "local_sort_ms_per_step": round(r["local"]["ms_per_step"], 3),
                    "partition_ms_per_step": round(p["ms_per_step"], 3),
                    "partition_launches_per_step": p["launches_per_step"]},
-        "roofline": {"bound": "hbm", "kernel": "k_partition (global partition pass)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_levels (every partition level of a sort in one persistent launch)" if driver == 2
+                                else "k_partition (one partition level per launch)"),
                      "achieved": round(p["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.config),
+                     "frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.config, "k_levels" if driver == 2 else "k_partition"),
                      "bytes_per_launch": round(p["bytes_per_launch"]),
                      "avg_launch_ms": round(p["avg_launch_ms"], 4)},
         "cpu_baseline": cpu,

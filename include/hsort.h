@@ -70,6 +70,16 @@ enum { HS_PIVOT_AUTO = 0,     /* the tuned default */
 enum { HS_METHOD_PLAIN = 0,     /* the paper's method: one pivot per partition */
        HS_METHOD_LEARNED = 1 }; /* a 256-way split by learned splitters first (see below) */
 
+/* Level drivers (hs_opts.driver).  In both, the segment list of the next
+ * level is built on the device by the kernels that finalize a level.
+ * PERSISTENT runs every partition level in one launch whose workgroups meet
+ * at grid barriers: no host round trip, so the call can be captured into a
+ * graph.  HOST launches the levels in batches of fixed-grid kernels and
+ * reads the control block back after each batch; on this chip a kernel
+ * boundary costs less than a grid barrier, so it is the faster one.  AUTO
+ * (0) takes HOST, or PERSISTENT while the stream is being captured. */
+enum { HS_DRIVER_AUTO = 0, HS_DRIVER_HOST = 1, HS_DRIVER_PERSISTENT = 2 };
+
 /* Flags of the learned method (hs_opts.learn_flags). */
 enum { HS_LEARN_FORCE_MODEL = 1,    /* use the model's splitters whatever the judge says */
        HS_LEARN_FORCE_SAMPLE = 2 }; /* use the sample's order statistics (skip the model) */
@@ -108,6 +118,9 @@ typedef struct hs_opts {
     int32_t train_steps;  /* learned method: Adam steps (default 300) */
     int32_t sample_log2;  /* learned method: log2 of the training sample (default 16, range 10..20) */
     float learning_rate;  /* learned method: Adam learning rate (default 1e-2) */
+    int32_t driver;       /* HS_DRIVER_*: how the partition levels are driven */
+    int32_t spin_limit;   /* testing: cap on the polls of one grid-barrier wait (0: about 4M); a wait that
+                           * runs out fails the call with HS_EINTERNAL */
     int32_t reserved;
     uint64_t seed;        /* learned method: seed of the sample draws and the initial weights */
     void *workspace;      /* caller-owned device scratch, or NULL */

@@ -38,6 +38,7 @@ class HSortError(RuntimeError):
 
 
 METHOD_PLAIN, METHOD_LEARNED = 0, 1
+DRIVER_AUTO, DRIVER_HOST, DRIVER_PERSISTENT = 0, 1, 2
 LEARN_FORCE_MODEL, LEARN_FORCE_SAMPLE = 1, 2
 
 
@@ -60,7 +61,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("pivot_rule", ctypes.c_int32), ("local_T", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("learn_flags", ctypes.c_int32),
                 ("train_steps", ctypes.c_int32), ("sample_log2", ctypes.c_int32),
-                ("learning_rate", ctypes.c_float), ("reserved", ctypes.c_int32),
+                ("learning_rate", ctypes.c_float), ("driver", ctypes.c_int32),
+                ("spin_limit", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 

@@ -26,6 +26,11 @@ FLAGS = [
     "-fvisibility=hidden",
     # hipcc -O3 forms packed fp32 ops by itself; keep them off.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Every atomic here is issued by one lane on purpose.  The atomic
+    # optimizer rewrites such an atomic into a wave-combined one whose result
+    # is broadcast at once, which makes the partition pass wait for all its
+    # in-flight loads right after reserving a tile's slots.
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-I", INCLUDE,
     "-I", CSRC,
 ]

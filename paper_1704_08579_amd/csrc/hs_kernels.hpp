@@ -40,6 +40,8 @@ constexpr uint32_t ERR_CURSOR = 1u;    // a segment's cursors do not add up
 constexpr uint32_t ERR_CAND_CAP = 2u;  // segment list overflow
 constexpr uint32_t ERR_TASK_CAP = 4u;  // task list overflow
 constexpr uint32_t ERR_OFFSETS = 8u;   // segment offsets outside [0, n_total] or decreasing
+constexpr uint32_t ERR_LEVELS = 16u;   // more partition levels than the driver allows
+constexpr uint32_t ERR_BARRIER = 32u;  // a grid barrier timed out (workgroups not co-resident)
 
 constexpr int PIVOT_MEDIAN3 = 1, PIVOT_NINTHER = 2, PIVOT_SAMPLE = 3;
 
@@ -57,24 +59,29 @@ template <typename K> struct Task {
     K fill;
 };
 
+// The segment list of one partition level, built while the level before it
+// is finalized.  Level L uses list, cursor array and counters number L & 1.
+struct alignas(256) LevelCounts {
+    unsigned long long segs_tiles;  // low half: segments in the list, high half: their tiles
+    unsigned long long keys;        // keys in those segments
+    uint32_t max_seg;               // the largest of them
+};
+
 // Control block of one call, in device memory.  Every counter that many
 // waves update atomically sits on a 256-byte line of its own: atomics on one
 // line serialize.
 struct Ctl {
-    // written by k_plan, read by the kernels of the level
-    uint32_t nseg;                   // segments in the current level list
-    uint32_t ntiles;                 // tiles of the current level
-    uint32_t levels;                 // levels that had at least one segment
-    uint32_t max_seg;                // largest segment of the current level
-    unsigned long long level_keys;   // keys in the current level's segments
-    unsigned long long part_keys;    // sum of level_keys over the levels run
-    alignas(256) uint32_t ncand;     // segments written for the next level
+    LevelCounts lev[2];
     alignas(256) uint32_t ntask;     // tasks for k_local, written from the front of the task list
     alignas(256) uint32_t nsmall;    // tasks for k_small, written from the back of the task list
     alignas(256) uint32_t task_next; // dynamic task counter of k_local
     alignas(256) uint32_t err;       // ERR_* bits
     alignas(256) unsigned long long local_keys;  // keys handed to local tasks
     unsigned long long fill_keys;                // keys handed to fill tasks
+    alignas(256) uint32_t bar_arrive;  // grid barrier of the persistent level driver
+    alignas(256) uint32_t bar_gen;
+    alignas(256) uint32_t levels;      // levels that had at least one segment (one writer)
+    unsigned long long part_keys;      // keys in the segments of every level run
 };
 
 // Items a wave emits over a batch of up to 64 steps are parked one per lane
@@ -134,6 +141,99 @@ __device__ __host__ __forceinline__ uint32_t seg_tiles(uint32_t b, uint32_t e)
     return (e + TILE - 1) / TILE - b / TILE;
 }
 
+// Append the segments a wave holds (lane k: one segment, if `has`) to the
+// next level's list.  One 64-bit atomic reserves both the list slots (low
+// half) and the segments' tiles (high half), so tile0 grows with the slot
+// index and a tile finds its segment by binary search.  The cursor word of
+// each new slot is cleared here.
+template <typename K>
+__device__ __forceinline__ void wave_emit_segs(Seg<K> item, bool has, Seg<K> *list, unsigned long long *curs,
+                                               LevelCounts *lc, uint32_t cap, Ctl *ctl)
+{
+    const uint64_t m = __ballot(has);
+    if (m == 0) return;
+    const int lane = lane_id();
+    const uint32_t nt = has ? seg_tiles<K>(item.b, item.e) : 0u;
+    const uint32_t sz = has ? item.e - item.b : 0u;
+    const uint32_t incl = wave_incl_scan(nt);
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, WAVE - 1);
+    const unsigned long long keys = wave_sum64(sz);
+    uint32_t mx = sz;
+    for (int d = 1; d < WAVE; d <<= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d));
+    unsigned long long base = 0;
+    if (lane == 0) {
+        base = atomicAdd(&lc->segs_tiles, ((unsigned long long)tot << 32) | (unsigned long long)__popcll(m));
+        atomicAdd(&lc->keys, keys);
+        atomicMax(&lc->max_seg, mx);
+    }
+    const uint32_t slot0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+    const uint32_t tile_base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(base >> 32));
+    if (has) {
+        const uint32_t k = slot0 + mask_below(m);
+        if (k < cap) {
+            item.tile0 = tile_base + incl - nt;
+            list[k] = item;
+            curs[(size_t)k * CUR_STRIDE] = 0ull;
+        } else {
+            atomicOr(&ctl->err, ERR_CAND_CAP);
+        }
+    }
+}
+
+// Number of segments of a level list that may be read (an overflow is
+// flagged in err; never read past the list).
+__device__ __forceinline__ uint32_t level_segs(unsigned long long st, uint32_t cap)
+{
+    return min((uint32_t)st, cap);
+}
+
+// ---------------------------------------------------------------- grid barrier
+
+// Barrier over every workgroup of a persistent launch (all of them resident:
+// the grid never exceeds what the occupancy calculator reports).  Arrival is
+// one device-scope atomic per workgroup; the last arrival resets the count
+// and bumps the generation, which the others poll with a bounded spin.  The
+// agent-scope fences on both sides make every write before the barrier
+// visible to every read after it, across the chip's L2 slices.  A spin that
+// runs out sets ERR_BARRIER; every workgroup then leaves the driver.
+constexpr uint32_t BARRIER_SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ bool grid_barrier(Ctl *ctl, uint32_t &gen, uint32_t spin_limit)
+{
+    __shared__ uint32_t s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        __threadfence();
+        if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER) {
+            ok = false;  // another workgroup gave up: leave without arriving
+        } else if (atomicAdd(&ctl->bar_arrive, 1u) == gridDim.x - 1) {
+            atomicExch(&ctl->bar_arrive, 0u);
+            __threadfence();
+            atomicAdd(&ctl->bar_gen, 1u);
+        } else {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER) {
+                    ok = false;
+                    break;
+                }
+                if (++spins > spin_limit) {
+                    atomicOr(&ctl->err, ERR_BARRIER);
+                    ok = false;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __threadfence();
+        ++gen;
+        s_ok = ok ? 1u : 0u;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
 // ---------------------------------------------------------------- pivot choice
 
 // Key readers: an internal buffer of order words, or the caller's arrays.
@@ -188,9 +288,9 @@ __device__ K wave_pick_pivot(const Rd &rd, uint32_t b, uint32_t e, int rule, int
 // One array: the whole range becomes a level-0 segment, or a single local
 // task when it fits on chip.
 template <int F>
-__global__ void k_init_single(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand, Task<typename KeyOf<F>::type> *tasks,
-                              Raw raw, uint32_t n, uint32_t T, uint32_t leaf, uint32_t task_cap, int rule,
-                              int has_pivot, typename KeyOf<F>::type user_pivot)
+__global__ void k_init_single(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand, unsigned long long *cur,
+                              Task<typename KeyOf<F>::type> *tasks, Raw raw, uint32_t n, uint32_t T, uint32_t leaf,
+                              uint32_t task_cap, int rule, int has_pivot, typename KeyOf<F>::type user_pivot)
 {
     using K = typename KeyOf<F>::type;
     if (blockIdx.x != 0 || threadIdx.x >= WAVE) return;
@@ -228,7 +328,10 @@ __global__ void k_init_single(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand, Task
     }
     if (lane == 0) {
         cand[0] = s;
-        ctl->ncand = 1;
+        cur[0] = 0ull;
+        ctl->lev[0].segs_tiles = ((unsigned long long)seg_tiles<K>(0, n) << 32) | 1ull;
+        ctl->lev[0].keys = n;
+        ctl->lev[0].max_seg = n;
     }
 }
 
@@ -238,6 +341,7 @@ __global__ void k_init_single(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand, Task
 // segment after the other).
 template <int F>
 __global__ __launch_bounds__(256) void k_init_segmented(Ctl *ctl, Seg<typename KeyOf<F>::type> *cand,
+                                                        unsigned long long *cur,
                                                         Task<typename KeyOf<F>::type> *tasks, Raw raw,
                                                         const int64_t *off, uint32_t nseg, uint32_t n_total,
                                                         uint32_t T, uint32_t leaf, int rule, uint32_t cand_cap,
@@ -286,66 +390,7 @@ __global__ __launch_bounds__(256) void k_init_segmented(Ctl *ctl, Seg<typename K
         const K p = wave_pick_pivot<K>(rd, bb, ee, rule, lane);
         if (lane == src) sg.piv = p;
     }
-    wave_flush(sg, is_big, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
-}
-
-// ---------------------------------------------------------------- plan
-
-// One workgroup: turn the candidate list into the level list (exclusive scan
-// of tile counts), zero the write cursors, publish the level's sizes.
-template <typename K>
-__global__ __launch_bounds__(1024) void k_plan(Ctl *ctl, Seg<K> *segs, unsigned long long *cur, uint32_t cap)
-{
-    __shared__ uint32_t wsum[16];
-    __shared__ unsigned long long wkeys[16];
-    __shared__ uint32_t wmax[16];
-    const uint32_t n = min(ctl->ncand, cap);  // an overflow is flagged in err; never read past the list
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-    const int nw = blockDim.x / WAVE;
-    uint32_t carry = 0, mx = 0;
-    unsigned long long keys = 0;
-    for (uint32_t base = 0; base < n; base += blockDim.x) {
-        const uint32_t i = base + tid;
-        uint32_t nt = 0, sz = 0;
-        if (i < n) {
-            nt = seg_tiles<K>(segs[i].b, segs[i].e);
-            sz = segs[i].e - segs[i].b;
-        }
-        const uint32_t incl = wave_incl_scan(nt);
-        const unsigned long long ks = wave_sum64(sz);
-        uint32_t wm = sz;
-        for (int d = 1; d < WAVE; d <<= 1) wm = max(wm, (uint32_t)__shfl_xor((int)wm, d));
-        if (lane == WAVE - 1) wsum[wave] = incl;
-        if (lane == 0) {
-            wkeys[wave] = ks;
-            wmax[wave] = wm;
-        }
-        __syncthreads();
-        uint32_t pre = 0, tot = 0;
-        unsigned long long ksum = 0;
-        for (int w = 0; w < nw; ++w) {
-            if (w < wave) pre += wsum[w];
-            tot += wsum[w];
-            ksum += wkeys[w];
-            mx = max(mx, wmax[w]);
-        }
-        if (i < n) {
-            segs[i].tile0 = carry + pre + incl - nt;
-            cur[(size_t)i * CUR_STRIDE] = 0ull;
-        }
-        carry += tot;
-        keys += ksum;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        ctl->nseg = n;
-        ctl->ntiles = carry;
-        ctl->ncand = 0;
-        ctl->level_keys = keys;
-        ctl->max_seg = mx;
-        ctl->part_keys += keys;
-        if (n) ctl->levels += 1;
-    }
+    wave_emit_segs(sg, is_big, cand, cur, &ctl->lev[0], cand_cap, ctl);
 }
 
 // ---------------------------------------------------------------- partition pass
@@ -364,43 +409,92 @@ template <typename K> struct TileLoc {
 // cursor word (low half: front cursor, high half: back cursor -- Algorithm
 // 3's left_w and right_w), compact the tile in LDS (<= keys first) and write
 // both runs out with consecutive lanes on consecutive addresses.
+// Bounds-checked loads: a buffer resource covering one tile's keys; a lane
+// past the end reads zero and moves no data, so every tile runs the same
+// straight-line code.
+constexpr int BUF_RSRC_WORD3 = 0x00020000;  // raw buffer, 32-bit dwords (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, BUF_RSRC_WORD3);
+}
+
+__device__ __forceinline__ uint32_t rsrc_load32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0);
+}
+
+__device__ __forceinline__ uint64_t rsrc_load64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0);
+    return ((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0];
+}
+
+// s_waitcnt on the vector-memory counter alone: at most n operations still
+// outstanding (gfx9 encoding: vmcnt bits 3:0 and 15:14; expcnt and lgkmcnt
+// left at their maxima).
+template <int N> __device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt is 6 bits");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | 0x70 | 0xF00);
+}
+
+// Workgroup `wg` of `nwg` takes the tiles [wg*per, (wg+1)*per) of the
+// level.  The tile count is bounded by the tiles of the segments in the list
+// (a list overflow, which is flagged, cannot create tiles without keys), so
+// every tile holds at least one key.  The LDS staging area is the caller's,
+// so the persistent driver shares it between levels.
+//
+// Order within a tile: classify, scan, reserve (the cursor atomic), issue
+// the next tile's loads, compact in LDS, write out.  Loads and stores share
+// one in-order counter on this chip, so the code between the atomic and the
+// use of its result, and the write-out, are straight-line with a fixed
+// number of memory instructions: waiting for the atomic then waits neither
+// for the next tile's loads nor for anything younger, and the next tile's
+// reads overlap this tile's writes.
 template <int F, bool SRC_IS_RAW, bool DST_IS_RAW>
-__global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partition(const Ctl *ctl, const Seg<typename KeyOf<F>::type> *segs,
-                                                   unsigned long long *cur, const typename KeyOf<F>::type *src,
-                                                   Raw raw, typename KeyOf<F>::type *dst, Raw raw_dst,
-                                                   int aligned)
+__device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
+                                                const Seg<typename KeyOf<F>::type> *segs, unsigned long long *cur,
+                                                const typename KeyOf<F>::type *src, Raw raw,
+                                                typename KeyOf<F>::type *dst, Raw raw_dst, uint32_t wg, uint32_t nwg,
+                                                typename KeyOf<F>::type *stage, uint32_t *wsum, uint32_t *sbase)
 {
     using K = typename KeyOf<F>::type;
     constexpr int NT = PartCfg<K>::NT, TILE = PartCfg<K>::TILE, ITEMS = TILE / NT;
     constexpr int NW = NT / WAVE;
     static_assert(ITEMS <= 32, "item masks are 32-bit");
     static_assert(TILE < 65536, "per-tile counts are 16-bit");
-    __shared__ K stage[TILE];
-    __shared__ uint32_t wsum[NW];
-    __shared__ uint32_t sbase[2];
 
-    const uint32_t ntiles = ctl->ntiles, nseg = ctl->nseg;
-    const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-    uint32_t t = blockIdx.x * per;
+    if (nseg == 0) return;
+    {
+        const Seg<K> last = segs[nseg - 1];
+        ntiles = min(ntiles, last.tile0 + seg_tiles<K>(last.b, last.e));
+    }
+    const uint32_t per = (ntiles + nwg - 1) / nwg;
+    uint32_t t = wg * per;
     const uint32_t tend = min(ntiles, t + per);
     if (t >= tend) return;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
 
-    // segment of the first tile, and a look-ahead copy of the one after it
+    // segment of the first tile
     uint32_t lo = 0, hi = nseg;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (segs[mid].tile0 <= t) lo = mid; else hi = mid;
     }
+    // the current segment and a look-ahead copy of the one after it (plain
+    // conditional loads: a select between whole records would go through
+    // scratch memory)
     uint32_t s_next = lo;
     Seg<K> sg_next = segs[s_next];
-    Seg<K> sg_after = (s_next + 1 < nseg) ? segs[s_next + 1] : sg_next;
+    Seg<K> sg_after = sg_next;
+    if (s_next + 1 < nseg) sg_after = segs[s_next + 1];
 
     auto locate = [&](uint32_t tt, Seg<K> &sg_out) {
         while (s_next + 1 < nseg && tt >= sg_after.tile0) {
             ++s_next;
             sg_next = sg_after;
-            sg_after = (s_next + 1 < nseg) ? segs[s_next + 1] : sg_next;
+            if (s_next + 1 < nseg) sg_after = segs[s_next + 1];
         }
         sg_out = sg_next;
         TileLoc<K> L;
@@ -408,85 +502,61 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partit
         const uint32_t a = sg_next.b / TILE + (tt - sg_next.tile0);
         L.p0 = max(sg_next.b, a * TILE);
         L.cnt = min(sg_next.e, (a + 1) * TILE) - L.p0;
-        L.full = aligned && L.cnt == (uint32_t)TILE;
+        L.full = L.cnt == (uint32_t)TILE;
         return L;
     };
-    auto load = [&](const TileLoc<K> &L, K (&x)[ITEMS]) {
-        if (L.full) {
-            if constexpr (F == FMT_KV && SRC_IS_RAW) {
-                const uint4 *kp = (const uint4 *)((const uint32_t *)raw.keys + L.p0);
-                const uint4 *vp = (const uint4 *)((const uint32_t *)raw.vals + L.p0);
-#pragma unroll
-                for (int j = 0; j < ITEMS / 4; ++j) {
-                    const uint4 kk = kp[j * NT + tid], vv = vp[j * NT + tid];
-                    x[4 * j + 0] = enc_kv(kk.x, vv.x);
-                    x[4 * j + 1] = enc_kv(kk.y, vv.y);
-                    x[4 * j + 2] = enc_kv(kk.z, vv.z);
-                    x[4 * j + 3] = enc_kv(kk.w, vv.w);
-                }
-            } else if constexpr (sizeof(K) == 4) {
-                const uint4 *pp = (const uint4 *)((SRC_IS_RAW ? (const K *)raw.keys : src) + L.p0);
-#pragma unroll
-                for (int j = 0; j < ITEMS / 4; ++j) {
-                    const uint4 v = pp[j * NT + tid];
-                    x[4 * j + 0] = v.x;
-                    x[4 * j + 1] = v.y;
-                    x[4 * j + 2] = v.z;
-                    x[4 * j + 3] = v.w;
-                }
-                if constexpr (SRC_IS_RAW) {
-#pragma unroll
-                    for (int j = 0; j < ITEMS; ++j) x[j] = (K)enc_i32((uint32_t)x[j]);
-                }
-            } else {
-                const ulonglong2 *pp = (const ulonglong2 *)((SRC_IS_RAW ? (const K *)raw.keys : src) + L.p0);
-#pragma unroll
-                for (int j = 0; j < ITEMS / 2; ++j) {
-                    const ulonglong2 v = pp[j * NT + tid];
-                    x[2 * j + 0] = v.x;
-                    x[2 * j + 1] = v.y;
-                }
-                if constexpr (SRC_IS_RAW) {
-#pragma unroll
-                    for (int j = 0; j < ITEMS; ++j) x[j] = (K)enc_f64((uint64_t)x[j]);
-                }
-            }
-        } else {
+    // lane tid takes keys j*NT + tid of the tile: consecutive lanes read
+    // consecutive addresses.  The tile's place is the same in every lane;
+    // readfirstlane says so, so the buffer resource lives in scalar registers.
+    auto load = [&](const TileLoc<K> &Lv, K (&x)[ITEMS]) {
+        TileLoc<K> L;
+        L.p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)Lv.p0);
+        L.cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)Lv.cnt);
+        if constexpr (SRC_IS_RAW && F == FMT_KV) {
+            const auto rk = tile_rsrc((const uint32_t *)raw.keys + L.p0, L.cnt * 4u);
+            const auto rv = tile_rsrc((const uint32_t *)raw.vals + L.p0, L.cnt * 4u);
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t i = (uint32_t)(j * NT + tid);
-                if (i < L.cnt) {
-                    if constexpr (SRC_IS_RAW) x[j] = raw_load<F>(raw, L.p0 + i);
-                    else x[j] = src[L.p0 + i];
-                } else {
-                    x[j] = 0;
-                }
+                const uint32_t off = (uint32_t)(j * NT + tid) * 4u;
+                x[j] = enc_kv(rsrc_load32(rk, off), rsrc_load32(rv, off));
+            }
+        } else if constexpr (sizeof(K) == 4) {
+            const auto r = tile_rsrc((SRC_IS_RAW ? (const K *)raw.keys : src) + L.p0, L.cnt * 4u);
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t v = rsrc_load32(r, (uint32_t)(j * NT + tid) * 4u);
+                x[j] = SRC_IS_RAW ? (K)enc_i32(v) : (K)v;
+            }
+        } else {
+            const auto r = tile_rsrc((SRC_IS_RAW ? (const K *)raw.keys : src) + L.p0, L.cnt * 8u);
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint64_t v = rsrc_load64(r, (uint32_t)(j * NT + tid) * 8u);
+                x[j] = SRC_IS_RAW ? (K)enc_f64(v) : (K)v;
             }
         }
     };
+
+    // Stores issued by the write-out of one tile.
+    constexpr int STORES = ITEMS * ((DST_IS_RAW && F == FMT_KV) ? 2 : 1);
+    static_assert(STORES < 64, "vmcnt is 6 bits");
 
     Seg<K> sg;
     TileLoc<K> L = locate(t, sg);
     K x[ITEMS];
     load(L, x);
+    // Both edges into the loop arrive with the tile's keys loaded, so the loop
+    // head waits for nothing (the back edge may still have stores in flight).
+    wait_vmcnt<0>();
 
     for (; t < tend; ++t) {
-        // issue the next tile's loads before working on this one
-        Seg<K> sgn;
-        TileLoc<K> Ln = L;
-        K xn[ITEMS];
         const bool more = t + 1 < tend;
-        if (more) {
-            Ln = locate(t + 1, sgn);
-            load(Ln, xn);
-        }
-
         const bool strict = (sg.flags & SEG_STRICT) != 0;
         const K piv = sg.piv;
         uint32_t lemask = 0, vmask = 0;
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
-            const bool valid = L.full || (uint32_t)(j * NT + tid) < L.cnt;
+            const bool valid = (uint32_t)(j * NT + tid) < L.cnt;
             const bool le = strict ? (x[j] < piv) : (x[j] <= piv);
             if (valid) {
                 vmask |= 1u << j;
@@ -498,6 +568,18 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partit
         const uint32_t code = cle | (cgt << 16);
         const uint32_t incl = wave_incl_scan(code);
         if (lane == WAVE - 1) wsum[wave] = incl;
+        // where the next tile lies (segment records are read before the
+        // atomic below, so that its wait covers nothing else)
+        Seg<K> sgn = sg;
+        TileLoc<K> Ln;
+        if (more) {
+            Ln = locate(t + 1, sgn);
+        } else {
+            Ln.s = L.s;
+            Ln.p0 = L.p0;
+            Ln.cnt = 0;
+            Ln.full = false;
+        }
         __syncthreads();
         uint32_t pre = 0, tot = 0;
 #pragma unroll
@@ -512,6 +594,10 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partit
         if (tid == 0)
             old = atomicAdd(&cur[(size_t)L.s * CUR_STRIDE],
                             (unsigned long long)tot_le | ((unsigned long long)tot_gt << 32));
+        // the next tile's loads (an empty range past the last tile)
+        K xn[ITEMS];
+        load(Ln, xn);
+        asm volatile("" ::: "memory");  // keep the use of the atomic's result below the loads
         uint32_t lp = excl & 0xFFFFu, gp = tot_le + (excl >> 16);
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
@@ -527,20 +613,40 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partit
         __syncthreads();
         // No barrier after the write-out: the next tile's LDS writes come
         // after its first barrier, which every wave reaches only once done here.
+        // Lanes past the end of a partial tile store the tile's last key
+        // again at its own slot: no branch, a fixed number of stores.
         const uint32_t lt_base = sbase[0], gt_base = sbase[1];
-        for (uint32_t i = tid; i < L.cnt; i += NT) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t i = min((uint32_t)(j * NT + tid), L.cnt - 1);
             const K v = stage[i];
             const uint32_t pos = i < tot_le ? lt_base + i : gt_base + (i - tot_le);
             if constexpr (DST_IS_RAW) raw_store<F>(raw_dst, pos, v);
             else dst[pos] = v;
         }
-        if (more) {
-            L = Ln;
-            sg = sgn;
+        wait_vmcnt<STORES>();  // the next tile's loads (older than the stores) are in
+        L = Ln;
+        sg = sgn;
 #pragma unroll
-            for (int j = 0; j < ITEMS; ++j) x[j] = xn[j];
-        }
+        for (int j = 0; j < ITEMS; ++j) x[j] = xn[j];
     }
+    __syncthreads();  // the caller may reuse the staging area
+}
+
+// One partition level as a kernel of its own (the host-driven level loop and
+// the partition entry point): level list number `par`.
+template <int F, bool SRC_IS_RAW, bool DST_IS_RAW>
+__global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partition(
+    const Ctl *ctl, int par, const Seg<typename KeyOf<F>::type> *segs, unsigned long long *cur,
+    const typename KeyOf<F>::type *src, Raw raw, typename KeyOf<F>::type *dst, Raw raw_dst, uint32_t cap)
+{
+    using K = typename KeyOf<F>::type;
+    __shared__ K stage[PartCfg<K>::TILE];
+    __shared__ uint32_t wsum[PartCfg<K>::NT / WAVE];
+    __shared__ uint32_t sbase[2];
+    const unsigned long long st = ctl->lev[par].segs_tiles;
+    partition_level<F, SRC_IS_RAW, DST_IS_RAW>((uint32_t)(st >> 32), level_segs(st, cap), segs, cur, src, raw, dst,
+                                               raw_dst, blockIdx.x, gridDim.x, stage, wsum, sbase);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -557,20 +663,21 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partit
 // When a segment's pivot equals that bound, the segment is split with "<"
 // instead of "<=", which moves every copy of the bound into a final range.
 // This keeps runs of equal keys from being re-partitioned level after level.
+// Fill tasks are cut into chunks of at most FILL_CHUNK keys so that no wave
+// writes a long run of equal keys alone.
+constexpr uint32_t FILL_CHUNK = 1u << 16;
+
 template <int F>
-__global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, const Seg<typename KeyOf<F>::type> *segs,
-                                                  const unsigned long long *cur,
-                                                  Seg<typename KeyOf<F>::type> *cand,
-                                                  Task<typename KeyOf<F>::type> *tasks,
-                                                  const typename KeyOf<F>::type *out, uint32_t out_id,
-                                                  uint32_t T, uint32_t leaf, int rule, uint32_t cand_cap,
-                                                  uint32_t task_cap)
+__device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Seg<typename KeyOf<F>::type> *segs,
+                                               const unsigned long long *cur, Seg<typename KeyOf<F>::type> *cand,
+                                               unsigned long long *ncur, LevelCounts *nlev,
+                                               Task<typename KeyOf<F>::type> *tasks,
+                                               const typename KeyOf<F>::type *out, uint32_t out_id, uint32_t T,
+                                               uint32_t leaf, int rule, uint32_t cand_cap, uint32_t task_cap,
+                                               uint32_t w, uint32_t nwaves)
 {
     using K = typename KeyOf<F>::type;
     const int lane = lane_id();
-    const uint32_t nseg = ctl->nseg;
-    const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
-    const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     SrcReader<F> rd{out, Raw{nullptr, nullptr}, false};
     unsigned long long lkeys = 0, fkeys = 0;
 
@@ -612,8 +719,19 @@ __global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, const Seg<typename K
                 if (side == 1 && strict) {  // keys == pivot: final
                     t.kind = TASK_FILL;
                     t.fill = sg.piv;
-                    is_task = true;
                     fkeys += m;
+                    if (m > FILL_CHUNK) {  // a long run: chunks, one lane each
+                        const uint32_t nchunk = (m + FILL_CHUNK - 1) / FILL_CHUNK;
+                        for (uint32_t c0i = 0; c0i < nchunk; c0i += WAVE) {
+                            const uint32_t ci = c0i + (uint32_t)lane;
+                            Task<K> tc = t;
+                            tc.b = b + min(ci, nchunk) * FILL_CHUNK;
+                            tc.e = min(e, tc.b + FILL_CHUNK);
+                            wave_flush_task(tc, ci < nchunk, true, tasks, task_cap, ctl);
+                        }
+                        continue;
+                    }
+                    is_task = true;
                 } else if (m <= T) {
                     t.kind = TASK_LOCAL;
                     is_task = true;
@@ -638,8 +756,8 @@ __global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, const Seg<typename K
                 }
             }
         }
-        wave_flush(c0, h_c0, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
-        wave_flush(c1, h_c1, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
+        wave_emit_segs(c0, h_c0, cand, ncur, nlev, cand_cap, ctl);
+        wave_emit_segs(c1, h_c1, cand, ncur, nlev, cand_cap, ctl);
         wave_flush_task(t0, h_t0, t0.kind == TASK_FILL || t0.e - t0.b <= leaf, tasks, task_cap, ctl);
         wave_flush_task(t1, h_t1, t1.kind == TASK_FILL || t1.e - t1.b <= leaf, tasks, task_cap, ctl);
     }
@@ -647,6 +765,102 @@ __global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, const Seg<typename K
         if (lkeys) atomicAdd(&ctl->local_keys, lkeys);
         if (fkeys) atomicAdd(&ctl->fill_keys, fkeys);
     }
+}
+
+// Bookkeeping at the start of a level with list number `par`: clear the
+// next level's counters (always: an empty level must leave an empty list
+// behind, not the one of the level before it) and count a non-empty level.
+// One thread.
+__device__ __forceinline__ void level_begin(Ctl *ctl, int par)
+{
+    LevelCounts &nx = ctl->lev[1 - par];
+    atomicExch(&nx.segs_tiles, 0ull);
+    atomicExch(&nx.keys, 0ull);
+    atomicExch(&nx.max_seg, 0u);
+    const LevelCounts &cur = ctl->lev[par];
+    if ((uint32_t)__hip_atomic_load(&cur.segs_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        atomicAdd(&ctl->levels, 1u);
+        atomicAdd(&ctl->part_keys, __hip_atomic_load(&cur.keys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+}
+
+__global__ void k_level_begin(Ctl *ctl, int par)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) level_begin(ctl, par);
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, int par, const Seg<typename KeyOf<F>::type> *segs,
+                                                  const unsigned long long *cur,
+                                                  Seg<typename KeyOf<F>::type> *cand, unsigned long long *ncur,
+                                                  Task<typename KeyOf<F>::type> *tasks,
+                                                  const typename KeyOf<F>::type *out, uint32_t out_id,
+                                                  uint32_t T, uint32_t leaf, int rule, uint32_t cand_cap,
+                                                  uint32_t task_cap)
+{
+    const uint32_t nseg = level_segs(ctl->lev[par].segs_tiles, cand_cap);
+    finalize_level<F>(ctl, nseg, segs, cur, cand, ncur, &ctl->lev[1 - par], tasks, out, out_id, T, leaf, rule,
+                      cand_cap, task_cap, (blockIdx.x * blockDim.x + threadIdx.x) / WAVE,
+                      gridDim.x * (blockDim.x / WAVE));
+}
+
+// ---------------------------------------------------------------- persistent level driver
+
+// Every partition level of one call in a single launch: the workgroups
+// partition the level's tiles, meet at a grid barrier, finalize its segments
+// (building the next level's list and the task lists), meet again, and go on
+// while the next list is non-empty.  Level L reads buffer L & 1 (level 0 the
+// caller's array) and writes buffer (L + 1) & 1.  Every workgroup reads the
+// same list size after the same barrier, so all of them leave together; a
+// barrier that times out (ERR_BARRIER) or too many levels (ERR_LEVELS) end
+// the launch with the error flagged.
+template <int F>
+__global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_levels(
+    Ctl *ctl, Seg<typename KeyOf<F>::type> *seg0, Seg<typename KeyOf<F>::type> *seg1, unsigned long long *cur0,
+    unsigned long long *cur1, typename KeyOf<F>::type *buf0, typename KeyOf<F>::type *buf1, Raw raw,
+    Task<typename KeyOf<F>::type> *tasks, uint32_t T, uint32_t leaf, int rule, int guard, int level0, int lmax,
+    uint32_t cand_cap, uint32_t task_cap, uint32_t spin_limit)
+{
+    using K = typename KeyOf<F>::type;
+    __shared__ K stage[PartCfg<K>::TILE];
+    __shared__ uint32_t wsum[PartCfg<K>::NT / WAVE];
+    __shared__ uint32_t sbase[2];
+    const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
+    uint32_t gen = 0;
+    for (int level = level0;; ++level) {
+        const int p = level & 1;
+        const unsigned long long st =
+            __hip_atomic_load(&ctl->lev[p].segs_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t nseg = level_segs(st, cand_cap), ntiles = (uint32_t)(st >> 32);
+        if (nseg == 0) break;
+        if (level >= lmax) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->err, ERR_LEVELS);
+            break;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) level_begin(ctl, p);
+        Seg<K> *segs = p ? seg1 : seg0, *next = p ? seg0 : seg1;
+        unsigned long long *cur = p ? cur1 : cur0, *ncur = p ? cur0 : cur1;
+        K *dst = p ? buf0 : buf1;
+        if (level == 0)
+            partition_level<F, true, false>(ntiles, nseg, segs, cur, nullptr, raw, dst, Raw{}, blockIdx.x, gridDim.x,
+                                            stage, wsum, sbase);
+        else
+            partition_level<F, false, false>(ntiles, nseg, segs, cur, p ? buf1 : buf0, raw, dst, Raw{}, blockIdx.x,
+                                             gridDim.x, stage, wsum, sbase);
+        if (!grid_barrier(ctl, gen, spin_limit)) break;
+        const int lrule = level > guard ? PIVOT_SAMPLE : rule;
+        finalize_level<F>(ctl, nseg, segs, cur, next, ncur, &ctl->lev[1 - p], tasks, dst, (uint32_t)(1 - p), T,
+                          leaf, lrule, cand_cap, task_cap, wave_id, nwaves);
+        if (!grid_barrier(ctl, gen, spin_limit)) break;
+    }
+}
+
+// Clear `nwords` 32-bit words (a kernel rather than a memset, so that the
+// call can be recorded into a graph).
+__global__ void k_zero_words(uint32_t *p, uint32_t nwords)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
 // Count of the <= side after a single-segment pass (partition entry point).

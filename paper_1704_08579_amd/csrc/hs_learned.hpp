@@ -697,13 +697,12 @@ __global__ void k_ls_set_k(LearnCtl *lc, uint32_t k)
 // so that one wave never fills more than FILL_CHUNK keys), open buckets of at
 // most T keys become local tasks, larger ones the first partition level's
 // segments.  One lane per bucket, wave-batched emission.
-constexpr uint32_t FILL_CHUNK = 1u << 16;
-
 template <int F>
 __global__ __launch_bounds__(256) void k_mw_route(Ctl *ctl, const LearnCtl *lc, const uint32_t *start,
                                                   const typename KeyOf<F>::type *dsplit,
                                                   const typename KeyOf<F>::type *buf, uint32_t buf_id,
-                                                  Seg<typename KeyOf<F>::type> *cand, Task<typename KeyOf<F>::type> *tasks,
+                                                  Seg<typename KeyOf<F>::type> *cand, unsigned long long *cur,
+                                                  Task<typename KeyOf<F>::type> *tasks,
                                                   uint32_t T, uint32_t leaf, int rule, uint32_t cand_cap,
                                                   uint32_t task_cap)
 {
@@ -759,7 +758,7 @@ __global__ __launch_bounds__(256) void k_mw_route(Ctl *ctl, const LearnCtl *lc, 
         const K pv = wave_pick_pivot<K>(rd, x0, x1, rule, lane);
         if (lane == src) sg.piv = pv;
     }
-    wave_flush(sg, big, &ctl->ncand, cand, cand_cap, ctl, ERR_CAND_CAP);
+    wave_emit_segs(sg, big, cand, cur, &ctl->lev[1], cand_cap, ctl);
 }
 
 }  // namespace hs

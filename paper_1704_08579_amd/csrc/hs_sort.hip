@@ -40,6 +40,13 @@ int fail(int code, const char *fmt, ...)
         if (e_ != hipSuccess) return fail(HS_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// Launch a kernel and turn a launch error into HS_EHIP.
+#define HS_LAUNCH(kernel, grid, block, stream, ...)                                     \
+    do {                                                                                \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, stream, __VA_ARGS__);    \
+        HS_LAUNCHED();                                                                  \
+    } while (0)
+
 #define HS_LAUNCHED()                                                                   \
     do {                                                                                \
         hipError_t e_ = hipGetLastError();                                              \
@@ -132,7 +139,7 @@ LearnParams learn_params(const hs_opts *o, int64_t n, int op)
 }
 
 struct Layout {
-    size_t buf0 = 0, buf1 = 0, segA = 0, segB = 0, cur = 0, tasks = 0, ctl = 0, total = 0;
+    size_t buf0 = 0, buf1 = 0, segA = 0, segB = 0, curA = 0, curB = 0, tasks = 0, ctl = 0, total = 0;
     uint32_t cand_cap = 0, task_cap = 0;
     // learned front end (LearnParams::on)
     size_t smp_k = 0, smp_v = 0, sub = 0, z = 0, y = 0, par = 0, mom = 0, vel = 0, part = 0, lossb = 0,
@@ -165,7 +172,8 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParam
     }
     L.segA = take((size_t)L.cand_cap * sizeof(Seg<K>));
     L.segB = take((size_t)L.cand_cap * sizeof(Seg<K>));
-    L.cur = take((size_t)L.cand_cap * 8 * CUR_STRIDE);
+    L.curA = take((size_t)L.cand_cap * 8 * CUR_STRIDE);
+    L.curB = take((size_t)L.cand_cap * 8 * CUR_STRIDE);
     L.tasks = take((size_t)L.task_cap * sizeof(Task<K>));
     L.ctl = take(sizeof(Ctl));
     if (P.on) {
@@ -210,6 +218,9 @@ int pivot_rule(const hs_opts *o) { return (o && o->pivot_rule > 0) ? o->pivot_ru
 int check_learn(const hs_opts *o)
 {
     if (!o) return HS_OK;
+    if (o->driver != HS_DRIVER_AUTO && o->driver != HS_DRIVER_PERSISTENT && o->driver != HS_DRIVER_HOST)
+        return fail(HS_EINVAL, "unknown driver %d", o->driver);
+    if (o->spin_limit < 0) return fail(HS_EINVAL, "spin_limit is negative");
     if (o->method != HS_METHOD_PLAIN && o->method != HS_METHOD_LEARNED)
         return fail(HS_EINVAL, "unknown method %d", o->method);
     if (o->method == HS_METHOD_LEARNED) {
@@ -277,7 +288,11 @@ int bind_workspace(DevState *d, const hs_opts *o, const Layout &L, char **base)
     return HS_OK;
 }
 
-bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+uint32_t zero_grid(size_t bytes)
+{
+    const size_t blocks = (bytes / 4 + 255) / 256;
+    return (uint32_t)(blocks < 1 ? 1 : blocks > 1024 ? 1024 : blocks);
+}
 
 // ---------------------------------------------------------------- driver
 
@@ -299,15 +314,21 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     buf[0] = F == FMT_KV ? (K *)(ws + L.buf0) : (K *)raw.keys;
     buf[1] = (K *)(ws + L.buf1);
     Seg<K> *segs[2] = {(Seg<K> *)(ws + L.segA), (Seg<K> *)(ws + L.segB)};
-    unsigned long long *cur = (unsigned long long *)(ws + L.cur);
+    unsigned long long *curs[2] = {(unsigned long long *)(ws + L.curA), (unsigned long long *)(ws + L.curB)};
     Task<K> *tasks = (Task<K> *)(ws + L.tasks);
     Ctl *ctl = (Ctl *)(ws + L.ctl);
     Ctl *h = d->h_ctl;
-    const int aligned = aligned16(raw.keys) && (F != FMT_KV || aligned16(raw.vals)) ? 1 : 0;
-    hipEvent_t *lev = &d->ev[2 * LMAX];  // [0,1] on-chip sort, [2..4] learned front end
+    hipEvent_t *lev = &d->ev[2 * LMAX];  // [0,1] on-chip sort, [2..4] learned front end, [5,6] level driver
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HS_HIP(hipStreamIsCapturing(stream, &cap));
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    const int drv = o ? o->driver : HS_DRIVER_AUTO;
+    if (capturing && drv == HS_DRIVER_HOST)
+        return fail(HS_EINVAL, "the host-driven level loop cannot be captured into a graph");
+    const bool host_driver = drv == HS_DRIVER_HOST || (drv == HS_DRIVER_AUTO && !capturing);
 
-    HS_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), stream));
-    int level = 0, cur_list = 0, batch = 0;
+    HS_LAUNCH(k_zero_words, zero_grid(sizeof(Ctl)), 256, stream, (uint32_t *)ctl, (uint32_t)(sizeof(Ctl) / 4));
+    int level0 = 0;
     LearnCtl *lctl = nullptr;
     if (learned) {
         // ---- learned splitters and the multiway pass
@@ -321,157 +342,136 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
         uint32_t *hist = (uint32_t *)(ws + L.hist), *btot = (uint32_t *)(ws + L.btot);
         uint32_t *bstart = (uint32_t *)(ws + L.bstart);
         if (st) HS_HIP(hipEventRecord(lev[2], stream));
-        HS_HIP(hipMemsetAsync(lctl, 0, sizeof(LearnCtl), stream));
+        HS_LAUNCH(k_zero_words, 1, 256, stream, (uint32_t *)lctl, (uint32_t)(sizeof(LearnCtl) / 4));
         // sample draws: the training sample from splitmix64(seed), the
         // held-out sample from splitmix64(seed + 1), the weights from
         // splitmix64(seed + 2)
-        k_ls_sample<F><<<(P.m + 255) / 256, 256, 0, stream>>>(raw, (uint32_t)n, P.seed, P.m, smp);
-        HS_LAUNCHED();
-        k_ls_holdout<F><<<(P.h + 255) / 256, 256, 0, stream>>>(raw, (uint32_t)n, P.seed + 1, P.h, hold);
-        HS_LAUNCHED();
+        HS_LAUNCH(k_ls_sample<F>, (P.m + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed, P.m, smp);
+        HS_LAUNCH(k_ls_holdout<F>, (P.h + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed + 1, P.h, hold);
         const Layout S = make_layout<K>(F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64
                                                                                        : HS_OP_SORT_KV_I32,
                                         P.m, 1, T);
         int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
         if (rc) return rc;
-        k_ls_prep<F><<<1, 1024, 0, stream>>>(smp, P.m, z, y, ssplit, lctl);
-        HS_LAUNCHED();
+        HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl);
         const uint32_t gblk = (P.m + 255) / 256;
         if (P.mode != JUDGE_SAMPLE) {
-            k_mlp_init<<<(MLP_NP + 255) / 256, 256, 0, stream>>>(par, mom, vel, P.seed + 2);
-            HS_LAUNCHED();
+            HS_LAUNCH(k_mlp_init, (MLP_NP + 255) / 256, 256, stream, par, mom, vel, P.seed + 2);
             for (int t = 1; t <= P.steps; ++t) {
                 const bool last = t == P.steps;
-                k_mlp_grad<<<gblk, 256, 0, stream>>>(par, z, y, P.m, part, lossb);
-                HS_LAUNCHED();
-                k_mlp_update<<<MLP_UPDATE_GRID, 256, 0, stream>>>(par, mom, vel, part, gblk, t, P.lr, nullptr,
-                                                                 lossb, last ? lossb + gblk : nullptr, P.m);
-                HS_LAUNCHED();
+                HS_LAUNCH(k_mlp_grad, gblk, 256, stream, par, z, y, P.m, part, lossb);
+                HS_LAUNCH(k_mlp_update, MLP_UPDATE_GRID, 256, stream, par, mom, vel, part, gblk, t, P.lr,
+                          (float *)nullptr, lossb, last ? lossb + gblk : (float *)nullptr, P.m);
             }
-            k_ls_invert<F><<<(NSPLIT * WAVE + 255) / 256, 256, 0, stream>>>(par, lctl, msplit);
-            HS_LAUNCHED();
+            HS_LAUNCH(k_ls_invert<F>, (NSPLIT * WAVE + 255) / 256, 256, stream, par, lctl, msplit);
         }
-        k_ls_judge<K><<<1, 256, 0, stream>>>(msplit, ssplit, hold, P.h, chosen, lctl, P.mode);
-        HS_LAUNCHED();
+        HS_LAUNCH(k_ls_judge<K>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode);
         if (st) HS_HIP(hipEventRecord(lev[3], stream));
         uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
         const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 4 - 1) / ((uint64_t)d->ncu * 4));
         if (chunk < cmin) chunk = cmin;
         chunk = (chunk + MW_TILE - 1) / MW_TILE * MW_TILE;
         const uint32_t G = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
-        k_mw_hist<F, true><<<G, MW_NT, 0, stream>>>(raw, nullptr, (uint32_t)n, chunk, chosen, lctl, hist);
-        HS_LAUNCHED();
-        k_mw_scan_cols<<<NB_MAX, 1024, 0, stream>>>(hist, G, lctl, btot);
-        HS_LAUNCHED();
-        k_mw_scan_starts<<<1, 1024, 0, stream>>>(btot, lctl, bstart);
-        HS_LAUNCHED();
-        k_mw_scatter<F, true, false><<<G, MW_NT, 0, stream>>>(raw, nullptr, (uint32_t)n, chunk, chosen, lctl, hist,
-                                                               bstart, buf[1], Raw{});
-        HS_LAUNCHED();
-        k_mw_route<F><<<(NB_MAX + 255) / 256, 256, 0, stream>>>(ctl, lctl, bstart, chosen, buf[1], SRC_BUF1,
-                                                                segs[0], tasks, T, LEAF, rule, L.cand_cap,
-                                                                L.task_cap);
-        HS_LAUNCHED();
+        HS_LAUNCH((k_mw_hist<F, true>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk, chosen, lctl,
+                  hist);
+        HS_LAUNCH(k_mw_scan_cols, NB_MAX, 1024, stream, hist, G, lctl, btot);
+        HS_LAUNCH(k_mw_scan_starts, 1, 1024, stream, btot, lctl, bstart);
+        HS_LAUNCH((k_mw_scatter<F, true, false>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk,
+                  chosen, lctl, hist, bstart, buf[1], Raw{});
+        // the buckets are in buffer 1, where level 1 reads: they form level 1's list
+        HS_LAUNCH(k_mw_route<F>, (NB_MAX + 255) / 256, 256, stream, ctl, lctl, bstart, chosen, buf[1], SRC_BUF1,
+                  segs[1], curs[1], tasks, T, LEAF, rule, L.cand_cap, L.task_cap);
         if (st) HS_HIP(hipEventRecord(lev[4], stream));
-        k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[0], cur, L.cand_cap);
-        HS_LAUNCHED();
-        level = 1;  // the buckets are in buf[1], where level 1 reads
-        batch = 0;  // read the control block back before the first level
+        level0 = 1;
+    } else if (d_off) {
+        const uint32_t g = (uint32_t)((nseg + 255) / 256);  // one wave per 64 segments
+        HS_LAUNCH(k_init_segmented<F>, g, 256, stream, ctl, segs[0], curs[0], tasks, raw, d_off, (uint32_t)nseg,
+                  (uint32_t)n, T, LEAF, rule, L.cand_cap, L.task_cap);
     } else {
-        if (d_off) {
-            const uint32_t g = (uint32_t)((nseg + 255) / 256);  // one wave per 64 segments
-            k_init_segmented<F><<<g, 256, 0, stream>>>(ctl, segs[0], tasks, raw, d_off, (uint32_t)nseg, (uint32_t)n,
-                                                       T, LEAF, rule, L.cand_cap, L.task_cap);
-        } else {
-            k_init_single<F><<<1, 64, 0, stream>>>(ctl, segs[0], tasks, raw, (uint32_t)n, T, LEAF, L.task_cap, rule,
-                                                   0, K(0));
-        }
-        HS_LAUNCHED();
-        k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[0], cur, L.cand_cap);
-        HS_LAUNCHED();
+        HS_LAUNCH(k_init_single<F>, 1, 64, stream, ctl, segs[0], curs[0], tasks, raw, (uint32_t)n, T, LEAF,
+                  L.task_cap, rule, 0, K(0));
     }
 
-    // Levels are launched in batches with fixed grids (every kernel reads the
-    // level's size from the control block), and the host reads the control
-    // block back once per batch.  A batch covers the levels that the largest
-    // live segment needs with balanced splits, plus one.
-    auto levels_for = [&](uint64_t size) {
-        int l = 1;
-        while (size > T) {
-            size = (size + 1) / 2;
-            ++l;
-        }
-        return l;
-    };
-    // one partition workgroup per resident slot: no partly filled last round
-    int occ = 0;
-    HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_partition<F, false, false>, PartCfg<K>::NT, 0));
-    if (occ < 1) occ = 1;
-    const int part_grid = d->ncu * occ;
-    const int fin_grid = d->ncu * 4;
     int guard = 2;
     for (int64_t x = n; x > 1; x >>= 1) ++guard;  // 2 + log2(n): beyond it, sample-median pivots
-    const int level0 = level;
-    if (!learned) batch = d_off ? 1 : ((uint64_t)n > T ? levels_for((uint64_t)n) : 0);
-    for (;;) {
-        for (int bi = 0; bi < batch && level < LMAX; ++bi, ++level) {
-            const int lrule = level > guard ? PIVOT_SAMPLE : rule;
-            const uint32_t out_id = (uint32_t)((level + 1) & 1);
-            if (st) HS_HIP(hipEventRecord(d->ev[2 * level], stream));
-            if (level == 0)
-                k_partition<F, true, false><<<part_grid, PartCfg<K>::NT, 0, stream>>>(
-                    ctl, segs[cur_list], cur, nullptr, raw, buf[out_id], Raw{}, aligned);
-            else
-                k_partition<F, false, false><<<part_grid, PartCfg<K>::NT, 0, stream>>>(
-                    ctl, segs[cur_list], cur, buf[level & 1], raw, buf[out_id], Raw{},
-                    (F == FMT_KV || aligned) ? 1 : 0);
-            HS_LAUNCHED();
-            if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
-            k_finalize<F><<<fin_grid, 256, 0, stream>>>(ctl, segs[cur_list], cur, segs[1 - cur_list], tasks,
-                                                        buf[out_id], out_id, T, LEAF, lrule, L.cand_cap,
-                                                        L.task_cap);
-            HS_LAUNCHED();
-            cur_list = 1 - cur_list;
-            k_plan<K><<<1, 1024, 0, stream>>>(ctl, segs[cur_list], cur, L.cand_cap);
-            HS_LAUNCHED();
+    int launches = 0;
+    if (!host_driver) {
+        // one persistent launch runs every level (its grid must be resident at once)
+        int occ = 0;
+        HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_levels<F>, PartCfg<K>::NT, 0));
+        if (occ < 1) return fail(HS_EINTERNAL, "the level driver does not fit on a compute unit");
+        if (st) HS_HIP(hipEventRecord(lev[5], stream));
+        HS_LAUNCH(k_levels<F>, d->ncu * occ, PartCfg<K>::NT, stream, ctl, segs[0], segs[1], curs[0], curs[1], buf[0],
+                  buf[1], raw, tasks, T, LEAF, rule, guard, level0, LMAX, L.cand_cap, L.task_cap,
+                  (o && o->spin_limit > 0) ? (uint32_t)o->spin_limit : BARRIER_SPIN_LIMIT);
+        if (st) HS_HIP(hipEventRecord(lev[6], stream));
+    } else {
+        // host-driven levels: batches of fixed-grid launches, one read-back per batch
+        auto levels_for = [&](uint64_t size) {
+            int l = 1;
+            while (size > T) {
+                size = (size + 1) / 2;
+                ++l;
+            }
+            return l;
+        };
+        int occ = 0;
+        HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_partition<F, false, false>, PartCfg<K>::NT, 0));
+        if (occ < 1) occ = 1;
+        const int part_grid = d->ncu * occ;
+        const int fin_grid = d->ncu * 4;
+        int level = level0, batch = 0;
+        for (;;) {
+            for (int bi = 0; bi < batch && level < LMAX; ++bi, ++level) {
+                const int p = level & 1;
+                const int lrule = level > guard ? PIVOT_SAMPLE : rule;
+                HS_LAUNCH(k_level_begin, 1, 64, stream, ctl, p);
+                if (st) HS_HIP(hipEventRecord(d->ev[2 * level], stream));
+                if (level == 0)
+                    HS_LAUNCH((k_partition<F, true, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, segs[p],
+                              curs[p], (const K *)nullptr, raw, buf[1 - p], Raw{}, L.cand_cap);
+                else
+                    HS_LAUNCH((k_partition<F, false, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, segs[p],
+                              curs[p], (const K *)buf[p], raw, buf[1 - p], Raw{}, L.cand_cap);
+                if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
+                HS_LAUNCH(k_finalize<F>, fin_grid, 256, stream, ctl, p, segs[p], curs[p], segs[1 - p], curs[1 - p],
+                          tasks, buf[1 - p], (uint32_t)(1 - p), T, LEAF, lrule, L.cand_cap, L.task_cap);
+                ++launches;
+            }
+            HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+            HS_HIP(hipStreamSynchronize(stream));
+            if (h->err) return fail(HS_EINTERNAL, "partition levels reported error bits 0x%x", h->err);
+            const LevelCounts &lc = h->lev[level & 1];
+            if ((uint32_t)lc.segs_tiles == 0) break;
+            if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
+            batch = levels_for(lc.max_seg);
         }
-        HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-        HS_HIP(hipStreamSynchronize(stream));
-        if (h->err) return fail(HS_EINTERNAL, "partition levels reported error bits 0x%x", h->err);
-        if (h->nseg == 0) break;
-        if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
-        batch = levels_for(h->max_seg);
     }
-    const int64_t launches = level - level0;
-    const uint32_t ntask = h->ntask, nsmall = h->nsmall;
-    if ((uint64_t)ntask + nsmall > L.task_cap) return fail(HS_EINTERNAL, "task list overflow");
-    if (ntask + nsmall > 0) {
+    // on-chip sorts: fixed grids, the task counts are read on the device
+    {
         using LC = LocalCfg<K>;
         if (st) HS_HIP(hipEventRecord(lev[0], stream));
-        if (nsmall > 0) {
-            const uint32_t gs = (nsmall + 3) / 4 < (uint32_t)(d->ncu * 8) ? (nsmall + 3) / 4 : (uint32_t)(d->ncu * 8);
-            k_small<F, LC::LEAF><<<gs, 256, 0, stream>>>(ctl, tasks, buf[0], buf[1], raw, L.task_cap);
-            HS_LAUNCHED();
-        }
-        if (ntask > 0) {
-            const uint32_t gmax = (uint32_t)(d->ncu * LC::WPC);
-            const int g = (int)(ntask < gmax ? ntask : gmax);
-            k_local<F, LC::NT, LC::T, LC::LEAF, LC::WPC>
-                <<<g, LC::NT, 0, stream>>>(ctl, tasks, buf[0], buf[1], raw, local_rule, L.task_cap);
-            HS_LAUNCHED();
-        }
+        HS_LAUNCH((k_small<F, LC::LEAF>), d->ncu * 8, 256, stream, ctl, tasks, buf[0], buf[1], raw, L.task_cap);
+        HS_LAUNCH((k_local<F, LC::NT, LC::T, LC::LEAF, LC::WPC>), d->ncu * LC::WPC, LC::NT, stream, ctl, tasks,
+                  buf[0], buf[1], raw, local_rule, L.task_cap);
         if (st) HS_HIP(hipEventRecord(lev[1], stream));
     }
+    if (capturing) return HS_OK;  // the caller checks the error word (plan entry points)
+    HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    float loss = 0.f;
     if (st) {
-        HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         if (learned) HS_HIP(hipMemcpyAsync(d->h_lctl, lctl, sizeof(LearnCtl), hipMemcpyDeviceToHost, stream));
-        float loss = 0.f;
         if (learned && P.mode != JUDGE_SAMPLE) {
             const uint32_t gblk = (P.m + 255) / 256;
             HS_HIP(hipMemcpyAsync(&loss, (float *)(ws + L.lossb) + gblk, sizeof(float), hipMemcpyDeviceToHost,
                                   stream));
         }
-        HS_HIP(hipStreamSynchronize(stream));
+    }
+    HS_HIP(hipStreamSynchronize(stream));
+    if (h->err) return fail(HS_EINTERNAL, "the sort reported error bits 0x%x", h->err);
+    const uint32_t ntask = h->ntask, nsmall = h->nsmall;
+    if ((uint64_t)ntask + nsmall > L.task_cap) return fail(HS_EINTERNAL, "task list overflow");
+    if (st) {
         std::memset(st, 0, sizeof *st);
         st->passes = h->levels;
         st->keys_partitioned = (int64_t)h->part_keys;
@@ -479,17 +479,22 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
         st->max_depth = h->levels;
         st->bytes_alg = (int64_t)(2 * sizeof(K)) * ((int64_t)h->part_keys + (int64_t)h->local_keys) +
                         (int64_t)sizeof(K) * (int64_t)h->fill_keys;
-        st->partition_launches = launches;
-        for (int64_t l = level0; l < level; ++l) {
+        if (!host_driver) {
+            st->partition_launches = 1;
             float ms = 0.f;
-            HS_HIP(hipEventElapsedTime(&ms, d->ev[2 * l], d->ev[2 * l + 1]));
-            st->partition_ms += ms;
+            HS_HIP(hipEventElapsedTime(&ms, lev[5], lev[6]));
+            st->partition_ms = ms;
+        } else {
+            st->partition_launches = launches;
+            for (int64_t l = level0; l < level0 + launches; ++l) {
+                float ms = 0.f;
+                HS_HIP(hipEventElapsedTime(&ms, d->ev[2 * l], d->ev[2 * l + 1]));
+                st->partition_ms += ms;
+            }
         }
-        if (ntask + nsmall > 0) {
-            float ms = 0.f;
-            HS_HIP(hipEventElapsedTime(&ms, lev[0], lev[1]));
-            st->local_ms = ms;
-        }
+        float ms = 0.f;
+        HS_HIP(hipEventElapsedTime(&ms, lev[0], lev[1]));
+        st->local_ms = ms;
         if (learned) {
             const LearnCtl &lc = *d->h_lctl;
             // the multiway pass reads the keys twice and writes them once
@@ -500,13 +505,11 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
             st->sample_imbalance = lc.sample_imb;
             st->bucket_imbalance = lc.use_model ? lc.model_imb : lc.sample_imb;
             st->final_loss = loss;
-            float ms = 0.f;
             HS_HIP(hipEventElapsedTime(&ms, lev[2], lev[3]));
             st->learn_ms = ms;
             HS_HIP(hipEventElapsedTime(&ms, lev[3], lev[4]));
             st->multiway_ms = ms;
         }
-        if (h->err) return fail(HS_EINTERNAL, "error bits 0x%x", h->err);
     }
     return HS_OK;
 }
@@ -645,27 +648,22 @@ int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_l
     if (shared_ws) HS_HIP(hipStreamWaitEvent(s, d->last, 0));
     int32_t *copy = (int32_t *)(ws + L.buf1);
     Seg<uint32_t> *segs = (Seg<uint32_t> *)(ws + L.segA);
-    unsigned long long *cur = (unsigned long long *)(ws + L.cur);
+    unsigned long long *cur = (unsigned long long *)(ws + L.curA);
     Task<uint32_t> *tasks = (Task<uint32_t> *)(ws + L.tasks);
     Ctl *ctl = (Ctl *)(ws + L.ctl);
     // The pass is out of place: stage the input in the workspace, then
     // partition it back into the caller's array.
     HS_HIP(hipMemcpyAsync(copy, keys, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
-    HS_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
+    HS_LAUNCH(k_zero_words, zero_grid(sizeof(Ctl)), 256, s, (uint32_t *)ctl, (uint32_t)(sizeof(Ctl) / 4));
     const uint32_t upiv = (uint32_t)pivot ^ 0x80000000u;
-    k_init_single<FMT_I32><<<1, 64, 0, s>>>(ctl, segs, tasks, Raw{copy, nullptr}, (uint32_t)n, 0, 0, L.task_cap,
-                                            PIVOT_MEDIAN3, 1, upiv);
-    HS_LAUNCHED();
-    k_plan<uint32_t><<<1, 1024, 0, s>>>(ctl, segs, cur, L.cand_cap);
-    HS_LAUNCHED();
+    HS_LAUNCH(k_init_single<FMT_I32>, 1, 64, s, ctl, segs, cur, tasks, Raw{copy, nullptr}, (uint32_t)n, 0u, 0u,
+              L.task_cap, PIVOT_MEDIAN3, 1, upiv);
     const uint32_t ntiles = seg_tiles<uint32_t>(0, (uint32_t)n);
     const uint32_t maxg = (uint32_t)d->ncu * 8;
     const int g = (int)(ntiles < maxg ? ntiles : maxg);
-    k_partition<FMT_I32, true, true><<<g, PartCfg<uint32_t>::NT, 0, s>>>(
-        ctl, segs, cur, nullptr, Raw{copy, nullptr}, nullptr, Raw{keys, nullptr}, 1);
-    HS_LAUNCHED();
-    k_write_count<<<1, 64, 0, s>>>(cur, d_count_le);
-    HS_LAUNCHED();
+    HS_LAUNCH((k_partition<FMT_I32, true, true>), g, PartCfg<uint32_t>::NT, s, ctl, 0, segs, cur,
+              (const uint32_t *)nullptr, Raw{copy, nullptr}, (uint32_t *)nullptr, Raw{keys, nullptr}, L.cand_cap);
+    HS_LAUNCH(k_write_count, 1, 64, s, cur, d_count_le);
     if (shared_ws) HS_HIP(hipEventRecord(d->last, s));
     return HS_OK;
 }

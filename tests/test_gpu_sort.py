@@ -235,3 +235,67 @@ def test_full_size_kv(hs):
     vo = v.cpu().numpy()
     assert np.all(ko[:-1] <= ko[1:])
     kv_index_check(keys, ko, vo)
+
+
+# ------------------------------------------------------------- level drivers
+
+def _driver_opts(hs, driver, local_T=0, pivot=0):
+    o = hs.Opts()
+    o.driver = driver
+    o.local_T = local_T
+    o.pivot_rule = pivot
+    return o
+
+
+@pytest.mark.parametrize("driver", [2, 1], ids=["persistent", "host"])
+def test_drivers_bit_exact(hs, oracle_mod, driver):
+    """Both level drivers against the oracle: many levels (small on-chip
+    limit), equal-key runs, key/value pairs, f64 and segmented inputs."""
+    a = workloads.uniform_i32(1 << 20, seed=1)
+    t = _gpu(a)
+    hs.sort_(t, opts=_driver_opts(hs, driver))
+    assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_i32(a))
+    for name, x in _adversarial(300001, 9).items():
+        t = _gpu(x)
+        hs.sort_(t, opts=_driver_opts(hs, driver, local_T=600, pivot=1))
+        assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_i32(x)), name
+    x = workloads.f64(700001, "normal", seed=5)
+    t = _gpu(x)
+    st = hs.sort_(t, opts=_driver_opts(hs, driver, local_T=1024), stats=True)
+    assert np.array_equal(t.cpu().numpy().view(np.uint64), oracle_mod.sort_f64(x).view(np.uint64))
+    assert st["passes"] >= 9
+    # the host driver launches levels in batches (trailing empty levels included)
+    assert st["partition_launches"] == 1 if driver == 2 else st["partition_launches"] >= st["passes"]
+    keys, vals = workloads.kv_dup_i32(500003, seed=6, ndistinct=1000)
+    k, v = _gpu(keys), _gpu(vals)
+    hs.sort_kv_(k, v, opts=_driver_opts(hs, driver, local_T=2048))
+    ko, vo = k.cpu().numpy(), v.cpu().numpy()
+    ok, _ = oracle_mod.sort_kv_i32(keys, vals)
+    assert np.array_equal(ko, ok)
+    kv_index_check(keys, ko, vo)
+    off = workloads.segment_offsets(300, 1, 200000, seed=8)
+    keys = workloads.uniform_i32(int(off[-1]), seed=9)
+    t, o = _gpu(keys), _gpu(off.astype(np.int64))
+    hs.sort_segmented_(t, o, opts=_driver_opts(hs, driver, local_T=4096))
+    assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
+
+
+def test_persistent_driver_barrier_timeout_is_reported(hs):
+    """A grid-barrier wait capped at one poll (forced from the host) ends the
+    level driver with an error instead of waiting: the call fails cleanly and
+    the library keeps working."""
+    x = workloads.f64(1 << 22, "uniform", seed=10)
+    o = _driver_opts(hs, 2)
+    o.spin_limit = 1
+    failed = 0
+    for _ in range(3):  # a one-poll wait fails unless every workgroup arrives at once
+        t = _gpu(x)
+        try:
+            hs.sort_(t, opts=o)
+        except hs.HSortError as e:
+            assert "0x" in str(e)
+            failed += 1
+    assert failed >= 1
+    t = _gpu(x)
+    hs.sort_(t)
+    assert np.array_equal(t.cpu().numpy(), np.sort(x))
