@@ -110,11 +110,13 @@ class Case:
             self.vwork.copy_(self.vsrc)
 
     def sort(self, hs, opts=None):
+        if getattr(self, "plan", None) is not None:
+            return self.plan.run()
         if self.kind in ("f64", "i32"):
             return hs.sort_(self.work, opts=opts, stats=True)
         if self.kind == "kv":
-            return hs.sort_kv_(self.work, self.vwork, stats=True)
-        return hs.sort_segmented_(self.work, self.off, stats=True)
+            return hs.sort_kv_(self.work, self.vwork, opts=opts, stats=True)
+        return hs.sort_segmented_(self.work, self.off, opts=opts, stats=True)
 
 
 def run_gpu(name, steps, warmup, driver=0):
@@ -129,6 +131,22 @@ def run_gpu(name, steps, warmup, driver=0):
     opts = hs.learned_opts(seed=100, flags=LEARNED[name]) if name in LEARNED else hs.Opts()
     opts.driver = driver
     learn = {d: [] for d in dists} if name in LEARNED else None
+    graph = None
+    if CONFIGS[name][0] == "seg":
+        # batched segmented sort: autotuned knobs, one graph replay per sort
+        c = cases[0]
+        c.restore()
+        base = hs.Opts()
+        base.driver = hs.DRIVER_PERSISTENT
+        t0 = time.perf_counter()
+        tuned, report = hs.autotune(c.work, offsets=c.off, opts=base)
+        tune_s = time.perf_counter() - t0
+        # stats of one eager sort with the tuned knobs (the graph cannot read them back)
+        c.restore()
+        seg_stats = c.sort(hs, tuned)
+        c.plan = hs.Plan(c.work, offsets=c.off, opts=tuned)
+        graph = dict(tune_report=report, tune_s=round(tune_s, 2),
+                     knobs=dict(local_T=tuned.local_T, leaf=tuned.leaf, pivot_rule=tuned.pivot_rule))
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -147,6 +165,9 @@ def run_gpu(name, steps, warmup, driver=0):
             ev1.record()
             ev1.synchronize()
             ms_step += ev0.elapsed_time(ev1)
+            if graph is not None:
+                c.plan.check()
+                st = seg_stats
             if timed and learn is not None:
                 learn[dist].append(dict(ms=ev0.elapsed_time(ev1), learn_ms=st["learn_ms"],
                                         multiway_ms=st["multiway_ms"], fallback_used=st["fallback_used"],
@@ -185,6 +206,7 @@ def run_gpu(name, steps, warmup, driver=0):
         elem_bytes=s,
         learned=None if learn is None else {
             d: {k: round(sum(r[k] for r in v) / len(v), 4) for k in v[0]} for d, v in learn.items()},
+        graph=graph,
     )
 
 
@@ -272,6 +294,8 @@ def main():
                          "workload": CONFIGS[nm][4]}
             if e["learned"]:
                 extra[nm]["per_distribution"] = e["learned"]
+            if e["graph"]:
+                extra[nm]["graph"] = e["graph"]
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.config)

@@ -112,7 +112,8 @@ typedef struct hs_stats {
  * tuned default. */
 typedef struct hs_opts {
     int32_t pivot_rule;   /* HS_PIVOT_* */
-    int32_t local_T;      /* on-chip segment limit; a power of two <= the type's maximum */
+    int32_t local_T;      /* on-chip segment limit in keys (ranges up to it are sorted on chip; larger ones
+                           * are partitioned again); capped at 8192 */
     int32_t method;       /* HS_METHOD_* */
     int32_t learn_flags;  /* HS_LEARN_* */
     int32_t train_steps;  /* learned method: Adam steps (default 300) */
@@ -121,6 +122,10 @@ typedef struct hs_opts {
     int32_t driver;       /* HS_DRIVER_*: how the partition levels are driven */
     int32_t spin_limit;   /* testing: cap on the polls of one grid-barrier wait (0: about 4M); a wait that
                            * runs out fails the call with HS_EINTERNAL */
+    int32_t leaf;         /* largest range one wave sorts with the bitonic network alone: 64, 128, 256 or
+                           * 512 (default 512); larger ranges go to the workgroup on-chip sort */
+    int32_t autotune;     /* 1: use (or first measure and remember) the tuned knobs for this operation and
+                           * size class; see hs_autotune */
     int32_t reserved;
     uint64_t seed;        /* learned method: seed of the sample draws and the initial weights */
     void *workspace;      /* caller-owned device scratch, or NULL */
@@ -201,6 +206,48 @@ HS_API int hs_mlp_train_f32(const float *d_z, const float *d_y, int64_t m, int32
  * (d_start[2k+1] = n).  The order inside a bucket is unspecified. */
 HS_API int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_splitters, int32_t k,
                                      uint32_t *d_start, void *stream);
+
+/* ---- Plans: one call captured into a HIP graph ------------------------
+ *
+ * hs_plan_create records one sort of the given buffers (op HS_OP_SORT_I32,
+ * _F64, _KV_I32 or _SORT_SEGMENTED_I32; vals only for key/value, d_offsets
+ * and nseg only for segmented) into a graph: the partition levels run in the
+ * persistent driver, every clear is a kernel, and the plan owns its
+ * workspace, so replaying it needs no host work beyond hipGraphLaunch.
+ * Each hs_plan_exec sorts whatever the buffers hold at that moment.  Replays
+ * of one plan must not overlap (they share its workspace).  With
+ * opts->autotune set, the knobs are tuned first (hs_autotune, persistent
+ * driver).  The call synchronizes the device while creating the plan. */
+typedef struct hs_plan hs_plan;
+HS_API int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_offsets, int64_t nseg,
+                          const hs_opts *opts, hs_plan **plan);
+HS_API int hs_plan_exec(hs_plan *plan, void *stream);
+/* Waits for the plan's last replay on `stream` and reports the error word
+ * its kernels left (HS_EINTERNAL if set). */
+HS_API int hs_plan_check(hs_plan *plan, void *stream);
+HS_API void hs_plan_destroy(hs_plan *plan);
+
+/* ---- Autotuner ---------------------------------------------------------
+ *
+ * Measures the sort of the given input (left unchanged: the tuner sorts a
+ * copy) under every combination of on-chip limit local_T (2048, 4096, 8192),
+ * one-wave bitonic bound leaf (128, 256, 512) and global pivot rule
+ * (ninther, sample median of 64), for the driver base->driver selects, with
+ * HIP events (one warm-up and two timed runs each, fastest kept).  Every
+ * candidate's output is compared on the device with the first candidate's:
+ * all must be identical.  The best knobs go to *best (a copy of base with
+ * them filled in) and are remembered per device, operation, driver and size
+ * class (n and nseg rounded up to powers of two); a later call or a sort with
+ * opts->autotune set reuses them.  Allocates a copy of the input. */
+typedef struct hs_tune_report {
+    int32_t candidates;      /* configurations measured (0: taken from the cache) */
+    int32_t outputs_equal;   /* 1 if every candidate produced the same bytes */
+    double best_ms;          /* fastest sort */
+    double default_ms;       /* the sort with the default knobs */
+    int32_t local_T, leaf, pivot_rule, reserved;
+} hs_tune_report;
+HS_API int hs_autotune(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_offsets, int64_t nseg,
+                       const hs_opts *base, hs_opts *best, hs_tune_report *report, void *stream);
 
 /* Bytes of workspace that operation `op` needs for n keys (and nseg
  * segments) with the given options. */

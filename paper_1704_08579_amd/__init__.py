@@ -62,7 +62,8 @@ class Opts(ctypes.Structure):
                 ("method", ctypes.c_int32), ("learn_flags", ctypes.c_int32),
                 ("train_steps", ctypes.c_int32), ("sample_log2", ctypes.c_int32),
                 ("learning_rate", ctypes.c_float), ("driver", ctypes.c_int32),
-                ("spin_limit", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("spin_limit", ctypes.c_int32), ("leaf", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
@@ -83,6 +84,11 @@ _SIGS = {
     "hs_mlp_train_f32": ([_P, _P, _I64, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64, _P, _P, _P],
                          ctypes.c_int),
     "hs_multiway_partition_f64": ([_P, _I64, _P, ctypes.c_int32, _P, _P], ctypes.c_int),
+    "hs_plan_create": ([ctypes.c_int, _P, _P, _I64, _P, _I64, _P, _P], ctypes.c_int),
+    "hs_plan_exec": ([_P, _P], ctypes.c_int),
+    "hs_plan_check": ([_P, _P], ctypes.c_int),
+    "hs_plan_destroy": ([_P], None),
+    "hs_autotune": ([ctypes.c_int, _P, _P, _I64, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
     "hs_last_error": ([], ctypes.c_char_p),
     "hs_version": ([], ctypes.c_int),
 }
@@ -266,3 +272,84 @@ def multiway_partition_(keys, splitters):
         _check(lib().hs_multiway_partition_f64(keys.data_ptr(), keys.numel(), splitters.data_ptr(), k,
                                                starts.data_ptr(), _stream_handle(keys)))
     return starts
+
+
+# ---------------------------------------------------------------- plans and the autotuner
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("outputs_equal", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("local_T", ctypes.c_int32), ("leaf", ctypes.c_int32), ("pivot_rule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+def _sort_args(keys, vals=None, offsets=None):
+    """(op, keys ptr, vals ptr, n, offsets ptr, nseg) of a sort over tensors."""
+    torch = _torch()
+    if offsets is not None:
+        _require(keys, (torch.int32,), "keys")
+        _require(offsets, (torch.int64,), "offsets")
+        return OP_SORT_SEGMENTED_I32, keys.data_ptr(), None, keys.numel(), offsets.data_ptr(), offsets.numel() - 1
+    if vals is not None:
+        _require(keys, (torch.int32,), "keys")
+        _require(vals, (torch.int32,), "vals")
+        if keys.numel() != vals.numel() or keys.device != vals.device:
+            raise ValueError("keys and vals must have the same size and device")
+        return OP_SORT_KV_I32, keys.data_ptr(), vals.data_ptr(), keys.numel(), None, 0
+    _require(keys, (torch.int32, torch.float64), "keys")
+    op = OP_SORT_I32 if keys.dtype == torch.int32 else OP_SORT_F64
+    return op, keys.data_ptr(), None, keys.numel(), None, 0
+
+
+class Plan:
+    """One sort of fixed tensors captured into a HIP graph (hs_plan_*).
+
+    ``run()`` replays it on the current stream: it sorts whatever the tensors
+    hold at that moment.  The tensors are kept alive by the plan."""
+
+    def __init__(self, keys, vals=None, offsets=None, opts: Opts | None = None):
+        torch = _torch()
+        self._tensors = (keys, vals, offsets)
+        op, kp, vp, n, op_off, nseg = _sort_args(keys, vals, offsets)
+        self._plan = ctypes.c_void_p()
+        self.device = keys.device
+        with torch.cuda.device(keys.device):
+            _check(lib().hs_plan_create(op, kp, vp, n, op_off, nseg, _opts_ptr(opts), ctypes.byref(self._plan)))
+
+    def run(self):
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            _check(lib().hs_plan_exec(self._plan, torch.cuda.current_stream(self.device).cuda_stream))
+        return self
+
+    def check(self):
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            _check(lib().hs_plan_check(self._plan, torch.cuda.current_stream(self.device).cuda_stream))
+
+    def close(self):
+        if getattr(self, "_plan", None) and self._plan.value:
+            lib().hs_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(keys, vals=None, offsets=None, opts: Opts | None = None):
+    """Tune the knobs for this sort (the tensors are left unchanged); returns
+    (tuned Opts, report dict)."""
+    torch = _torch()
+    op, kp, vp, n, op_off, nseg = _sort_args(keys, vals, offsets)
+    best = Opts()
+    rep = TuneReport()
+    with torch.cuda.device(keys.device):
+        _check(lib().hs_autotune(op, kp, vp, n, op_off, nseg, _opts_ptr(opts), ctypes.byref(best), ctypes.byref(rep),
+                                 _stream_handle(keys)))
+    return best, rep.as_dict()

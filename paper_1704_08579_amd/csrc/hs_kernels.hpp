@@ -863,6 +863,17 @@ __global__ void k_zero_words(uint32_t *p, uint32_t nwords)
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+// Number of 32-bit words where a and b differ, added to *count (one atomic
+// per wave).
+__global__ void k_count_diff(const uint32_t *a, const uint32_t *b, uint64_t nwords, unsigned long long *count)
+{
+    unsigned long long d = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += (uint64_t)gridDim.x * blockDim.x)
+        d += a[i] != b[i];
+    d = wave_sum64(d);
+    if (lane_id() == 0 && d) atomicAdd(count, d);
+}
+
 // Count of the <= side after a single-segment pass (partition entry point).
 __global__ void k_write_count(const unsigned long long *cur, int64_t *d_count)
 {

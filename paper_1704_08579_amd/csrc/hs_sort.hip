@@ -8,8 +8,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "hs_kernels.hpp"
 #include "hs_learned.hpp"
@@ -215,12 +218,24 @@ template <typename K> uint32_t local_limit(const hs_opts *o)
 
 int pivot_rule(const hs_opts *o) { return (o && o->pivot_rule > 0) ? o->pivot_rule : PIVOT_SAMPLE; }
 
+// The largest task one wave sorts alone (routing bound of the task lists).
+template <typename K> uint32_t leaf_limit(const hs_opts *o)
+{
+    const uint32_t Lmax = (uint32_t)LocalCfg<K>::LEAF;
+    if (!o || o->leaf <= 0) return Lmax;
+    return (uint32_t)o->leaf < Lmax ? (uint32_t)o->leaf : Lmax;
+}
+
 int check_learn(const hs_opts *o)
 {
     if (!o) return HS_OK;
     if (o->driver != HS_DRIVER_AUTO && o->driver != HS_DRIVER_PERSISTENT && o->driver != HS_DRIVER_HOST)
         return fail(HS_EINVAL, "unknown driver %d", o->driver);
     if (o->spin_limit < 0) return fail(HS_EINVAL, "spin_limit is negative");
+    if (o->leaf != 0 && o->leaf != 64 && o->leaf != 128 && o->leaf != 256 && o->leaf != 512)
+        return fail(HS_EINVAL, "leaf = %d is not 64, 128, 256 or 512", o->leaf);
+    if (o->local_T < 0) return fail(HS_EINVAL, "local_T = %d is negative", o->local_T);
+    if (o->autotune != 0 && o->autotune != 1) return fail(HS_EINVAL, "autotune = %d is not 0 or 1", o->autotune);
     if (o->method != HS_METHOD_PLAIN && o->method != HS_METHOD_LEARNED)
         return fail(HS_EINVAL, "unknown method %d", o->method);
     if (o->method == HS_METHOD_LEARNED) {
@@ -305,7 +320,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
 {
     using K = typename KeyOf<F>::type;
     const uint32_t T = local_limit<K>(o);
-    const uint32_t LEAF = (uint32_t)LocalCfg<K>::LEAF;
+    const uint32_t LEAF = leaf_limit<K>(o);
     const int rule = pivot_rule(o);
     const int local_rule = (o && o->pivot_rule > 0) ? o->pivot_rule : PIVOT_NINTHER;
     const bool learned = P.on && (uint64_t)n > T;
@@ -515,8 +530,8 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
 }
 
 template <int F>
-int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
-             hs_stats *st, hipStream_t stream)
+int run_sort_tuned(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
+                   hs_stats *st, hipStream_t stream)
 {
     const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
                          : (F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : HS_OP_SORT_KV_I32);
@@ -535,6 +550,172 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
     return rc;
 }
 
+// ---------------------------------------------------------------- autotuner
+
+int ceil_log2(int64_t x)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < x) ++l;
+    return l;
+}
+
+using TuneKey = std::tuple<int, int, int, int, int>;  // device, op, driver, log2 n, log2 (nseg + 1)
+std::map<TuneKey, std::tuple<int, int, int>> g_tuned;  // -> local_T, leaf, pivot_rule
+std::mutex g_tune_mu;
+
+int tuned_driver(const hs_opts *o) { return (!o || o->driver == HS_DRIVER_AUTO) ? HS_DRIVER_HOST : o->driver; }
+
+TuneKey tune_key(int op, const hs_opts *o, int64_t n, int64_t nseg)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return TuneKey{dev, op, tuned_driver(o), ceil_log2(n), ceil_log2(nseg + 1)};
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Measure every candidate on a copy of the input (see hs_autotune).
+template <int F>
+int autotune_impl(DevState *d, int op, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *base,
+                  hs_opts *best, hs_tune_report *rep, hipStream_t s)
+{
+    using K = typename KeyOf<F>::type;
+    hs_opts b{};
+    if (base) b = *base;
+    b.autotune = 0;
+    b.driver = tuned_driver(base);
+    b.workspace = nullptr;
+    b.workspace_bytes = 0;
+    hs_tune_report r{};
+    const TuneKey key = tune_key(op, &b, n, nseg);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            *best = b;
+            std::tie(best->local_T, best->leaf, best->pivot_rule) = it->second;
+            r.candidates = 0;
+            r.outputs_equal = 1;
+            r.local_T = best->local_T;
+            r.leaf = best->leaf;
+            r.pivot_rule = best->pivot_rule;
+            if (rep) *rep = r;
+            return HS_OK;
+        }
+    }
+    const size_t kb = (size_t)n * (F == FMT_F64 ? 8 : 4), vb = F == FMT_KV ? (size_t)n * 4 : 0;
+    DevBuf src, work, ref, cnt;
+    auto alloc = [&](DevBuf &x, size_t bytes) -> int {
+        if (hipMalloc(&x.p, bytes ? bytes : 8) != hipSuccess) {
+            (void)hipGetLastError();
+            x.p = nullptr;
+            return fail(HS_ENOMEM, "autotune: hipMalloc of %zu bytes failed", bytes);
+        }
+        return HS_OK;
+    };
+    int rc;
+    if ((rc = alloc(src, kb + vb)) || (rc = alloc(work, kb + vb)) || (rc = alloc(ref, kb + vb)) || (rc = alloc(cnt, 8)))
+        return rc;
+    HS_HIP(hipMemcpyAsync(src.p, raw.keys, kb, hipMemcpyDeviceToDevice, s));
+    if (vb) HS_HIP(hipMemcpyAsync((char *)src.p + kb, raw.vals, vb, hipMemcpyDeviceToDevice, s));
+    EventPair ev;
+    HS_HIP(hipEventCreate(&ev.a));
+    HS_HIP(hipEventCreate(&ev.b));
+    const Raw wr{work.p, vb ? (int32_t *)((char *)work.p + kb) : nullptr};
+    const uint32_t Tmax = (uint32_t)LocalCfg<K>::T;
+    std::vector<std::tuple<int, int, int>> cands;
+    cands.emplace_back((int)Tmax, (int)LocalCfg<K>::LEAF, PIVOT_SAMPLE);  // the defaults first: the reference output
+    for (int T : {2048, 4096, 8192})
+        for (int leaf : {128, 256, 512})
+            for (int piv : {PIVOT_NINTHER, PIVOT_SAMPLE}) {
+                if ((uint32_t)T > Tmax) continue;
+                auto c = std::make_tuple(T, leaf, piv);
+                if (c != cands[0]) cands.push_back(c);
+            }
+    double best_ms = 1e30;
+    std::tuple<int, int, int> best_c = cands[0];
+    bool equal = true;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        hs_opts c = b;
+        std::tie(c.local_T, c.leaf, c.pivot_rule) = cands[ci];
+        double ms_min = 1e30;
+        for (int k = 0; k < 3; ++k) {  // one warm-up, two timed
+            HS_HIP(hipMemcpyAsync(work.p, src.p, kb + vb, hipMemcpyDeviceToDevice, s));
+            HS_HIP(hipEventRecord(ev.a, s));
+            if ((rc = run_sort_tuned<F>(d, wr, n, d_off, nseg, &c, nullptr, s))) return rc;
+            HS_HIP(hipEventRecord(ev.b, s));
+            HS_HIP(hipEventSynchronize(ev.b));
+            float ms = 0.f;
+            HS_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+            if (k > 0 && ms < ms_min) ms_min = ms;
+        }
+        if (ci == 0) {
+            r.default_ms = ms_min;
+            HS_HIP(hipMemcpyAsync(ref.p, work.p, kb + vb, hipMemcpyDeviceToDevice, s));
+        } else {
+            // compare the output with the reference on the device
+            HS_LAUNCH(k_zero_words, 1, 64, s, (uint32_t *)cnt.p, 2u);
+            const uint64_t words = (kb + vb) / 4;
+            const uint64_t g64 = (words + 255) / 256;
+            HS_LAUNCH(k_count_diff, (uint32_t)(g64 < 4096 ? (g64 ? g64 : 1) : 4096), 256, s, (const uint32_t *)work.p,
+                      (const uint32_t *)ref.p, words, (unsigned long long *)cnt.p);
+            unsigned long long diff = 0;
+            HS_HIP(hipMemcpyAsync(&diff, cnt.p, 8, hipMemcpyDeviceToHost, s));
+            HS_HIP(hipStreamSynchronize(s));
+            if (diff) equal = false;
+        }
+        if (ms_min < best_ms) {
+            best_ms = ms_min;
+            best_c = cands[ci];
+        }
+    }
+    r.candidates = (int32_t)cands.size();
+    r.outputs_equal = equal ? 1 : 0;
+    r.best_ms = best_ms;
+    std::tie(r.local_T, r.leaf, r.pivot_rule) = best_c;
+    *best = b;
+    std::tie(best->local_T, best->leaf, best->pivot_rule) = best_c;
+    if (rep) *rep = r;
+    if (!equal) return fail(HS_EINTERNAL, "autotune: candidate configurations produced different outputs");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best_c;
+    return HS_OK;
+}
+
+template <int F>
+int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
+             hs_stats *st, hipStream_t stream)
+{
+    if (o && o->autotune) {
+        int rc = check_learn(o);
+        if (rc) return rc;
+        const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
+                             : (F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : HS_OP_SORT_KV_I32);
+        hs_opts tuned;
+        if ((rc = autotune_impl<F>(d, op, raw, n, d_off, nseg, o, &tuned, nullptr, stream))) return rc;
+        tuned.workspace = o->workspace;
+        tuned.workspace_bytes = o->workspace_bytes;
+        tuned.driver = o->driver;
+        return run_sort_tuned<F>(d, raw, n, d_off, nseg, &tuned, st, stream);
+    }
+    return run_sort_tuned<F>(d, raw, n, d_off, nseg, o, st, stream);
+}
+
 int check_n(int64_t n)
 {
     if (n < 0) return fail(HS_EINVAL, "n = %lld is negative", (long long)n);
@@ -546,6 +727,72 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb)
 {
     const char *x = (const char *)a, *y = (const char *)b;
     return x < y + nb && y < x + na;
+}
+
+// Argument checks shared by the plan and autotune entry points: a sort
+// operation over keys (and vals / offsets as the operation needs).
+int check_sort_args(int op, const void *keys, const int32_t *vals, int64_t n, const int64_t *d_off, int64_t nseg)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    switch (op) {
+    case HS_OP_SORT_I32:
+    case HS_OP_SORT_F64:
+        break;
+    case HS_OP_SORT_KV_I32:
+        if (n > 0 && !vals) return fail(HS_EINVAL, "vals is NULL");
+        if (n > 0 && overlap(keys, (size_t)n * 4, vals, (size_t)n * 4)) return fail(HS_EINVAL, "keys and vals overlap");
+        break;
+    case HS_OP_SORT_SEGMENTED_I32:
+        if (nseg < 0 || nseg >= ((int64_t)1 << 31)) return fail(HS_EINVAL, "nseg = %lld out of range", (long long)nseg);
+        if (nseg > 0 && !d_off) return fail(HS_EINVAL, "d_offsets is NULL");
+        break;
+    default:
+        return fail(HS_EINVAL, "op %d is not a sort", op);
+    }
+    if (n > 0 && !keys) return fail(HS_EINVAL, "keys is NULL");
+    return HS_OK;
+}
+
+// Call fn with the key format of a sort operation as a template argument.
+template <typename Fn> int with_format(int op, Fn &&fn)
+{
+    switch (op) {
+    case HS_OP_SORT_I32:
+    case HS_OP_SORT_SEGMENTED_I32:
+        return fn(std::integral_constant<int, FMT_I32>());
+    case HS_OP_SORT_F64:
+        return fn(std::integral_constant<int, FMT_F64>());
+    case HS_OP_SORT_KV_I32:
+        return fn(std::integral_constant<int, FMT_KV>());
+    default:
+        return fail(HS_EINVAL, "op %d is not a sort", op);
+    }
+}
+
+}  // namespace
+
+struct hs_plan {
+    int device = 0;
+    void *ws = nullptr;
+    size_t ctl_off = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Ctl *h_ctl = nullptr;
+};
+
+namespace {
+
+void plan_release(hs_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->h_ctl) (void)hipHostFree(p->h_ctl);
+    delete p;
 }
 
 }  // namespace
@@ -831,6 +1078,131 @@ int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_splitte
     }
     HS_HIP(hipEventRecord(d->last, s));
     return HS_OK;
+}
+
+// ---- plans and the autotuner
+
+int hs_autotune(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_offsets, int64_t nseg,
+                const hs_opts *base, hs_opts *best, hs_tune_report *report, void *stream)
+{
+    if (!best) return fail(HS_EINVAL, "best is NULL");
+    int rc = check_sort_args(op, keys, vals, n, d_offsets, nseg);
+    if (rc) return rc;
+    if ((rc = check_learn(base))) return rc;
+    if (n < 2 || (op == HS_OP_SORT_SEGMENTED_I32 && nseg == 0)) {
+        *best = base ? *base : hs_opts{};
+        best->autotune = 0;
+        if (report) *report = hs_tune_report{};
+        return HS_OK;
+    }
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    const int64_t *off = op == HS_OP_SORT_SEGMENTED_I32 ? d_offsets : nullptr;
+    return with_format(op, [&](auto fmt) {
+        return autotune_impl<decltype(fmt)::value>(d, op, Raw{keys, vals}, n, off, nseg, base, best, report,
+                                                   (hipStream_t)stream);
+    });
+}
+
+int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_offsets, int64_t nseg,
+                   const hs_opts *opts, hs_plan **plan)
+{
+    if (!plan) return fail(HS_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    int rc = check_sort_args(op, keys, vals, n, d_offsets, nseg);
+    if (rc) return rc;
+    if ((rc = check_learn(opts))) return rc;
+    if (opts && opts->driver == HS_DRIVER_HOST)
+        return fail(HS_EINVAL, "a plan runs the persistent level driver; HS_DRIVER_HOST cannot be captured");
+    if (opts && opts->workspace) return fail(HS_EINVAL, "a plan owns its workspace; pass none");
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    hs_plan *p = new hs_plan();
+    HS_HIP(hipGetDevice(&p->device));
+    if (n < 2 || (op == HS_OP_SORT_SEGMENTED_I32 && nseg == 0)) {  // nothing to sort: an empty plan
+        *plan = p;
+        return HS_OK;
+    }
+    const int64_t *off = op == HS_OP_SORT_SEGMENTED_I32 ? d_offsets : nullptr;
+    hs_opts o = opts ? *opts : hs_opts{};
+    o.driver = HS_DRIVER_PERSISTENT;
+    if (o.autotune) {
+        hs_opts tuned;
+        rc = with_format(op, [&](auto fmt) {
+            return autotune_impl<decltype(fmt)::value>(d, op, Raw{keys, vals}, n, off, nseg, &o, &tuned, nullptr,
+                                                       nullptr);
+        });
+        if (rc) {
+            plan_release(p);
+            return rc;
+        }
+        o = tuned;
+        o.autotune = 0;
+        o.driver = HS_DRIVER_PERSISTENT;
+    }
+    Layout L;
+    if ((rc = layout_for(op, n, nseg, &o, &L))) {
+        plan_release(p);
+        return rc;
+    }
+    if (hipMalloc(&p->ws, L.total) != hipSuccess) {
+        (void)hipGetLastError();
+        p->ws = nullptr;
+        plan_release(p);
+        return fail(HS_ENOMEM, "hipMalloc of %zu plan workspace bytes failed", L.total);
+    }
+    o.workspace = p->ws;
+    o.workspace_bytes = L.total;
+    p->ctl_off = L.ctl;
+    if (hipHostMalloc((void **)&p->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+        plan_release(p);
+        return fail(HS_EHIP, "plan set-up failed");
+    }
+    HS_HIP(hipDeviceSynchronize());  // the autotuner's work and the workspace are ready
+    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        plan_release(p);
+        return fail(HS_EHIP, "hipStreamBeginCapture failed");
+    }
+    rc = with_format(op, [&](auto fmt) {
+        return run_sort_tuned<decltype(fmt)::value>(d, Raw{keys, vals}, n, off, nseg, &o, nullptr, p->cap);
+    });
+    const hipError_t ec = hipStreamEndCapture(p->cap, &p->graph);
+    if (rc == HS_OK && ec != hipSuccess) rc = fail(HS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    if (rc == HS_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(HS_EHIP, "hipGraphInstantiate failed");
+    if (rc) {
+        (void)hipGetLastError();
+        plan_release(p);
+        return rc;
+    }
+    *plan = p;
+    return HS_OK;
+}
+
+int hs_plan_exec(hs_plan *plan, void *stream)
+{
+    if (!plan) return fail(HS_EINVAL, "plan is NULL");
+    if (!plan->exec) return HS_OK;
+    HS_HIP(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    return HS_OK;
+}
+
+int hs_plan_check(hs_plan *plan, void *stream)
+{
+    if (!plan) return fail(HS_EINVAL, "plan is NULL");
+    if (!plan->exec) return HS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HS_HIP(hipMemcpyAsync(plan->h_ctl, (char *)plan->ws + plan->ctl_off, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HS_HIP(hipStreamSynchronize(s));
+    if (plan->h_ctl->err) return fail(HS_EINTERNAL, "the plan's sort reported error bits 0x%x", plan->h_ctl->err);
+    return HS_OK;
+}
+
+void hs_plan_destroy(hs_plan *plan)
+{
+    if (plan) (void)hipDeviceSynchronize();
+    plan_release(plan);
 }
 
 }  // extern "C"

@@ -149,3 +149,31 @@ def test_learned_argument_errors_before_launch(hs):
     assert L.hs_multiway_partition_f64(p, 10, p, -1, p, None) == -1
     assert L.hs_multiway_partition_f64(p, 10, None, 3, p, None) == -1
     assert L.hs_multiway_partition_f64(p, 10, p, 3, None, None) == -1
+
+
+def test_header_declares_plan_entry_points():
+    names = set(_declared())
+    for n in ["hs_plan_create", "hs_plan_exec", "hs_plan_check", "hs_plan_destroy", "hs_autotune"]:
+        assert n in names
+
+
+def test_plan_argument_errors_before_launch(hs):
+    L = hs.lib()
+    p = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p()
+    assert L.hs_plan_create(hs.OP_SORT_I32, p, None, 10, None, 0, None, None) == -1
+    assert L.hs_plan_create(hs.OP_PARTITION_I32, p, None, 10, None, 0, None, ctypes.byref(out)) == -1
+    assert L.hs_plan_create(hs.OP_SORT_KV_I32, p, None, 10, None, 0, None, ctypes.byref(out)) == -1
+    assert L.hs_plan_create(hs.OP_SORT_SEGMENTED_I32, p, None, 10, None, 3, None, ctypes.byref(out)) == -1
+    o = hs.Opts()
+    o.driver = hs.DRIVER_HOST
+    assert L.hs_plan_create(hs.OP_SORT_I32, p, None, 10, None, 0, ctypes.byref(o), ctypes.byref(out)) == -1
+    o = hs.Opts()
+    o.leaf = 100
+    assert L.hs_plan_create(hs.OP_SORT_I32, p, None, 10, None, 0, ctypes.byref(o), ctypes.byref(out)) == -1
+    assert L.hs_plan_exec(None, None) == -1
+    assert L.hs_plan_check(None, None) == -1
+    L.hs_plan_destroy(None)
+    assert L.hs_autotune(hs.OP_SORT_I32, p, None, 10, None, 0, None, None, None, None) == -1
+    best = hs.Opts()
+    assert L.hs_autotune(99, p, None, 10, None, 0, None, ctypes.byref(best), None, None) == -1

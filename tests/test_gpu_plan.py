@@ -1,0 +1,147 @@
+"""Graph plans (hs_plan_*) and the autotuner, through the C ABI.
+
+A plan records one sort of fixed tensors into a HIP graph; every test
+replays it several times with fresh data, with eager work of the program's
+own (copies and an unrelated sort) and synchronizations between the
+replays, and checks every replay against the oracle.  The autotuner must
+leave its input unchanged, find every candidate's output identical, and
+hand back knobs from its candidate set.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from helpers import kv_index_check
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import paper_1704_08579_amd as hsort
+    hsort.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return hsort
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _eager_noise(hs, seed):
+    """Unrelated eager work between replays."""
+    x = _gpu(workloads.uniform_i32(100003, seed=seed))
+    hs.sort_(x)
+    torch.cuda.synchronize()
+    assert bool((x[1:] >= x[:-1]).all())
+
+
+def test_plan_segmented_replays(hs, oracle_mod):
+    off = workloads.segment_offsets(3000, 16, 1 << 16, seed=41)
+    off = off.astype(np.int64)
+    n = int(off[-1])
+    t = torch.empty(n, dtype=torch.int32, device="cuda")
+    o = _gpu(off)
+    plan = hs.Plan(t, offsets=o)
+    for r in range(3):
+        keys = workloads.uniform_i32(n, seed=42 + r)
+        t.copy_(_gpu(keys))
+        torch.cuda.synchronize()
+        plan.run()
+        plan.check()
+        assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off)), r
+        _eager_noise(hs, r)
+    plan.close()
+
+
+@pytest.mark.parametrize("dist", ["uniform", "lognormal"])
+def test_plan_f64_replays(hs, oracle_mod, dist):
+    n = (1 << 20) + 321
+    t = torch.empty(n, dtype=torch.float64, device="cuda")
+    plan = hs.Plan(t)
+    for r in range(3):
+        x = workloads.f64(n, dist, seed=50 + r)
+        t.copy_(_gpu(x))
+        plan.run()
+        plan.check()
+        assert np.array_equal(t.cpu().numpy().view(np.uint64), oracle_mod.sort_f64(x).view(np.uint64)), r
+        _eager_noise(hs, 10 + r)
+
+
+def test_plan_kv_replays(hs, oracle_mod):
+    n = 700001
+    k = torch.empty(n, dtype=torch.int32, device="cuda")
+    v = torch.empty(n, dtype=torch.int32, device="cuda")
+    plan = hs.Plan(k, vals=v)
+    for r in range(2):
+        keys, vals = workloads.kv_dup_i32(n, seed=60 + r, ndistinct=5000)
+        k.copy_(_gpu(keys))
+        v.copy_(_gpu(vals))
+        plan.run()
+        plan.check()
+        ko, vo = k.cpu().numpy(), v.cpu().numpy()
+        ok, _ = oracle_mod.sort_kv_i32(keys, vals)
+        assert np.array_equal(ko, ok)
+        kv_index_check(keys, ko, vo)
+        _eager_noise(hs, 20 + r)
+
+
+def test_plan_learned(hs, oracle_mod):
+    n = 1 << 20
+    t = torch.empty(n, dtype=torch.float64, device="cuda")
+    plan = hs.Plan(t, opts=hs.learned_opts(steps=50))
+    for r in range(2):
+        x = workloads.f64(n, "mixture", seed=70 + r)
+        t.copy_(_gpu(x))
+        plan.run()
+        plan.check()
+        assert np.array_equal(t.cpu().numpy().view(np.uint64), oracle_mod.sort_f64(x).view(np.uint64)), r
+
+
+def test_plan_rejects_host_driver(hs):
+    t = torch.empty(1000, dtype=torch.int32, device="cuda")
+    o = hs.Opts()
+    o.driver = hs.DRIVER_HOST
+    with pytest.raises(hs.HSortError):
+        hs.Plan(t, opts=o)
+
+
+def test_autotune_segmented(hs, oracle_mod):
+    off = workloads.segment_offsets(2000, 16, 1 << 15, seed=80).astype(np.int64)
+    n = int(off[-1])
+    keys = workloads.uniform_i32(n, seed=81)
+    t, o = _gpu(keys), _gpu(off)
+    base = hs.Opts()
+    base.driver = hs.DRIVER_PERSISTENT
+    best, rep = hs.autotune(t, offsets=o, opts=base)
+    assert rep["candidates"] == 18 and rep["outputs_equal"] == 1
+    assert rep["best_ms"] <= rep["default_ms"]
+    assert best.local_T in (2048, 4096, 8192) and best.leaf in (128, 256, 512) and best.pivot_rule in (2, 3)
+    assert np.array_equal(t.cpu().numpy(), keys), "the autotuner changed its input"
+    best2, rep2 = hs.autotune(t, offsets=o, opts=base)
+    assert rep2["candidates"] == 0
+    assert (best2.local_T, best2.leaf, best2.pivot_rule) == (best.local_T, best.leaf, best.pivot_rule)
+    plan = hs.Plan(t, offsets=o, opts=best)
+    plan.run()
+    plan.check()
+    assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
+
+
+def test_autotune_flag(hs, oracle_mod):
+    """opts.autotune: the first call tunes, later calls of the size class reuse it."""
+    a = workloads.uniform_i32(300007, seed=90)
+    o = hs.Opts()
+    o.autotune = 1
+    for r in range(2):
+        t = _gpu(a)
+        hs.sort_(t, opts=o)
+        assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_i32(a))
+    off = workloads.segment_offsets(500, 16, 1 << 14, seed=91).astype(np.int64)
+    keys = workloads.uniform_i32(int(off[-1]), seed=92)
+    t, ot = _gpu(keys), _gpu(off)
+    plan = hs.Plan(t, offsets=ot, opts=o)
+    plan.run()
+    plan.check()
+    assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
