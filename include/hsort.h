@@ -122,8 +122,9 @@ typedef struct hs_opts {
     int32_t driver;       /* HS_DRIVER_*: how the partition levels are driven */
     int32_t spin_limit;   /* testing: cap on the polls of one grid-barrier wait (0: about 4M); a wait that
                            * runs out fails the call with HS_EINTERNAL */
-    int32_t leaf;         /* largest range one wave sorts with the bitonic network alone: 64, 128, 256 or
-                           * 512 (default 512); larger ranges go to the workgroup on-chip sort */
+    int32_t leaf;         /* largest range one wave sorts with the bitonic network alone: a power of two in
+                           * 64..1024, capped at the type's network (1024 int32, 512 float64 and
+                           * key/value; the default); larger ranges go to the workgroup on-chip sort */
     int32_t autotune;     /* 1: use (or first measure and remember) the tuned knobs for this operation and
                            * size class; see hs_autotune */
     int32_t reserved;
@@ -231,7 +232,8 @@ HS_API void hs_plan_destroy(hs_plan *plan);
  *
  * Measures the sort of the given input (left unchanged: the tuner sorts a
  * copy) under every combination of on-chip limit local_T (2048, 4096, 8192),
- * one-wave bitonic bound leaf (128, 256, 512) and global pivot rule
+ * one-wave bitonic bound leaf (the type's network size L, L/2, L/4: 1024,
+ * 512, 256 for int32; 512, 256, 128 otherwise) and global pivot rule
  * (ninther, sample median of 64), for the driver base->driver selects, with
  * HIP events (one warm-up and two timed runs each, fastest kept).  Every
  * candidate's output is compared on the device with the first candidate's:

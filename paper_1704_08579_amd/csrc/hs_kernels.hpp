@@ -887,7 +887,7 @@ __global__ void k_write_count(const unsigned long long *cur, int64_t *d_count)
 // resident per CU (LDS: 160 KB per CU; registers: 16 waves per CU keep the
 // 128-VGPR budget that the chunk of keys per thread needs).
 template <typename K> struct LocalCfg;
-template <> struct LocalCfg<uint32_t> { static constexpr int T = 8192, NT = 512, LEAF = 512, WPC = 2; };
+template <> struct LocalCfg<uint32_t> { static constexpr int T = 8192, NT = 512, LEAF = 1024, WPC = 2; };
 template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 512, LEAF = 512, WPC = 2; };
 
 // Sort the keys of one wave's registers (any load order) with the smallest

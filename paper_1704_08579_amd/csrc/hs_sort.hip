@@ -232,8 +232,8 @@ int check_learn(const hs_opts *o)
     if (o->driver != HS_DRIVER_AUTO && o->driver != HS_DRIVER_PERSISTENT && o->driver != HS_DRIVER_HOST)
         return fail(HS_EINVAL, "unknown driver %d", o->driver);
     if (o->spin_limit < 0) return fail(HS_EINVAL, "spin_limit is negative");
-    if (o->leaf != 0 && o->leaf != 64 && o->leaf != 128 && o->leaf != 256 && o->leaf != 512)
-        return fail(HS_EINVAL, "leaf = %d is not 64, 128, 256 or 512", o->leaf);
+    if (o->leaf != 0 && (o->leaf < 64 || o->leaf > 1024 || (o->leaf & (o->leaf - 1))))
+        return fail(HS_EINVAL, "leaf = %d is not a power of two in 64..1024", o->leaf);
     if (o->local_T < 0) return fail(HS_EINVAL, "local_T = %d is negative", o->local_T);
     if (o->autotune != 0 && o->autotune != 1) return fail(HS_EINVAL, "autotune = %d is not 0 or 1", o->autotune);
     if (o->method != HS_METHOD_PLAIN && o->method != HS_METHOD_LEARNED)
@@ -639,9 +639,10 @@ int autotune_impl(DevState *d, int op, Raw raw, int64_t n, const int64_t *d_off,
     const Raw wr{work.p, vb ? (int32_t *)((char *)work.p + kb) : nullptr};
     const uint32_t Tmax = (uint32_t)LocalCfg<K>::T;
     std::vector<std::tuple<int, int, int>> cands;
-    cands.emplace_back((int)Tmax, (int)LocalCfg<K>::LEAF, PIVOT_SAMPLE);  // the defaults first: the reference output
+    const int Lmax = (int)LocalCfg<K>::LEAF;
+    cands.emplace_back((int)Tmax, Lmax, PIVOT_SAMPLE);  // the defaults first: the reference output
     for (int T : {2048, 4096, 8192})
-        for (int leaf : {128, 256, 512})
+        for (int leaf : {Lmax / 4, Lmax / 2, Lmax})
             for (int piv : {PIVOT_NINTHER, PIVOT_SAMPLE}) {
                 if ((uint32_t)T > Tmax) continue;
                 auto c = std::make_tuple(T, leaf, piv);

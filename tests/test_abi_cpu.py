@@ -171,6 +171,8 @@ def test_plan_argument_errors_before_launch(hs):
     o = hs.Opts()
     o.leaf = 100
     assert L.hs_plan_create(hs.OP_SORT_I32, p, None, 10, None, 0, ctypes.byref(o), ctypes.byref(out)) == -1
+    o.leaf = 2048
+    assert L.hs_plan_create(hs.OP_SORT_I32, p, None, 10, None, 0, ctypes.byref(o), ctypes.byref(out)) == -1
     assert L.hs_plan_exec(None, None) == -1
     assert L.hs_plan_check(None, None) == -1
     L.hs_plan_destroy(None)

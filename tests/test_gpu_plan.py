@@ -118,7 +118,7 @@ def test_autotune_segmented(hs, oracle_mod):
     best, rep = hs.autotune(t, offsets=o, opts=base)
     assert rep["candidates"] == 18 and rep["outputs_equal"] == 1
     assert rep["best_ms"] <= rep["default_ms"]
-    assert best.local_T in (2048, 4096, 8192) and best.leaf in (128, 256, 512) and best.pivot_rule in (2, 3)
+    assert best.local_T in (2048, 4096, 8192) and best.leaf in (256, 512, 1024) and best.pivot_rule in (2, 3)
     assert np.array_equal(t.cpu().numpy(), keys), "the autotuner changed its input"
     best2, rep2 = hs.autotune(t, offsets=o, opts=base)
     assert rep2["candidates"] == 0
