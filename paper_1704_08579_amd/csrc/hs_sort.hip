@@ -314,9 +314,24 @@ uint32_t zero_grid(size_t bytes)
 // Sort n keys whose workspace `ws` (laid out as L) is already bound.  Does
 // not lock the device state: the learned front end calls it again for its
 // training sample with a sub-workspace.
+// Levels that a segment of `size` keys needs with balanced splits down to T,
+// plus one.
+int levels_for(uint64_t size, uint32_t T)
+{
+    int l = 1;
+    while (size > T) {
+        size = (size + 1) / 2;
+        ++l;
+    }
+    return l;
+}
+
+// graph_levels > 0 (graph plans): record that many per-level launches (a
+// level with an empty list costs three empty launches) before the
+// persistent driver, which finishes whatever levels remain.
 template <int F>
 int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg,
-              const hs_opts *o, const LearnParams &P, hs_stats *st, hipStream_t stream)
+              const hs_opts *o, const LearnParams &P, hs_stats *st, hipStream_t stream, int graph_levels = 0)
 {
     using K = typename KeyOf<F>::type;
     const uint32_t T = local_limit<K>(o);
@@ -410,48 +425,55 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     int guard = 2;
     for (int64_t x = n; x > 1; x >>= 1) ++guard;  // 2 + log2(n): beyond it, sample-median pivots
     int launches = 0;
+    // one level as three fixed-grid launches (every kernel reads the level's
+    // size from the control block, so an empty level does nothing)
+    int occ_p = 0;
+    HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_p, k_partition<F, false, false>, PartCfg<K>::NT, 0));
+    if (occ_p < 1) occ_p = 1;
+    const int part_grid = d->ncu * occ_p;
+    const int fin_grid = d->ncu * 4;
+    auto launch_level = [&](int level) -> int {
+        const int p = level & 1;
+        const int lrule = level > guard ? PIVOT_SAMPLE : rule;
+        HS_LAUNCH(k_level_begin, 1, 64, stream, ctl, p);
+        if (st) HS_HIP(hipEventRecord(d->ev[2 * level], stream));
+        if (level == 0)
+            HS_LAUNCH((k_partition<F, true, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, segs[p], curs[p],
+                      (const K *)nullptr, raw, buf[1 - p], Raw{}, L.cand_cap);
+        else
+            HS_LAUNCH((k_partition<F, false, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, segs[p], curs[p],
+                      (const K *)buf[p], raw, buf[1 - p], Raw{}, L.cand_cap);
+        if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
+        HS_LAUNCH(k_finalize<F>, fin_grid, 256, stream, ctl, p, segs[p], curs[p], segs[1 - p], curs[1 - p], tasks,
+                  buf[1 - p], (uint32_t)(1 - p), T, LEAF, lrule, L.cand_cap, L.task_cap);
+        ++launches;
+        return HS_OK;
+    };
     if (!host_driver) {
-        // one persistent launch runs every level (its grid must be resident at once)
+        int first = level0;
+        if (graph_levels > 0 && !st) {
+            for (int l = 0; l < graph_levels && first < LMAX; ++l, ++first) {
+                const int rc = launch_level(first);
+                if (rc) return rc;
+            }
+        }
+        // one persistent launch runs every (remaining) level; its grid must be resident at once
         int occ = 0;
         HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_levels<F>, PartCfg<K>::NT, 0));
         if (occ < 1) return fail(HS_EINTERNAL, "the level driver does not fit on a compute unit");
         if (st) HS_HIP(hipEventRecord(lev[5], stream));
         HS_LAUNCH(k_levels<F>, d->ncu * occ, PartCfg<K>::NT, stream, ctl, segs[0], segs[1], curs[0], curs[1], buf[0],
-                  buf[1], raw, tasks, T, LEAF, rule, guard, level0, LMAX, L.cand_cap, L.task_cap,
+                  buf[1], raw, tasks, T, LEAF, rule, guard, first, LMAX, L.cand_cap, L.task_cap,
                   (o && o->spin_limit > 0) ? (uint32_t)o->spin_limit : BARRIER_SPIN_LIMIT);
         if (st) HS_HIP(hipEventRecord(lev[6], stream));
     } else {
         // host-driven levels: batches of fixed-grid launches, one read-back per batch
-        auto levels_for = [&](uint64_t size) {
-            int l = 1;
-            while (size > T) {
-                size = (size + 1) / 2;
-                ++l;
-            }
-            return l;
-        };
-        int occ = 0;
-        HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_partition<F, false, false>, PartCfg<K>::NT, 0));
-        if (occ < 1) occ = 1;
-        const int part_grid = d->ncu * occ;
-        const int fin_grid = d->ncu * 4;
-        int level = level0, batch = 0;
+        int level = level0;
+        int batch = (!learned && !d_off && (uint64_t)n > T) ? levels_for((uint64_t)n, T) : 0;
         for (;;) {
             for (int bi = 0; bi < batch && level < LMAX; ++bi, ++level) {
-                const int p = level & 1;
-                const int lrule = level > guard ? PIVOT_SAMPLE : rule;
-                HS_LAUNCH(k_level_begin, 1, 64, stream, ctl, p);
-                if (st) HS_HIP(hipEventRecord(d->ev[2 * level], stream));
-                if (level == 0)
-                    HS_LAUNCH((k_partition<F, true, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, segs[p],
-                              curs[p], (const K *)nullptr, raw, buf[1 - p], Raw{}, L.cand_cap);
-                else
-                    HS_LAUNCH((k_partition<F, false, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, segs[p],
-                              curs[p], (const K *)buf[p], raw, buf[1 - p], Raw{}, L.cand_cap);
-                if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
-                HS_LAUNCH(k_finalize<F>, fin_grid, 256, stream, ctl, p, segs[p], curs[p], segs[1 - p], curs[1 - p],
-                          tasks, buf[1 - p], (uint32_t)(1 - p), T, LEAF, lrule, L.cand_cap, L.task_cap);
-                ++launches;
+                const int rc = launch_level(level);
+                if (rc) return rc;
             }
             HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
             HS_HIP(hipStreamSynchronize(stream));
@@ -459,7 +481,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
             const LevelCounts &lc = h->lev[level & 1];
             if ((uint32_t)lc.segs_tiles == 0) break;
             if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
-            batch = levels_for(lc.max_seg);
+            batch = levels_for(lc.max_seg, T);
         }
     }
     // on-chip sorts: fixed grids, the task counts are read on the device
@@ -531,7 +553,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
 
 template <int F>
 int run_sort_tuned(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
-                   hs_stats *st, hipStream_t stream)
+                   hs_stats *st, hipStream_t stream, int graph_levels = 0)
 {
     const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
                          : (F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : HS_OP_SORT_KV_I32);
@@ -545,7 +567,7 @@ int run_sort_tuned(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_
     if (rc) return rc;
     const bool shared_ws = !(o && o->workspace);
     if (shared_ws) HS_HIP(hipStreamWaitEvent(stream, d->last, 0));
-    rc = sort_body<F>(d, ws, L, raw, n, d_off, nseg, o, P, st, stream);
+    rc = sort_body<F>(d, ws, L, raw, n, d_off, nseg, o, P, st, stream, graph_levels);
     if (shared_ws) HS_HIP(hipEventRecord(d->last, stream));
     return rc;
 }
@@ -1161,12 +1183,33 @@ int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *
         return fail(HS_EHIP, "plan set-up failed");
     }
     HS_HIP(hipDeviceSynchronize());  // the autotuner's work and the workspace are ready
+    // Per-level launches recorded before the persistent driver: the levels
+    // the largest segment needs with balanced splits, plus two (a level with
+    // an empty list costs three empty launches; the persistent driver takes
+    // whatever remains).
+    int graph_levels = 0;
+    {
+        const uint32_t T = op == HS_OP_SORT_I32 || op == HS_OP_SORT_SEGMENTED_I32 ? local_limit<uint32_t>(&o)
+                                                                                 : local_limit<uint64_t>(&o);
+        uint64_t biggest = (uint64_t)n;
+        if (op == HS_OP_SORT_SEGMENTED_I32) {
+            std::vector<int64_t> h_off((size_t)nseg + 1);
+            HS_HIP(hipMemcpy(h_off.data(), d_offsets, h_off.size() * 8, hipMemcpyDeviceToHost));
+            biggest = 0;
+            for (int64_t i = 0; i < nseg; ++i)
+                if (h_off[i + 1] - h_off[i] > (int64_t)biggest) biggest = (uint64_t)(h_off[i + 1] - h_off[i]);
+        } else if (o.method == HS_METHOD_LEARNED) {
+            biggest = (uint64_t)n / 64;  // buckets of the multiway pass hold about n/256 keys
+        }
+        graph_levels = biggest > T ? levels_for(biggest, T) + 1 : 0;
+    }
     if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         plan_release(p);
         return fail(HS_EHIP, "hipStreamBeginCapture failed");
     }
     rc = with_format(op, [&](auto fmt) {
-        return run_sort_tuned<decltype(fmt)::value>(d, Raw{keys, vals}, n, off, nseg, &o, nullptr, p->cap);
+        return run_sort_tuned<decltype(fmt)::value>(d, Raw{keys, vals}, n, off, nseg, &o, nullptr, p->cap,
+                                                    graph_levels);
     });
     const hipError_t ec = hipStreamEndCapture(p->cap, &p->graph);
     if (rc == HS_OK && ec != hipSuccess) rc = fail(HS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));

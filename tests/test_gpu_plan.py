@@ -145,3 +145,25 @@ def test_autotune_flag(hs, oracle_mod):
     plan.run()
     plan.check()
     assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
+
+
+def test_plan_persistent_tail(hs, oracle_mod):
+    """Skewed splits (median-of-3 on an organ pipe, small on-chip limit) need
+    more levels than the plan records as per-level launches; the persistent
+    driver recorded after them finishes the sort."""
+    n = 400003
+    half = np.arange(n // 2, dtype=np.int32)
+    base = np.concatenate([half, half[::-1], [7]]).astype(np.int32)
+    o = hs.Opts()
+    o.pivot_rule = 1
+    o.local_T = 600
+    t = torch.empty(n, dtype=torch.int32, device="cuda")
+    plan = hs.Plan(t, opts=o)
+    for r in range(2):
+        x = np.roll(base, 1000 * r)
+        t.copy_(_gpu(x))
+        plan.run()
+        plan.check()
+        assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_i32(x)), r
+    st = hs.sort_(_gpu(base), opts=o, stats=True)
+    assert st["passes"] > 12  # more than the 11 + 1 levels the plan records
