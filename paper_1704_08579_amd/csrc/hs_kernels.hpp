@@ -125,8 +125,12 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
 // ---------------------------------------------------------------- tile geometry
 
 template <typename K> struct PartCfg;
-template <> struct PartCfg<uint32_t> { static constexpr int NT = 512, TILE = 8192; };
-template <> struct PartCfg<uint64_t> { static constexpr int NT = 256, TILE = 4096; };
+// Measured on MI355X (f64 and int32 at 2^27..2^28): 1024-thread workgroups
+// with 8 keys (8-byte words) or 16 keys (int32) per thread keep the most
+// bytes in flight; 256/512-thread shapes and 1-workgroup-per-CU tiles were
+// up to 6% slower end to end.
+template <> struct PartCfg<uint32_t> { static constexpr int NT = 1024, TILE = 16384; };
+template <> struct PartCfg<uint64_t> { static constexpr int NT = 1024, TILE = 8192; };
 
 // Write-cursor words of different segments sit 256 bytes apart: atomics on
 // one cache line serialize, so neighbouring segments must not share one.
