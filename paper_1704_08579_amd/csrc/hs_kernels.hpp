@@ -63,8 +63,8 @@ template <typename K> struct Task {
 // is finalized.  Level L uses list, cursor array and counters number L & 1.
 struct alignas(256) LevelCounts {
     unsigned long long segs_tiles;  // low half: segments in the list, high half: their tiles
-    unsigned long long keys;        // keys in those segments
-    uint32_t max_seg;               // the largest of them
+    alignas(256) unsigned long long keys;  // keys in those segments (its own line: see wave_emit_segs2)
+    uint32_t max_seg;                      // the largest of them
 };
 
 // Control block of one call, in device memory.  Every counter that many
@@ -84,9 +84,30 @@ struct Ctl {
     unsigned long long part_keys;      // keys in the segments of every level run
 };
 
-// Items a wave emits over a batch of up to 64 steps are parked one per lane
-// (lane k keeps what step k emitted) and appended to a device list with a
-// single atomic per wave.
+// Items a wave emits over a batch of up to 64 steps are parked one or two per
+// lane (lane k keeps what step k emitted) and appended to a device list with
+// a single atomic per wave.
+template <typename T>
+__device__ __forceinline__ void wave_flush2(const T &a, bool ha, const T &b, bool hb, uint32_t *counter, T *list,
+                                            uint32_t cap, Ctl *ctl, uint32_t errbit, bool from_back)
+{
+    const uint32_t cnt = (ha ? 1u : 0u) + (hb ? 1u : 0u);
+    if (__ballot(cnt != 0) == 0) return;
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, WAVE - 1);
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, total);
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+    uint32_t k = base + incl - cnt;
+    auto put = [&](const T &item) {
+        if (k < cap) list[from_back ? cap - 1 - k : k] = item;
+        else atomicOr(&ctl->err, errbit);
+        ++k;
+    };
+    if (ha) put(a);
+    if (hb) put(b);
+}
+
 template <typename T>
 __device__ __forceinline__ void wave_flush(const T &item, bool has, uint32_t *counter, T *list, uint32_t cap,
                                            Ctl *ctl, uint32_t errbit, bool from_back = false)
@@ -114,6 +135,15 @@ __device__ __forceinline__ void wave_flush_task(const T &item, bool has, bool sm
 {
     wave_flush(item, has && !small, &ctl->ntask, list, cap, ctl, ERR_TASK_CAP, false);
     wave_flush(item, has && small, &ctl->nsmall, list, cap, ctl, ERR_TASK_CAP, true);
+}
+
+// Two items per lane, one atomic per list.
+template <typename T>
+__device__ __forceinline__ void wave_flush_task2(const T &a, bool ha, bool sa, const T &b, bool hb, bool sb,
+                                                 T *list, uint32_t cap, Ctl *ctl)
+{
+    wave_flush2(a, ha && !sa, b, hb && !sb, &ctl->ntask, list, cap, ctl, ERR_TASK_CAP, false);
+    wave_flush2(a, ha && sa, b, hb && sb, &ctl->nsmall, list, cap, ctl, ERR_TASK_CAP, true);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
@@ -145,43 +175,68 @@ __device__ __host__ __forceinline__ uint32_t seg_tiles(uint32_t b, uint32_t e)
     return (e + TILE - 1) / TILE - b / TILE;
 }
 
-// Append the segments a wave holds (lane k: one segment, if `has`) to the
+// Append the segments a wave holds (lane k: up to two, a before b) to the
 // next level's list.  One 64-bit atomic reserves both the list slots (low
 // half) and the segments' tiles (high half), so tile0 grows with the slot
 // index and a tile finds its segment by binary search.  The cursor word of
-// each new slot is cleared here.
+// each new slot is cleared here.  The list's key count and largest segment
+// are only read after the level, so the caller accumulates them per lane
+// (keys, mx) and adds them once at its end: the slot/tile atomic is the only
+// one that every batch of every wave makes on that line.
 template <typename K>
-__device__ __forceinline__ void wave_emit_segs(Seg<K> item, bool has, Seg<K> *list, unsigned long long *curs,
-                                               LevelCounts *lc, uint32_t cap, Ctl *ctl)
+__device__ __forceinline__ void wave_emit_segs2(Seg<K> a, bool ha, Seg<K> b, bool hb, Seg<K> *list,
+                                                unsigned long long *curs, LevelCounts *lc, uint32_t cap, Ctl *ctl,
+                                                unsigned long long &keys, uint32_t &mx)
 {
-    const uint64_t m = __ballot(has);
-    if (m == 0) return;
-    const int lane = lane_id();
-    const uint32_t nt = has ? seg_tiles<K>(item.b, item.e) : 0u;
-    const uint32_t sz = has ? item.e - item.b : 0u;
-    const uint32_t incl = wave_incl_scan(nt);
-    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, WAVE - 1);
-    const unsigned long long keys = wave_sum64(sz);
-    uint32_t mx = sz;
-    for (int d = 1; d < WAVE; d <<= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d));
+    const uint32_t cnt = (ha ? 1u : 0u) + (hb ? 1u : 0u);
+    if (__ballot(cnt != 0) == 0) return;
+    const uint32_t nta = ha ? seg_tiles<K>(a.b, a.e) : 0u, ntb = hb ? seg_tiles<K>(b.b, b.e) : 0u;
+    const uint32_t nt = nta + ntb;
+    const uint32_t ic = wave_incl_scan(cnt), it = wave_incl_scan(nt);
+    const uint32_t tc = (uint32_t)__builtin_amdgcn_readlane((int)ic, WAVE - 1);
+    const uint32_t tt = (uint32_t)__builtin_amdgcn_readlane((int)it, WAVE - 1);
     unsigned long long base = 0;
-    if (lane == 0) {
-        base = atomicAdd(&lc->segs_tiles, ((unsigned long long)tot << 32) | (unsigned long long)__popcll(m));
-        atomicAdd(&lc->keys, keys);
-        atomicMax(&lc->max_seg, mx);
-    }
+    if (lane_id() == 0) base = atomicAdd(&lc->segs_tiles, ((unsigned long long)tt << 32) | (unsigned long long)tc);
     const uint32_t slot0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
     const uint32_t tile_base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(base >> 32));
-    if (has) {
-        const uint32_t k = slot0 + mask_below(m);
+    uint32_t k = slot0 + ic - cnt, t0 = tile_base + it - nt;
+    auto put = [&](Seg<K> item, uint32_t ntiles) {
         if (k < cap) {
-            item.tile0 = tile_base + incl - nt;
+            item.tile0 = t0;
             list[k] = item;
             curs[(size_t)k * CUR_STRIDE] = 0ull;
         } else {
             atomicOr(&ctl->err, ERR_CAND_CAP);
         }
+        ++k;
+        t0 += ntiles;
+        keys += item.e - item.b;
+        mx = max(mx, item.e - item.b);
+    };
+    if (ha) put(a, nta);
+    if (hb) put(b, ntb);
+}
+
+// Add a wave's accumulated key count and largest segment to a level list.
+__device__ __forceinline__ void wave_emit_totals(LevelCounts *lc, unsigned long long keys, uint32_t mx)
+{
+    keys = wave_sum64(keys);
+    for (int d = 1; d < WAVE; d <<= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d));
+    if (lane_id() == 0 && keys) {
+        atomicAdd(&lc->keys, keys);
+        atomicMax(&lc->max_seg, mx);
     }
+}
+
+// One segment per lane.
+template <typename K>
+__device__ __forceinline__ void wave_emit_segs(Seg<K> item, bool has, Seg<K> *list, unsigned long long *curs,
+                                               LevelCounts *lc, uint32_t cap, Ctl *ctl)
+{
+    unsigned long long keys = 0;
+    uint32_t mx = 0;
+    wave_emit_segs2(item, has, item, false, list, curs, lc, cap, ctl, keys, mx);
+    wave_emit_totals(lc, keys, mx);
 }
 
 // Number of segments of a level list that may be read (an overflow is
@@ -683,7 +738,8 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
     using K = typename KeyOf<F>::type;
     const int lane = lane_id();
     SrcReader<F> rd{out, Raw{nullptr, nullptr}, false};
-    unsigned long long lkeys = 0, fkeys = 0;
+    unsigned long long lkeys = 0, fkeys = 0, ekeys = 0;
+    uint32_t emax = 0;
 
     for (uint32_t step0 = 0; w + (uint64_t)step0 * nwaves < nseg; step0 += WAVE) {
         // parked items of this batch (lane k: batch step k)
@@ -760,11 +816,11 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
                 }
             }
         }
-        wave_emit_segs(c0, h_c0, cand, ncur, nlev, cand_cap, ctl);
-        wave_emit_segs(c1, h_c1, cand, ncur, nlev, cand_cap, ctl);
-        wave_flush_task(t0, h_t0, t0.kind == TASK_FILL || t0.e - t0.b <= leaf, tasks, task_cap, ctl);
-        wave_flush_task(t1, h_t1, t1.kind == TASK_FILL || t1.e - t1.b <= leaf, tasks, task_cap, ctl);
+        wave_emit_segs2(c0, h_c0, c1, h_c1, cand, ncur, nlev, cand_cap, ctl, ekeys, emax);
+        wave_flush_task2(t0, h_t0, t0.kind == TASK_FILL || t0.e - t0.b <= leaf, t1, h_t1,
+                         t1.kind == TASK_FILL || t1.e - t1.b <= leaf, tasks, task_cap, ctl);
     }
+    wave_emit_totals(nlev, ekeys, emax);
     if (lane == 0) {
         if (lkeys) atomicAdd(&ctl->local_keys, lkeys);
         if (fkeys) atomicAdd(&ctl->fill_keys, fkeys);
