@@ -452,6 +452,23 @@ __global__ __launch_bounds__(256) void k_init_segmented(Ctl *ctl, Seg<typename K
     wave_emit_segs(sg, is_big, cand, cur, &ctl->lev[0], cand_cap, ctl);
 }
 
+// Bookkeeping at the start of a level with list number `par`: clear the
+// next level's counters (always: an empty level must leave an empty list
+// behind, not the one of the level before it) and count a non-empty level.
+// One thread.
+__device__ __forceinline__ void level_begin(Ctl *ctl, int par)
+{
+    LevelCounts &nx = ctl->lev[1 - par];
+    atomicExch(&nx.segs_tiles, 0ull);
+    atomicExch(&nx.keys, 0ull);
+    atomicExch(&nx.max_seg, 0u);
+    const LevelCounts &cur = ctl->lev[par];
+    if ((uint32_t)__hip_atomic_load(&cur.segs_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        atomicAdd(&ctl->levels, 1u);
+        atomicAdd(&ctl->part_keys, __hip_atomic_load(&cur.keys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+}
+
 // ---------------------------------------------------------------- partition pass
 
 // Where one tile of the level lies: segment index, first key, key count.
@@ -693,16 +710,19 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
 }
 
 // One partition level as a kernel of its own (the host-driven level loop and
-// the partition entry point): level list number `par`.
+// the partition entry point): level list number `par`.  With begin_level set
+// its first thread also does the level's bookkeeping (level_begin): the
+// finalize kernel that follows builds the next list on cleared counters.
 template <int F, bool SRC_IS_RAW, bool DST_IS_RAW>
 __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partition(
-    const Ctl *ctl, int par, const Seg<typename KeyOf<F>::type> *segs, unsigned long long *cur,
+    Ctl *ctl, int par, int begin_level, const Seg<typename KeyOf<F>::type> *segs, unsigned long long *cur,
     const typename KeyOf<F>::type *src, Raw raw, typename KeyOf<F>::type *dst, Raw raw_dst, uint32_t cap)
 {
     using K = typename KeyOf<F>::type;
     __shared__ K stage[PartCfg<K>::TILE];
     __shared__ uint32_t wsum[PartCfg<K>::NT / WAVE];
     __shared__ uint32_t sbase[2];
+    if (begin_level && blockIdx.x == 0 && threadIdx.x == 0) level_begin(ctl, par);
     const unsigned long long st = ctl->lev[par].segs_tiles;
     partition_level<F, SRC_IS_RAW, DST_IS_RAW>((uint32_t)(st >> 32), level_segs(st, cap), segs, cur, src, raw, dst,
                                                raw_dst, blockIdx.x, gridDim.x, stage, wsum, sbase);
@@ -825,28 +845,6 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
         if (lkeys) atomicAdd(&ctl->local_keys, lkeys);
         if (fkeys) atomicAdd(&ctl->fill_keys, fkeys);
     }
-}
-
-// Bookkeeping at the start of a level with list number `par`: clear the
-// next level's counters (always: an empty level must leave an empty list
-// behind, not the one of the level before it) and count a non-empty level.
-// One thread.
-__device__ __forceinline__ void level_begin(Ctl *ctl, int par)
-{
-    LevelCounts &nx = ctl->lev[1 - par];
-    atomicExch(&nx.segs_tiles, 0ull);
-    atomicExch(&nx.keys, 0ull);
-    atomicExch(&nx.max_seg, 0u);
-    const LevelCounts &cur = ctl->lev[par];
-    if ((uint32_t)__hip_atomic_load(&cur.segs_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        atomicAdd(&ctl->levels, 1u);
-        atomicAdd(&ctl->part_keys, __hip_atomic_load(&cur.keys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    }
-}
-
-__global__ void k_level_begin(Ctl *ctl, int par)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) level_begin(ctl, par);
 }
 
 template <int F>

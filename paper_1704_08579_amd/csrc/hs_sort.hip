@@ -431,17 +431,16 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_p, k_partition<F, false, false>, PartCfg<K>::NT, 0));
     if (occ_p < 1) occ_p = 1;
     const int part_grid = d->ncu * occ_p;
-    const int fin_grid = d->ncu * 4;
+    const int fin_grid = d->ncu * 2;
     auto launch_level = [&](int level) -> int {
         const int p = level & 1;
         const int lrule = level > guard ? PIVOT_SAMPLE : rule;
-        HS_LAUNCH(k_level_begin, 1, 64, stream, ctl, p);
         if (st) HS_HIP(hipEventRecord(d->ev[2 * level], stream));
         if (level == 0)
-            HS_LAUNCH((k_partition<F, true, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, segs[p], curs[p],
+            HS_LAUNCH((k_partition<F, true, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, 1, segs[p], curs[p],
                       (const K *)nullptr, raw, buf[1 - p], Raw{}, L.cand_cap);
         else
-            HS_LAUNCH((k_partition<F, false, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, segs[p], curs[p],
+            HS_LAUNCH((k_partition<F, false, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, 1, segs[p], curs[p],
                       (const K *)buf[p], raw, buf[1 - p], Raw{}, L.cand_cap);
         if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
         HS_LAUNCH(k_finalize<F>, fin_grid, 256, stream, ctl, p, segs[p], curs[p], segs[1 - p], curs[1 - p], tasks,
@@ -931,7 +930,7 @@ int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_l
     const uint32_t ntiles = seg_tiles<uint32_t>(0, (uint32_t)n);
     const uint32_t maxg = (uint32_t)d->ncu * 8;
     const int g = (int)(ntiles < maxg ? ntiles : maxg);
-    HS_LAUNCH((k_partition<FMT_I32, true, true>), g, PartCfg<uint32_t>::NT, s, ctl, 0, segs, cur,
+    HS_LAUNCH((k_partition<FMT_I32, true, true>), g, PartCfg<uint32_t>::NT, s, ctl, 0, 0, segs, cur,
               (const uint32_t *)nullptr, Raw{copy, nullptr}, (uint32_t *)nullptr, Raw{keys, nullptr}, L.cand_cap);
     HS_LAUNCH(k_write_count, 1, 64, s, cur, d_count_le);
     if (shared_ws) HS_HIP(hipEventRecord(d->last, s));
