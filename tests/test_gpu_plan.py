@@ -167,3 +167,51 @@ def test_plan_persistent_tail(hs, oracle_mod):
         assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_i32(x)), r
     st = hs.sort_(_gpu(base), opts=o, stats=True)
     assert st["passes"] > 12  # more than the 11 + 1 levels the plan records
+
+
+# ------------------------------------------------------------- full sizes (properties)
+
+def _segment_checks(keys_in, keys_out, off):
+    """Every segment sorted, and a permutation of its input (per-segment sums
+    of two mixing functions of the keys)."""
+    seg_start = off[:-1]
+    nonempty = off[1:] > off[:-1]
+    d = np.diff(keys_out.astype(np.int64))
+    boundary = np.zeros(keys_out.size, dtype=bool)
+    boundary[off[1:-1]] = True
+    assert np.all((d >= 0) | boundary[1:]), "a segment is not sorted"
+    u_in = keys_in.astype(np.uint32).astype(np.uint64)
+    u_out = keys_out.astype(np.uint32).astype(np.uint64)
+    for mix in (lambda u: (u * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF),
+                lambda u: (u ^ (u >> np.uint64(7))) * (u | np.uint64(1)) & np.uint64(0xFFFFFFFFFF)):
+        a = np.add.reduceat(mix(u_in), seg_start[nonempty])
+        b = np.add.reduceat(mix(u_out), seg_start[nonempty])
+        assert np.array_equal(a, b), "a segment is not a permutation of its input"
+
+
+@pytest.mark.parametrize("name,nseg,lo,hi", [("A", 200000, 16, 1 << 13), ("B", 2840, 16, 1 << 20)])
+def test_full_size_batched_graph(hs, name, nseg, lo, hi):
+    """The batched workloads bench.py times (one autotuned graph replay)."""
+    off = workloads.segment_offsets(nseg, lo, hi, seed=5).astype(np.int64)
+    keys = workloads.uniform_i32(int(off[-1]), seed=6)
+    t, o = _gpu(keys), _gpu(off)
+    base = hs.Opts()
+    base.driver = hs.DRIVER_PERSISTENT
+    tuned, _ = hs.autotune(t, offsets=o, opts=base)
+    plan = hs.Plan(t, offsets=o, opts=tuned)
+    plan.run()
+    plan.check()
+    _segment_checks(keys, t.cpu().numpy(), off)
+    plan.close()
+
+
+def test_full_size_learned(hs):
+    """2^28 float64 lognormal keys with learned splitters (the size bench.py
+    times): sorted by totalOrder and a permutation of the input."""
+    x = workloads.f64(1 << 28, "lognormal", seed=6)
+    t = _gpu(x)
+    st = hs.sort_(t, opts=hs.learned_opts(seed=100), stats=True)
+    got = t.cpu().numpy().view(np.uint64)
+    del t
+    assert st["splitters"] > 0
+    assert np.array_equal(np.sort(x).view(np.uint64), got)
