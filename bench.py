@@ -275,7 +275,7 @@ def main():
                     help="partition levels in one persistent launch, or one launch per level")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus above 1 is not supported", file=sys.stderr)
+        print("bench.py: runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
 
     driver = 2 if args.driver == "persistent" else 1
