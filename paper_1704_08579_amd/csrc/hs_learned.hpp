@@ -532,6 +532,42 @@ __device__ __forceinline__ uint32_t mw_bucket(const K *sd, uint32_t k, K x)
 
 constexpr int MW_ITEMS = 8;  // keys per thread per round of the histogram pass
 
+// Load the keys p0 + j*MW_NT + threadIdx.x (j < ITEMS) of the range
+// [p0, p0 + cnt) as order words, with bounds-checked buffer loads (a lane
+// past the end reads zero and moves no data): straight-line code, so the
+// next round's loads can be in flight while this round is processed.
+template <int F, bool SRC_IS_RAW, int ITEMS>
+__device__ __forceinline__ void mw_load(Raw raw, const typename KeyOf<F>::type *src, uint32_t p0, uint32_t cnt,
+                                        typename KeyOf<F>::type (&x)[ITEMS])
+{
+    using K = typename KeyOf<F>::type;
+    p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
+    cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)cnt);
+    if constexpr (SRC_IS_RAW && F == FMT_KV) {
+        const auto rk = tile_rsrc((const uint32_t *)raw.keys + p0, cnt * 4u);
+        const auto rv = tile_rsrc((const uint32_t *)raw.vals + p0, cnt * 4u);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t off = (uint32_t)(j * MW_NT + threadIdx.x) * 4u;
+            x[j] = enc_kv(rsrc_load32(rk, off), rsrc_load32(rv, off));
+        }
+    } else if constexpr (sizeof(K) == 4) {
+        const auto r = tile_rsrc((SRC_IS_RAW ? (const K *)raw.keys : src) + p0, cnt * 4u);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t v = rsrc_load32(r, (uint32_t)(j * MW_NT + threadIdx.x) * 4u);
+            x[j] = SRC_IS_RAW ? (K)enc_i32(v) : (K)v;
+        }
+    } else {
+        const auto r = tile_rsrc((SRC_IS_RAW ? (const K *)raw.keys : src) + p0, cnt * 8u);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t v = rsrc_load64(r, (uint32_t)(j * MW_NT + threadIdx.x) * 8u);
+            x[j] = SRC_IS_RAW ? (K)enc_f64(v) : (K)v;
+        }
+    }
+}
+
 // Pass 1: bucket sizes of every workgroup's chunk, bucket-major:
 // hist[b * G + w].
 template <int F, bool SRC_IS_RAW>
@@ -547,19 +583,23 @@ __global__ __launch_bounds__(MW_NT) void k_mw_hist(Raw raw, const typename KeyOf
     for (uint32_t i = threadIdx.x; i < nb; i += MW_NT) cnt[i] = 0;
     __syncthreads();
     const uint32_t b0 = blockIdx.x * chunk, b1 = min(n, b0 + chunk);
-    for (uint32_t base = b0; base < b1; base += MW_NT * MW_ITEMS) {
-        K x[MW_ITEMS];
-#pragma unroll
-        for (int j = 0; j < MW_ITEMS; ++j) {
-            const uint32_t i = base + j * MW_NT + threadIdx.x;
-            x[j] = i < b1 ? (SRC_IS_RAW ? raw_load<F>(raw, i) : src[i]) : K(0);
-        }
+    constexpr uint32_t STEP = MW_NT * MW_ITEMS;
+    K x[MW_ITEMS];
+    if (b0 < b1) mw_load<F, SRC_IS_RAW, MW_ITEMS>(raw, src, b0, min(STEP, b1 - b0), x);
+    for (uint32_t base = b0; base < b1; base += STEP) {
+        // the next round's loads first (an empty range after the last round)
+        K xn[MW_ITEMS];
+        const uint32_t nbase = base + STEP;
+        mw_load<F, SRC_IS_RAW, MW_ITEMS>(raw, src, nbase < b1 ? nbase : base, nbase < b1 ? min(STEP, b1 - nbase) : 0u,
+                                        xn);
 #pragma unroll
         for (int j = 0; j < MW_ITEMS; ++j) {
             const uint32_t i = base + j * MW_NT + threadIdx.x;
             const uint32_t bk = mw_bucket(sd, k, x[j]);
             if (i < b1) atomicAdd(&cnt[bk], 1u);
         }
+#pragma unroll
+        for (int j = 0; j < MW_ITEMS; ++j) x[j] = xn[j];
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += MW_NT) hist[(size_t)b * gridDim.x + blockIdx.x] = cnt[b];
@@ -624,6 +664,7 @@ __global__ __launch_bounds__(MW_NT) void k_mw_scatter(Raw raw, const typename Ke
 {
     using K = typename KeyOf<F>::type;
     constexpr int ITEMS = MW_TILE / MW_NT;
+    constexpr int STORES = ITEMS * ((DST_IS_RAW && F == FMT_KV) ? 2 : 1);
     __shared__ K sd[NBUCKET];
     __shared__ uint32_t cnt[NB_MAX], tbase[NB_MAX], run[NB_MAX];
     __shared__ K stage[MW_TILE];
@@ -632,23 +673,30 @@ __global__ __launch_bounds__(MW_NT) void k_mw_scatter(Raw raw, const typename Ke
     const uint32_t k = lc->k, nb = 2 * k + 1;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     mw_load_splitters(sd, dsplit, k);
-    for (uint32_t b = tid; b < nb; b += MW_NT) run[b] = start[b] + hist[(size_t)b * gridDim.x + blockIdx.x];
+    for (uint32_t b = tid; b < nb; b += MW_NT) {
+        run[b] = start[b] + hist[(size_t)b * gridDim.x + blockIdx.x];
+        cnt[b] = 0;
+    }
     const uint32_t c0 = blockIdx.x * chunk, c1 = min(n, c0 + chunk);
+    K x[ITEMS];
+    if (c0 < c1) mw_load<F, SRC_IS_RAW, ITEMS>(raw, src, c0, min((uint32_t)MW_TILE, c1 - c0), x);
+    wait_vmcnt<0>();  // both edges into the loop arrive with the tile loaded
+    __syncthreads();
     for (uint32_t t0 = c0; t0 < c1; t0 += MW_TILE) {
         const uint32_t cnt_t = min((uint32_t)MW_TILE, c1 - t0);
-        for (uint32_t b = tid; b < nb; b += MW_NT) cnt[b] = 0;
-        __syncthreads();
-        K x[ITEMS];
         uint32_t bk[ITEMS], rk[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t i = (uint32_t)(j * MW_NT + tid);
-            if (i < cnt_t) {
-                x[j] = SRC_IS_RAW ? raw_load<F>(raw, t0 + i) : src[t0 + i];
-                bk[j] = mw_bucket(sd, k, x[j]);
-                rk[j] = atomicAdd(&cnt[bk[j]], 1u);
-            }
+            bk[j] = mw_bucket(sd, k, x[j]);
+            rk[j] = 0;
+            if (i < cnt_t) rk[j] = atomicAdd(&cnt[bk[j]], 1u);
         }
+        // the next tile's loads (an empty range after the last tile)
+        K xn[ITEMS];
+        const uint32_t nt0 = t0 + MW_TILE;
+        mw_load<F, SRC_IS_RAW, ITEMS>(raw, src, nt0 < c1 ? nt0 : t0, nt0 < c1 ? min((uint32_t)MW_TILE, c1 - nt0) : 0u,
+                                      xn);
         __syncthreads();
         {  // exclusive scan of the tile's bucket counts: thread t owns buckets 2t, 2t+1
             const uint32_t c0v = (uint32_t)(2 * tid) < nb ? cnt[2 * tid] : 0u;
@@ -676,14 +724,24 @@ __global__ __launch_bounds__(MW_NT) void k_mw_scatter(Raw raw, const typename Ke
             }
         }
         __syncthreads();
-        for (uint32_t i = tid; i < cnt_t; i += MW_NT) {
+        // Lanes past the end of a partial tile store the tile's last key
+        // again at its own slot: a fixed number of stores, no branch.
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t i = min((uint32_t)(j * MW_NT + tid), cnt_t - 1);
             const uint32_t b = sbk[i];
             if constexpr (DST_IS_RAW) raw_store<F>(out, run[b] + (i - tbase[b]), stage[i]);
             else dst[run[b] + (i - tbase[b])] = stage[i];
         }
         __syncthreads();
-        for (uint32_t b = tid; b < nb; b += MW_NT) run[b] += cnt[b];
+        for (uint32_t b = tid; b < nb; b += MW_NT) {
+            run[b] += cnt[b];
+            cnt[b] = 0;
+        }
         __syncthreads();
+        wait_vmcnt<STORES>();  // the next tile's loads (older than the stores) are in
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) x[j] = xn[j];
     }
 }
 

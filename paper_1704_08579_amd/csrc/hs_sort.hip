@@ -398,7 +398,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
         HS_LAUNCH(k_ls_judge<K>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode);
         if (st) HS_HIP(hipEventRecord(lev[3], stream));
         uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
-        const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 4 - 1) / ((uint64_t)d->ncu * 4));
+        const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 8 - 1) / ((uint64_t)d->ncu * 8));
         if (chunk < cmin) chunk = cmin;
         chunk = (chunk + MW_TILE - 1) / MW_TILE * MW_TILE;
         const uint32_t G = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
@@ -1080,7 +1080,7 @@ int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_splitte
         // out of place: stage the input in the workspace, scatter back
         HS_HIP(hipMemcpyAsync(ws + o_copy, keys, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
         uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
-        const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 4 - 1) / ((uint64_t)d->ncu * 4));
+        const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 8 - 1) / ((uint64_t)d->ncu * 8));
         if (chunk < cmin) chunk = cmin;
         chunk = (chunk + MW_TILE - 1) / MW_TILE * MW_TILE;
         const uint32_t G = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
