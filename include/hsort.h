@@ -222,6 +222,7 @@ HS_API int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_
 typedef struct hs_plan hs_plan;
 HS_API int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_offsets, int64_t nseg,
                           const hs_opts *opts, hs_plan **plan);
+/* `stream` must belong to the device the plan was created on. */
 HS_API int hs_plan_exec(hs_plan *plan, void *stream);
 /* Waits for the plan's last replay on `stream` and reports the error word
  * its kernels left (HS_EINTERNAL if set). */
@@ -238,9 +239,9 @@ HS_API void hs_plan_destroy(hs_plan *plan);
  * HIP events (one warm-up and two timed runs each, fastest kept).  Every
  * candidate's output is compared on the device with the first candidate's:
  * all must be identical.  The best knobs go to *best (a copy of base with
- * them filled in) and are remembered per device, operation, driver and size
- * class (n and nseg rounded up to powers of two); a later call or a sort with
- * opts->autotune set reuses them.  Allocates a copy of the input. */
+ * them filled in) and are remembered per device, operation, method, driver
+ * and size class (n and nseg rounded up to powers of two); a later call or a
+ * sort with opts->autotune set reuses them.  Allocates a copy of the input. */
 typedef struct hs_tune_report {
     int32_t candidates;      /* configurations measured (0: taken from the cache) */
     int32_t outputs_equal;   /* 1 if every candidate produced the same bytes */

@@ -580,7 +580,7 @@ int ceil_log2(int64_t x)
     return l;
 }
 
-using TuneKey = std::tuple<int, int, int, int, int>;  // device, op, driver, log2 n, log2 (nseg + 1)
+using TuneKey = std::tuple<int, int, int, int, int, int>;  // device, op, method, driver, log2 n, log2 (nseg + 1)
 std::map<TuneKey, std::tuple<int, int, int>> g_tuned;  // -> local_T, leaf, pivot_rule
 std::mutex g_tune_mu;
 
@@ -590,7 +590,7 @@ TuneKey tune_key(int op, const hs_opts *o, int64_t n, int64_t nseg)
 {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    return TuneKey{dev, op, tuned_driver(o), ceil_log2(n), ceil_log2(nseg + 1)};
+    return TuneKey{dev, op, o ? o->method : HS_METHOD_PLAIN, tuned_driver(o), ceil_log2(n), ceil_log2(nseg + 1)};
 }
 
 struct DevBuf {
