@@ -11,10 +11,13 @@
  * Conventions shared by every entry point:
  *   - Every array pointer is a DEVICE pointer (hipMalloc memory, or e.g. a
  *     torch tensor's data_ptr()).  `stream` is a hipStream_t; NULL means the
- *     null stream.  Work is enqueued on `stream`; the level-synchronous
- *     driver reads small counters back between launches, so the call returns
- *     after the partition levels have been issued, with the final local-sort
- *     launch still in flight on `stream`.
+ *     null stream.  Work is enqueued on `stream`.  The sorts read their
+ *     control block back at the end (and, with the host-driven level loop,
+ *     after each batch of levels) to report errors raised inside kernels,
+ *     so a sort returns once its work on `stream` has completed; while the
+ *     stream is being captured into a graph nothing is read back (see the
+ *     plan entry points).  hs_partition_i32 and the learned method's
+ *     kernel entry points return as soon as their work is enqueued.
  *   - Sorts are in place, ascending and not stable: the paper's partition
  *     and bitonic network are not stable (Sec. II-A).  Equal keys of the
  *     key/value sort come out ordered by value (a valid, deterministic
