@@ -166,6 +166,33 @@ __device__ __forceinline__ uint32_t mask_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// base + mask_below(m), the base riding in mbcnt's accumulator.
+__device__ __forceinline__ uint32_t mbcnt_add(uint64_t m, uint32_t base)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
+}
+
+// The lanes whose predicate holds, as a wave-uniform 64-bit mask.
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__builtin_popcountll(m); }
+
+// a in the lanes of mask m, b elsewhere: one v_cndmask.  Written out because
+// the compiler otherwise turns a select between mbcnt results into branches
+// under the exec mask, one per arm.
+__device__ __forceinline__ uint32_t lane_select(uint64_t m, uint32_t a, uint32_t b)
+{
+    uint32_t d;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(d) : "v"(b), "v"(a), "s"(m));
+    return d;
+}
+
+// Lanes [0, k) (every lane for k >= 64).
+__device__ __forceinline__ uint64_t lanes_below(uint32_t k) { return k >= 64u ? ~0ull : ((1ull << k) - 1ull); }
+
+// Sum of v over the wave, in every lane.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return lane_bcast(wave_incl_scan(v), WAVE - 1); }
+
 // ---------------------------------------------------------------- static loops
 
 template <int B, int E, typename Fn>

@@ -488,7 +488,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
         using LC = LocalCfg<K>;
         if (st) HS_HIP(hipEventRecord(lev[0], stream));
         HS_LAUNCH((k_small<F, LC::LEAF>), d->ncu * 8, 256, stream, ctl, tasks, buf[0], buf[1], raw, L.task_cap);
-        HS_LAUNCH((k_local<F, LC::NT, LC::T, LC::LEAF, LC::WPC>), d->ncu * LC::WPC, LC::NT, stream, ctl, tasks,
+        HS_LAUNCH((k_local<F, LC::NT, LC::T, LC::LW, LC::WPC>), d->ncu * LC::WPC, LC::NT, stream, ctl, tasks,
                   buf[0], buf[1], raw, local_rule, L.task_cap);
         if (st) HS_HIP(hipEventRecord(lev[1], stream));
     }
