@@ -16,6 +16,7 @@
 
 #include "hs_kernels.hpp"
 #include "hs_learned.hpp"
+#include "hs_local.hpp"
 #include "hsort.h"
 
 namespace {
