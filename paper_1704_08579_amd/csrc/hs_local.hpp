@@ -27,7 +27,7 @@ namespace hs {
 // down to 512 keys for 64-bit words (measured: 512 beats 256 and 128), and
 // 32-bit words go to the network from a span (1024 keys) on.
 template <typename K> struct LocalCfg;
-template <> struct LocalCfg<uint32_t> { static constexpr int T = 8192, NT = 512, LEAF = 1024, LW = 1024, WPC = 2; };
+template <> struct LocalCfg<uint32_t> { static constexpr int T = 8192, NT = 512, LEAF = 1024, LW = 1024, WPC = 4; };
 template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 512, LEAF = 512, LW = 512, WPC = 2; };
 
 // Sort the keys of one wave's registers (any load order) with the smallest
