@@ -182,8 +182,12 @@ __device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__builti
 // under the exec mask, one per arm.
 __device__ __forceinline__ uint32_t lane_select(uint64_t m, uint32_t a, uint32_t b)
 {
+    // the mask is wave-uniform; readfirstlane keeps it in scalar registers
+    // whatever the compiler concluded about it
+    const uint64_t ms = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(m >> 32)) << 32) |
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)m);
     uint32_t d;
-    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(d) : "v"(b), "v"(a), "s"(m));
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(d) : "v"(b), "v"(a), "s"(ms));
     return d;
 }
 

@@ -115,6 +115,8 @@ __device__ __forceinline__ void wave_qsort(K *sk, uint32_t b, uint32_t e, int ru
     uint32_t stk = 0;
     int sp = 0;
     for (;;) {
+        b = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);  // uniform: row masks stay scalar
+        e = (uint32_t)__builtin_amdgcn_readfirstlane((int)e);
         const uint32_t s = e - b;
         if (LW >= KR * WAVE || s <= (uint32_t)LW) {
             if (s >= 2)
@@ -220,14 +222,25 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
     const uint32_t ntask = min(ctl->ntask, task_cap);
     auto lds_rd = [&](uint32_t p) { return sk[p]; };
 
-    // queued ranges [0, cnt), claimed through s_qnext
+    // queued ranges [0, cnt), claimed through s_qnext, largest first when the
+    // list fits a wave (every wave sorts the same claim order: (size, index)
+    // words through the 64-lane network, so the k-th claim is lane 63 - k)
     auto drain = [&](uint32_t cnt) {
+        const bool lpt = cnt <= (uint32_t)WAVE;
+        uint32_t ord[1] = {0u};
+        if (lpt) {
+            if ((uint32_t)lane < cnt) {
+                const uint32_t t = qr[lane];
+                ord[0] = (((t >> 16) - (t & 0xFFFFu)) << 6) | (uint32_t)lane;
+            }
+            bitonic_wave<1>(ord, lane);
+        }
         for (;;) {
             uint32_t k = 0;
             if (lane == 0) k = atomicAdd(&s_qnext, 1u);
             k = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
             if (k >= cnt) break;
-            const uint32_t t = qr[k];
+            const uint32_t t = qr[lpt ? (lane_bcast(ord[0], WAVE - 1 - (int)k) & (WAVE - 1)) : k];
             wave_qsort<KPT, LW, K>(sk, t & 0xFFFFu, t >> 16, rule, lane);
         }
     };
