@@ -536,7 +536,6 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
     using K = typename KeyOf<F>::type;
     constexpr int NT = PartCfg<K>::NT, TILE = PartCfg<K>::TILE, ITEMS = TILE / NT;
     constexpr int NW = NT / WAVE;
-    static_assert(ITEMS <= 32, "item masks are 32-bit");
     static_assert(TILE < 65536, "per-tile counts are 16-bit");
 
     if (nseg == 0) return;
@@ -544,9 +543,10 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
         const Seg<K> last = segs[nseg - 1];
         ntiles = min(ntiles, last.tile0 + seg_tiles<K>(last.b, last.e));
     }
-    const uint32_t per = (ntiles + nwg - 1) / nwg;
-    uint32_t t = wg * per;
-    const uint32_t tend = min(ntiles, t + per);
+    // the workgroup's tile range is uniform: keep it (and the tile loop) scalar
+    const uint32_t per = (uint32_t)__builtin_amdgcn_readfirstlane((int)((ntiles + nwg - 1) / nwg));
+    uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)(wg * per));
+    const uint32_t tend = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(ntiles, t + per));
     if (t >= tend) return;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
 
@@ -574,8 +574,10 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
         TileLoc<K> L;
         L.s = s_next;
         const uint32_t a = sg_next.b / TILE + (tt - sg_next.tile0);
-        L.p0 = max(sg_next.b, a * TILE);
-        L.cnt = min(sg_next.e, (a + 1) * TILE) - L.p0;
+        // the tile's place is the same in every lane: readfirstlane keeps it
+        // (and the full-tile branch) scalar
+        L.p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)max(sg_next.b, a * TILE));
+        L.cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)(min(sg_next.e, (a + 1) * TILE) - L.p0));
         L.full = L.cnt == (uint32_t)TILE;
         return L;
     };
@@ -625,20 +627,30 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
 
     for (; t < tend; ++t) {
         const bool more = t + 1 < tend;
+        // "<= pivot" (or "< pivot" for a strict segment) as one compare against
+        // the largest key still on the low side; none is when strict and the
+        // pivot is the least key
         const bool strict = (sg.flags & SEG_STRICT) != 0;
-        const K piv = sg.piv;
-        uint32_t lemask = 0, vmask = 0;
+        const bool none = strict && sg.piv == K(0);
+        const K lim = strict ? sg.piv - K(1) : sg.piv;
+        auto low = [&](K v) { return !none && v <= lim; };
+        // lanes past the end of a partial tile hold no key: item j is one iff
+        // tid < cnt - j*NT (a scalar bound per item)
+        auto valid = [&](int j) { return (int)tid < (int)L.cnt - j * NT; };
+        uint32_t cle = 0, cva = ITEMS;
+        if (L.full) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const bool valid = (uint32_t)(j * NT + tid) < L.cnt;
-            const bool le = strict ? (x[j] < piv) : (x[j] <= piv);
-            if (valid) {
-                vmask |= 1u << j;
-                if (le) lemask |= 1u << j;
+            for (int j = 0; j < ITEMS; ++j) cle += (uint32_t)low(x[j]);
+        } else {
+            cva = 0;
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const bool v = valid(j);
+                cle += (uint32_t)(v && low(x[j]));
+                cva += (uint32_t)v;
             }
         }
-        const uint32_t cle = (uint32_t)__builtin_popcount(lemask);
-        const uint32_t cgt = (uint32_t)__builtin_popcount(vmask) - cle;
+        const uint32_t cgt = cva - cle;
         const uint32_t code = cle | (cgt << 16);
         const uint32_t incl = wave_incl_scan(code);
         if (lane == WAVE - 1) wsum[wave] = incl;
@@ -672,12 +684,23 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
         K xn[ITEMS];
         load(Ln, xn);
         asm volatile("" ::: "memory");  // keep the use of the atomic's result below the loads
+        // compaction into the staging area: a running slot per side
         uint32_t lp = excl & 0xFFFFu, gp = tot_le + (excl >> 16);
+        if (L.full) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            if (vmask & (1u << j)) {
-                if (lemask & (1u << j)) stage[lp++] = x[j];
-                else stage[gp++] = x[j];
+            for (int j = 0; j < ITEMS; ++j) {
+                const bool l = low(x[j]);
+                stage[l ? lp : gp] = x[j];
+                lp += (uint32_t)l;
+                gp += (uint32_t)!l;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const bool v = valid(j), l = low(x[j]);
+                if (v) stage[l ? lp : gp] = x[j];
+                lp += (uint32_t)(v && l);
+                gp += (uint32_t)(v && !l);
             }
         }
         if (tid == 0) {
