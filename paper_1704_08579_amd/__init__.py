@@ -19,7 +19,8 @@ import ctypes
 import os
 
 __all__ = ["sort_", "sort_kv_", "partition_", "sort_segmented_", "workspace_size", "Stats", "Opts",
-           "lib", "LIB_PATH", "HSortError"]
+           "learned_opts", "mlp_forward", "mlp_grad", "mlp_train", "multiway_partition_", "Plan", "autotune",
+           "TuneReport", "lib", "LIB_PATH", "HSortError"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhsort.so")
 
