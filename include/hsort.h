@@ -59,15 +59,17 @@ typedef enum hs_status {
     HS_EINTERNAL = -6     /* a kernel reported a broken invariant */
 } hs_status;
 
-/* Operation codes for hs_workspace_size(). */
+/* Operation codes for hs_workspace_size(), plans and the autotuner. */
 enum { HS_OP_SORT_I32 = 0, HS_OP_SORT_F64 = 1, HS_OP_SORT_KV_I32 = 2,
-       HS_OP_PARTITION_I32 = 3, HS_OP_SORT_SEGMENTED_I32 = 4 };
+       HS_OP_PARTITION_I32 = 3, HS_OP_SORT_SEGMENTED_I32 = 4,
+       HS_OP_SORT_U32 = 5, HS_OP_SORT_I64 = 6 };
 
 /* Pivot rules (hs_opts.pivot_rule). */
 enum { HS_PIVOT_AUTO = 0,     /* the tuned default */
        HS_PIVOT_MEDIAN3 = 1,  /* median of first, middle, last (Sec. IV-A) */
        HS_PIVOT_NINTHER = 2,  /* median of three medians of three */
-       HS_PIVOT_SAMPLE = 3 }; /* median of a 31-element strided sample */
+       HS_PIVOT_SAMPLE = 3 }; /* global levels: lower median of 64 evenly spaced keys
+                                 (ninther below 256 keys and on chip) */
 
 /* Sort methods (hs_opts.method). */
 enum { HS_METHOD_PLAIN = 0,     /* the paper's method: one pivot per partition */
@@ -144,6 +146,22 @@ HS_API int hs_sort_i32(int32_t *keys, int64_t n, const hs_opts *opts, hs_stats *
  * bits, permuted. */
 HS_API int hs_sort_f64(double *keys, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream);
 
+/* Sort n uint32 keys in place (unsigned order; the same kernels as int32). */
+HS_API int hs_sort_u32(uint32_t *keys, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream);
+
+/* Sort n int64 keys in place (two's-complement order; the same kernels as
+ * float64, with the sign bit flipped instead of the totalOrder map). */
+HS_API int hs_sort_i64(int64_t *keys, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream);
+
+/* Stable argsort of n int32 keys: keys_out receives the keys in ascending
+ * order and idx_out[i] the position in `keys` of keys_out[i]; equal keys keep
+ * their input order.  It is the key/value sort (Sec. III-D) with the indices
+ * 0..n-1 as values: the (key, value) order word orders equal keys by index,
+ * so the output is unique.  keys_out may be `keys` (in place) or a separate
+ * array; idx_out must not overlap either.  All three are DEVICE pointers. */
+HS_API int hs_argsort_i32(const int32_t *keys, int32_t *keys_out, int32_t *idx_out, int64_t n,
+                          const hs_opts *opts, hs_stats *stats, void *stream);
+
 /* Sort n (key, value) pairs held as two separate arrays (Sec. III-D) by key,
  * in place; every value moves with its key.  keys and vals must not
  * overlap. */
@@ -214,7 +232,7 @@ HS_API int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_
 /* ---- Plans: one call captured into a HIP graph ------------------------
  *
  * hs_plan_create records one sort of the given buffers (op HS_OP_SORT_I32,
- * _F64, _KV_I32 or _SORT_SEGMENTED_I32; vals only for key/value, d_offsets
+ * _U32, _I64, _F64, _KV_I32 or _SORT_SEGMENTED_I32; vals only for key/value, d_offsets
  * and nseg only for segmented) into a graph: the partition levels run in the
  * persistent driver, every clear is a kernel, and the plan owns its
  * workspace, so replaying it needs no host work beyond hipGraphLaunch.

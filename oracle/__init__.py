@@ -47,6 +47,9 @@ def lib() -> ctypes.CDLL:
             ("oracle_sort_i32", [_P, _I64, _I64], _I64),
             ("oracle_sort_f64", [_P, _I64, _I64], _I64),
             ("oracle_sort_kv_i32", [_P, _P, _I64, _I64], _I64),
+            ("oracle_sort_u32", [_P, _I64, _I64], _I64),
+            ("oracle_sort_i64", [_P, _I64, _I64], _I64),
+            ("oracle_argsort_i32", [_P, _P, _I64, _I64], _I64),
             ("oracle_sort_segmented_i32", [_P, _P, _I64, _I64], _I64),
             ("oracle_partition_le_i32", [_P, _I64, ctypes.c_int32], _I64),
             ("oracle_simd_partition_i32", [_P, _I64, ctypes.c_int32, ctypes.c_int], _I64),
@@ -105,6 +108,29 @@ def sort_f64(keys: np.ndarray, leaf: int = LEAF) -> np.ndarray:
     if lib().oracle_sort_f64(_ptr(a), a.size, leaf) < 0:
         raise MemoryError("oracle_sort_f64")
     return a.view(np.float64)
+
+
+def sort_u32(keys: np.ndarray, leaf: int = LEAF) -> np.ndarray:
+    a = np.ascontiguousarray(keys, dtype=np.uint32).copy()
+    if lib().oracle_sort_u32(_ptr(a), a.size, leaf) < 0:
+        raise MemoryError("oracle_sort_u32")
+    return a
+
+
+def sort_i64(keys: np.ndarray, leaf: int = LEAF) -> np.ndarray:
+    a = np.ascontiguousarray(keys, dtype=np.int64).copy()
+    if lib().oracle_sort_i64(_ptr(a), a.size, leaf) < 0:
+        raise MemoryError("oracle_sort_i64")
+    return a
+
+
+def argsort_i32(keys: np.ndarray, leaf: int = LEAF):
+    """Stable argsort: (sorted keys, int32 positions of them in `keys`)."""
+    k = np.ascontiguousarray(keys, dtype=np.int32).copy()
+    idx = np.empty(k.size, dtype=np.int32)
+    if lib().oracle_argsort_i32(_ptr(k), _ptr(idx), k.size, leaf) < 0:
+        raise MemoryError("oracle_argsort_i32")
+    return k, idx
 
 
 def sort_kv_i32(keys: np.ndarray, vals: np.ndarray, leaf: int = LEAF):

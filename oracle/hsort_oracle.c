@@ -57,6 +57,13 @@ typedef struct {
 static uint64_t key_i32(int32_t x) { return (uint64_t)((uint32_t)x ^ 0x80000000u); }
 static int32_t unkey_i32(uint64_t k) { return (int32_t)((uint32_t)k ^ 0x80000000u); }
 
+/* uint32 -> order key: the value itself.  int64 -> order key: the sign bit
+ * flipped, as for int32 (INT64_MIN -> 0, 0 -> 2^63). */
+static uint64_t key_u32(uint32_t x) { return (uint64_t)x; }
+static uint32_t unkey_u32(uint64_t k) { return (uint32_t)k; }
+static uint64_t key_i64(int64_t x) { return (uint64_t)x ^ 0x8000000000000000ull; }
+static int64_t unkey_i64(uint64_t k) { return (int64_t)(k ^ 0x8000000000000000ull); }
+
 /* float64 bits -> totalOrder key.  Negative numbers (sign bit set) have all
  * bits inverted, so a larger magnitude gives a smaller key and -NaN lands
  * below -inf; non-negative numbers get the sign bit set, so they sit above
@@ -219,6 +226,54 @@ int64_t oracle_sort_f64(uint64_t *bits, int64_t n, int64_t leaf)
     }
     int64_t d = sort_elems(a, n, leaf);
     for (int64_t i = 0; i < n; ++i) bits[i] = oracle_unkey_f64(a[i].key);
+    free(a);
+    return d;
+}
+
+int64_t oracle_sort_u32(uint32_t *keys, int64_t n, int64_t leaf)
+{
+    elem_t *a = (elem_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(elem_t));
+    if (!a) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        a[i].key = key_u32(keys[i]);
+        a[i].val = 0;
+    }
+    int64_t d = sort_elems(a, n, leaf);
+    for (int64_t i = 0; i < n; ++i) keys[i] = unkey_u32(a[i].key);
+    free(a);
+    return d;
+}
+
+int64_t oracle_sort_i64(int64_t *keys, int64_t n, int64_t leaf)
+{
+    elem_t *a = (elem_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(elem_t));
+    if (!a) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        a[i].key = key_i64(keys[i]);
+        a[i].val = 0;
+    }
+    int64_t d = sort_elems(a, n, leaf);
+    for (int64_t i = 0; i < n; ++i) keys[i] = unkey_i64(a[i].key);
+    free(a);
+    return d;
+}
+
+/* Stable argsort by definition: sort the pairs (key, position) -- as one
+ * order key, the int32 key's order word above the position -- and read the
+ * positions back.  n < 2^31. */
+int64_t oracle_argsort_i32(int32_t *keys, int32_t *idx, int64_t n, int64_t leaf)
+{
+    elem_t *a = (elem_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(elem_t));
+    if (!a) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        a[i].key = (key_i32(keys[i]) << 32) | (uint64_t)i;
+        a[i].val = 0;
+    }
+    int64_t d = sort_elems(a, n, leaf);
+    for (int64_t i = 0; i < n; ++i) {
+        keys[i] = unkey_i32(a[i].key >> 32);
+        idx[i] = (int32_t)(uint32_t)a[i].key;
+    }
     free(a);
     return d;
 }

@@ -18,14 +18,14 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["sort_", "sort_kv_", "partition_", "sort_segmented_", "workspace_size", "Stats", "Opts",
+__all__ = ["sort_", "sort_kv_", "argsort", "partition_", "sort_segmented_", "workspace_size", "Stats", "Opts",
            "learned_opts", "mlp_forward", "mlp_grad", "mlp_train", "multiway_partition_", "Plan", "autotune",
            "TuneReport", "lib", "LIB_PATH", "HSortError"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhsort.so")
 
 HS_OK = 0
-OP_SORT_I32, OP_SORT_F64, OP_SORT_KV_I32, OP_PARTITION_I32, OP_SORT_SEGMENTED_I32 = range(5)
+OP_SORT_I32, OP_SORT_F64, OP_SORT_KV_I32, OP_PARTITION_I32, OP_SORT_SEGMENTED_I32, OP_SORT_U32, OP_SORT_I64 = range(7)
 PIVOT_AUTO, PIVOT_MEDIAN3, PIVOT_NINTHER, PIVOT_SAMPLE = range(4)
 
 _STATUS = {0: "HS_OK", -1: "HS_EINVAL", -2: "HS_ENOMEM", -3: "HS_EHIP", -4: "HS_EWORKSPACE",
@@ -77,6 +77,9 @@ _SIGS = {
     "hs_sort_i32": ([_P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_f64": ([_P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_kv_i32": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_sort_u32": ([_P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_sort_i64": ([_P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_argsort_i32": ([_P, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_partition_i32": ([_P, _I64, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
     "hs_sort_segmented_i32": ([_P, _I64, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_workspace_size": ([ctypes.c_int, _I64, _I64, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -144,16 +147,45 @@ def _opts_ptr(opts):
     return None if opts is None else ctypes.addressof(opts)
 
 
-def sort_(t, opts: Opts | None = None, stats: bool = False):
-    """Sort a 1-D int32 or float64 CUDA tensor in place (float64 by IEEE totalOrder)."""
+def _sort_fn(dtype):
     torch = _torch()
-    _require(t, (torch.int32, torch.float64), "t")
+    return {torch.int32: "hs_sort_i32", torch.float64: "hs_sort_f64", torch.uint32: "hs_sort_u32",
+            torch.int64: "hs_sort_i64"}[dtype]
+
+
+def sort_(t, opts: Opts | None = None, stats: bool = False):
+    """Sort a 1-D int32, uint32, int64 or float64 CUDA tensor in place
+    (float64 by IEEE totalOrder)."""
+    torch = _torch()
+    _require(t, (torch.int32, torch.float64, torch.uint32, torch.int64), "t")
     st = Stats() if stats else None
     with torch.cuda.device(t.device):
-        fn = lib().hs_sort_i32 if t.dtype == torch.int32 else lib().hs_sort_f64
+        fn = getattr(lib(), _sort_fn(t.dtype))
         _check(fn(t.data_ptr(), t.numel(), _opts_ptr(opts), None if st is None else ctypes.addressof(st),
                   _stream_handle(t)))
     return st.as_dict() if st is not None else t
+
+
+def argsort(keys, opts: Opts | None = None, stats: bool = False, out=None):
+    """Stable argsort of a 1-D int32 CUDA tensor: returns (sorted keys, int32
+    indices) with keys[idx] == sorted keys and equal keys in input order.
+    `keys` is left as it is unless out=(keys, idx) names it."""
+    torch = _torch()
+    _require(keys, (torch.int32,), "keys")
+    if out is None:
+        ko = torch.empty_like(keys)
+        idx = torch.empty_like(keys)
+    else:
+        ko, idx = out
+        _require(ko, (torch.int32,), "out[0]")
+        _require(idx, (torch.int32,), "out[1]")
+        if ko.numel() != keys.numel() or idx.numel() != keys.numel():
+            raise ValueError("out tensors must have the size of keys")
+    st = Stats() if stats else None
+    with torch.cuda.device(keys.device):
+        _check(lib().hs_argsort_i32(keys.data_ptr(), ko.data_ptr(), idx.data_ptr(), keys.numel(), _opts_ptr(opts),
+                                    None if st is None else ctypes.addressof(st), _stream_handle(keys)))
+    return (ko, idx, st.as_dict()) if st is not None else (ko, idx)
 
 
 def sort_kv_(keys, vals, opts: Opts | None = None, stats: bool = False):
@@ -300,8 +332,9 @@ def _sort_args(keys, vals=None, offsets=None):
         if keys.numel() != vals.numel() or keys.device != vals.device:
             raise ValueError("keys and vals must have the same size and device")
         return OP_SORT_KV_I32, keys.data_ptr(), vals.data_ptr(), keys.numel(), None, 0
-    _require(keys, (torch.int32, torch.float64), "keys")
-    op = OP_SORT_I32 if keys.dtype == torch.int32 else OP_SORT_F64
+    _require(keys, (torch.int32, torch.float64, torch.uint32, torch.int64), "keys")
+    op = {torch.int32: OP_SORT_I32, torch.float64: OP_SORT_F64, torch.uint32: OP_SORT_U32,
+          torch.int64: OP_SORT_I64}[keys.dtype]
     return op, keys.data_ptr(), None, keys.numel(), None, 0
 
 

@@ -1,8 +1,9 @@
 // hs_device.hpp -- device primitives of the gfx950 hybrid sort.
 //
-//  * order-key codecs: the caller's int32 / float64 / (int32 key, int32 value)
-//    formats are mapped to unsigned words whose unsigned order is the key
-//    order, so every kernel compares plain unsigned integers;
+//  * order-key codecs: the caller's int32 / uint32 / int64 / float64 /
+//    (int32 key, int32 value) formats are mapped to unsigned words whose
+//    unsigned order is the key order, so every kernel compares plain
+//    unsigned integers;
 //  * wavefront (64-lane) scan and lane shuffles;
 //  * the same-direction bitonic network of the paper (Sec. II-A, Fig. 2
 //    caption; Sec. III-A, Algorithms 1 and 2) held in VGPRs of one wave.
@@ -18,10 +19,14 @@ namespace hs {
 
 constexpr int WAVE = 64;
 
-enum Fmt : int { FMT_I32 = 0, FMT_F64 = 1, FMT_KV = 2 };
+enum Fmt : int { FMT_I32 = 0, FMT_F64 = 1, FMT_KV = 2, FMT_U32 = 3, FMT_I64 = 4 };
 
 template <int F> struct KeyOf { using type = uint64_t; };
 template <> struct KeyOf<FMT_I32> { using type = uint32_t; };
+template <> struct KeyOf<FMT_U32> { using type = uint32_t; };
+
+// Bytes of one key in the caller's key array.
+template <int F> constexpr int raw_key_bytes() { return F == FMT_F64 || F == FMT_I64 ? 8 : 4; }
 
 // The caller's arrays, in the caller's format.
 struct Raw {
@@ -31,9 +36,10 @@ struct Raw {
 
 // ---------------------------------------------------------------- codecs
 //
-// int32: flipping the sign bit maps two's-complement order onto unsigned
-// order.  float64: IEEE 754-2008 totalOrder -- negative values (sign bit
-// set) have every bit inverted, non-negative values get the sign bit set.
+// int32 and int64: flipping the sign bit maps two's-complement order onto
+// unsigned order; uint32 keys are their own order words.  float64: IEEE
+// 754-2008 totalOrder -- negative values (sign bit set) have every bit
+// inverted, non-negative values get the sign bit set.
 // key/value: the int32 key's order word in the high half and the value's
 // bits in the low half, so a pair moves as one word and ties between equal
 // keys are broken by value (the method is unstable, so any tie order is a
@@ -53,16 +59,26 @@ __device__ __forceinline__ uint64_t enc_kv(uint32_t key, uint32_t val)
 {
     return ((uint64_t)enc_i32(key) << 32) | val;
 }
+__device__ __forceinline__ uint64_t enc_i64(uint64_t b) { return b ^ 0x8000000000000000ull; }
+__device__ __forceinline__ uint64_t dec_i64(uint64_t k) { return k ^ 0x8000000000000000ull; }
+
+// Order word of one key of a single-array format, from its raw bits.
+template <int F> __device__ __forceinline__ typename KeyOf<F>::type enc_word(typename KeyOf<F>::type b)
+{
+    if constexpr (F == FMT_I32) return enc_i32(b);
+    else if constexpr (F == FMT_U32) return b;
+    else if constexpr (F == FMT_F64) return enc_f64(b);
+    else return enc_i64(b);
+}
 
 template <int F>
 __device__ __forceinline__ typename KeyOf<F>::type raw_load(const Raw &r, uint32_t i)
 {
-    if constexpr (F == FMT_I32) {
-        return enc_i32(((const uint32_t *)r.keys)[i]);
-    } else if constexpr (F == FMT_F64) {
-        return enc_f64(((const uint64_t *)r.keys)[i]);
-    } else {
+    if constexpr (F == FMT_KV) {
         return enc_kv(((const uint32_t *)r.keys)[i], (uint32_t)r.vals[i]);
+    } else {
+        using K = typename KeyOf<F>::type;
+        return enc_word<F>(((const K *)r.keys)[i]);
     }
 }
 
@@ -71,8 +87,12 @@ __device__ __forceinline__ void raw_store(const Raw &r, uint32_t i, typename Key
 {
     if constexpr (F == FMT_I32) {
         ((uint32_t *)r.keys)[i] = dec_i32(k);
+    } else if constexpr (F == FMT_U32) {
+        ((uint32_t *)r.keys)[i] = k;
     } else if constexpr (F == FMT_F64) {
         ((uint64_t *)r.keys)[i] = dec_f64(k);
+    } else if constexpr (F == FMT_I64) {
+        ((uint64_t *)r.keys)[i] = dec_i64(k);
     } else {
         ((uint32_t *)r.keys)[i] = dec_i32((uint32_t)(k >> 32));
         r.vals[i] = (int32_t)(uint32_t)k;

@@ -601,14 +601,14 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t v = rsrc_load32(r, (uint32_t)(j * NT + tid) * 4u);
-                x[j] = SRC_IS_RAW ? (K)enc_i32(v) : (K)v;
+                x[j] = SRC_IS_RAW ? enc_word<F>((K)v) : (K)v;
             }
         } else {
             const auto r = tile_rsrc((SRC_IS_RAW ? (const K *)raw.keys : src) + L.p0, L.cnt * 8u);
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
                 const uint64_t v = rsrc_load64(r, (uint32_t)(j * NT + tid) * 8u);
-                x[j] = SRC_IS_RAW ? (K)enc_f64(v) : (K)v;
+                x[j] = SRC_IS_RAW ? enc_word<F>((K)v) : (K)v;
             }
         }
     };
@@ -940,6 +940,12 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_levels
 __global__ void k_zero_words(uint32_t *p, uint32_t nwords)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// v[i] = i (the indices an argsort carries as values).
+__global__ void k_iota(int32_t *v, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = (int32_t)i;
 }
 
 // Number of 32-bit words where a and b differ, added to *count (one atomic

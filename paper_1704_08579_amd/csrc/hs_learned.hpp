@@ -77,6 +77,20 @@ template <> struct LearnKey<FMT_I32> {
     static __device__ __forceinline__ K word(S s) { return s; }
     static __device__ __forceinline__ double value(S s) { return (double)(int32_t)dec_i32(s); }
 };
+template <> struct LearnKey<FMT_U32> {
+    using K = uint32_t;
+    using S = uint32_t;
+    static __device__ __forceinline__ S search(K k) { return k; }
+    static __device__ __forceinline__ K word(S s) { return s; }
+    static __device__ __forceinline__ double value(S s) { return (double)s; }
+};
+template <> struct LearnKey<FMT_I64> {
+    using K = uint64_t;
+    using S = uint64_t;
+    static __device__ __forceinline__ S search(K k) { return k; }
+    static __device__ __forceinline__ K word(S s) { return s; }
+    static __device__ __forceinline__ double value(S s) { return (double)(long long)dec_i64(s); }
+};
 template <> struct LearnKey<FMT_KV> {
     using K = uint64_t;
     using S = uint32_t;
@@ -103,7 +117,7 @@ __global__ void k_ls_sample(Raw raw, uint32_t n, uint64_t seed, uint32_t m, Raw 
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     const uint32_t i = (uint32_t)__umul64hi(splitmix64_at(seed, k), (uint64_t)n);
-    if constexpr (F == FMT_F64) {
+    if constexpr (raw_key_bytes<F>() == 8) {
         ((uint64_t *)out.keys)[k] = ((const uint64_t *)raw.keys)[i];
     } else {
         ((uint32_t *)out.keys)[k] = ((const uint32_t *)raw.keys)[i];
@@ -557,14 +571,14 @@ __device__ __forceinline__ void mw_load(Raw raw, const typename KeyOf<F>::type *
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t v = rsrc_load32(r, (uint32_t)(j * MW_NT + threadIdx.x) * 4u);
-            x[j] = SRC_IS_RAW ? (K)enc_i32(v) : (K)v;
+            x[j] = SRC_IS_RAW ? enc_word<F>((K)v) : (K)v;
         }
     } else {
         const auto r = tile_rsrc((SRC_IS_RAW ? (const K *)raw.keys : src) + p0, cnt * 8u);
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint64_t v = rsrc_load64(r, (uint32_t)(j * MW_NT + threadIdx.x) * 8u);
-            x[j] = SRC_IS_RAW ? (K)enc_f64(v) : (K)v;
+            x[j] = SRC_IS_RAW ? enc_word<F>((K)v) : (K)v;
         }
     }
 }

@@ -184,7 +184,7 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParam
         // The training sample is sorted by a nested plain sort with its own
         // sub-workspace.
         const Layout S = make_layout<K>(op, P.m, 1, T);
-        const size_t rk = op == HS_OP_SORT_F64 ? 8 : 4;
+        const size_t rk = op == HS_OP_SORT_F64 || op == HS_OP_SORT_I64 ? 8 : 4;
         L.smp_k = take((size_t)P.m * rk);
         if (op == HS_OP_SORT_KV_I32) L.smp_v = take((size_t)P.m * 4);
         L.sub = take(S.total);
@@ -253,12 +253,20 @@ int check_learn(const hs_opts *o)
     return HS_OK;
 }
 
+// The sort operation of a key format (whole arrays).
+template <int F> constexpr int op_of()
+{
+    return F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : F == FMT_KV ? HS_OP_SORT_KV_I32
+         : F == FMT_U32 ? HS_OP_SORT_U32 : HS_OP_SORT_I64;
+}
+
 int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
 {
     int rc = check_learn(o);
     if (rc) return rc;
     switch (op) {
     case HS_OP_SORT_I32:
+    case HS_OP_SORT_U32:
     case HS_OP_SORT_SEGMENTED_I32:
         *L = make_layout<uint32_t>(op, n, nseg, local_limit<uint32_t>(o), learn_params(o, n, op));
         return HS_OK;
@@ -266,6 +274,7 @@ int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
         *L = make_layout<uint32_t>(op, n, nseg, 0);
         return HS_OK;
     case HS_OP_SORT_F64:
+    case HS_OP_SORT_I64:
     case HS_OP_SORT_KV_I32:
         *L = make_layout<uint64_t>(op, n, nseg, local_limit<uint64_t>(o), learn_params(o, n, op));
         return HS_OK;
@@ -379,9 +388,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
         // splitmix64(seed + 2)
         HS_LAUNCH(k_ls_sample<F>, (P.m + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed, P.m, smp);
         HS_LAUNCH(k_ls_holdout<F>, (P.h + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed + 1, P.h, hold);
-        const Layout S = make_layout<K>(F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64
-                                                                                       : HS_OP_SORT_KV_I32,
-                                        P.m, 1, T);
+        const Layout S = make_layout<K>(op_of<F>(), P.m, 1, T);
         int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
         if (rc) return rc;
         HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl);
@@ -556,7 +563,7 @@ int run_sort_tuned(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_
                    hs_stats *st, hipStream_t stream, int graph_levels = 0)
 {
     const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
-                         : (F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : HS_OP_SORT_KV_I32);
+                         : op_of<F>();
     Layout L;
     int rc = layout_for(op, n, nseg, o, &L);
     if (rc) return rc;
@@ -640,7 +647,7 @@ int autotune_impl(DevState *d, int op, Raw raw, int64_t n, const int64_t *d_off,
             return HS_OK;
         }
     }
-    const size_t kb = (size_t)n * (F == FMT_F64 ? 8 : 4), vb = F == FMT_KV ? (size_t)n * 4 : 0;
+    const size_t kb = (size_t)n * raw_key_bytes<F>(), vb = F == FMT_KV ? (size_t)n * 4 : 0;
     DevBuf src, work, ref, cnt;
     auto alloc = [&](DevBuf &x, size_t bytes) -> int {
         if (hipMalloc(&x.p, bytes ? bytes : 8) != hipSuccess) {
@@ -728,7 +735,7 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
         int rc = check_learn(o);
         if (rc) return rc;
         const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
-                             : (F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : HS_OP_SORT_KV_I32);
+                             : op_of<F>();
         hs_opts tuned;
         if ((rc = autotune_impl<F>(d, op, raw, n, d_off, nseg, o, &tuned, nullptr, stream))) return rc;
         tuned.workspace = o->workspace;
@@ -761,6 +768,8 @@ int check_sort_args(int op, const void *keys, const int32_t *vals, int64_t n, co
     switch (op) {
     case HS_OP_SORT_I32:
     case HS_OP_SORT_F64:
+    case HS_OP_SORT_U32:
+    case HS_OP_SORT_I64:
         break;
     case HS_OP_SORT_KV_I32:
         if (n > 0 && !vals) return fail(HS_EINVAL, "vals is NULL");
@@ -788,6 +797,10 @@ template <typename Fn> int with_format(int op, Fn &&fn)
         return fn(std::integral_constant<int, FMT_F64>());
     case HS_OP_SORT_KV_I32:
         return fn(std::integral_constant<int, FMT_KV>());
+    case HS_OP_SORT_U32:
+        return fn(std::integral_constant<int, FMT_U32>());
+    case HS_OP_SORT_I64:
+        return fn(std::integral_constant<int, FMT_I64>());
     default:
         return fail(HS_EINVAL, "op %d is not a sort", op);
     }
@@ -863,6 +876,53 @@ int hs_sort_f64(double *keys, int64_t n, const hs_opts *opts, hs_stats *stats, v
     DevState *d;
     if ((rc = get_device(&d))) return rc;
     return run_sort<FMT_F64>(d, Raw{keys, nullptr}, n, nullptr, 0, opts, stats, (hipStream_t)stream);
+}
+
+int hs_sort_u32(uint32_t *keys, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n > 0 && !keys) return fail(HS_EINVAL, "keys is NULL");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n <= 1) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    return run_sort<FMT_U32>(d, Raw{keys, nullptr}, n, nullptr, 0, opts, stats, (hipStream_t)stream);
+}
+
+int hs_sort_i64(int64_t *keys, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n > 0 && !keys) return fail(HS_EINVAL, "keys is NULL");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n <= 1) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    return run_sort<FMT_I64>(d, Raw{keys, nullptr}, n, nullptr, 0, opts, stats, (hipStream_t)stream);
+}
+
+int hs_argsort_i32(const int32_t *keys, int32_t *keys_out, int32_t *idx_out, int64_t n, const hs_opts *opts,
+                   hs_stats *stats, void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n > 0 && (!keys || !keys_out || !idx_out)) return fail(HS_EINVAL, "keys, keys_out or idx_out is NULL");
+    if (n > 0 && keys != keys_out && overlap(keys, (size_t)n * 4, keys_out, (size_t)n * 4))
+        return fail(HS_EINVAL, "keys and keys_out overlap without being the same array");
+    if (n > 0 && (overlap(idx_out, (size_t)n * 4, keys_out, (size_t)n * 4) ||
+                  overlap(idx_out, (size_t)n * 4, keys, (size_t)n * 4)))
+        return fail(HS_EINVAL, "idx_out overlaps the keys");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n == 0) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (keys != keys_out) HS_HIP(hipMemcpyAsync(keys_out, keys, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    HS_LAUNCH(k_iota, (unsigned)((n + 255) / 256), 256, s, idx_out, (uint32_t)n);
+    if (n == 1) return HS_OK;
+    // the (key, index) word orders equal keys by index: the sort comes out stable
+    return run_sort<FMT_KV>(d, Raw{keys_out, idx_out}, n, nullptr, 0, opts, stats, s);
 }
 
 int hs_sort_kv_i32(int32_t *keys, int32_t *vals, int64_t n, const hs_opts *opts, hs_stats *stats,
@@ -1189,8 +1249,8 @@ int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *
     // whatever remains).
     int graph_levels = 0;
     {
-        const uint32_t T = op == HS_OP_SORT_I32 || op == HS_OP_SORT_SEGMENTED_I32 ? local_limit<uint32_t>(&o)
-                                                                                 : local_limit<uint64_t>(&o);
+        const bool w32 = op == HS_OP_SORT_I32 || op == HS_OP_SORT_U32 || op == HS_OP_SORT_SEGMENTED_I32;
+        const uint32_t T = w32 ? local_limit<uint32_t>(&o) : local_limit<uint64_t>(&o);
         uint64_t biggest = (uint64_t)n;
         if (op == HS_OP_SORT_SEGMENTED_I32) {
             std::vector<int64_t> h_off((size_t)nseg + 1);
