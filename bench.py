@@ -263,6 +263,70 @@ def cpu_baseline(name):
                              f"os.cpu_count()={os.cpu_count()})"}
 
 
+def run_small(reps=40):
+    """Small arrays: latency of one sort per size (GPU time between events on
+    the sort stream, and host time from the call to the sort's completion),
+    and batched sorts of many equal-size arrays in one segmented call."""
+    import statistics
+
+    import torch
+
+    import paper_1704_08579_amd as hs
+    import workloads
+    hs.lib()
+    dev = torch.device("cuda")
+    out = {"single": {}, "batched_i32": {}}
+    sizes = [2, 16, 64, 256, 512, 1024, 2048, 8192, 65536]
+    for kind in ("i32", "f64", "kv"):
+        rows = {}
+        for n in sizes:
+            if kind == "f64":
+                src = torch.from_numpy(workloads.f64(n, "uniform", seed=n)).to(dev)
+            else:
+                src = torch.from_numpy(workloads.uniform_i32(n, seed=n)).to(dev)
+            t = src.clone()
+            v = torch.arange(n, dtype=torch.int32, device=dev) if kind == "kv" else None
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            gpu_us, wall_us = [], []
+            for r in range(reps + 5):
+                t.copy_(src)
+                torch.cuda.synchronize()
+                w0 = time.perf_counter()
+                e0.record()
+                if kind == "kv":
+                    hs.sort_kv_(t, v)
+                else:
+                    hs.sort_(t)
+                e1.record()
+                e1.synchronize()
+                w1 = time.perf_counter()
+                if r >= 5:
+                    gpu_us.append(e0.elapsed_time(e1) * 1e3)
+                    wall_us.append((w1 - w0) * 1e6)
+            rows[str(n)] = {"gpu_us": round(statistics.median(gpu_us), 1),
+                            "call_to_done_us": round(statistics.median(wall_us), 1)}
+        out["single"][kind] = rows
+    total = 1 << 22
+    for s in (16, 64, 256, 1024, 4096):
+        nseg = total // s
+        off = torch.arange(0, (nseg + 1) * s, s, dtype=torch.int64, device=dev)
+        src = torch.from_numpy(workloads.uniform_i32(nseg * s, seed=s)).to(dev)
+        t = src.clone()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for r in range(8):
+            t.copy_(src)
+            e0.record()
+            hs.sort_segmented_(t, off)
+            e1.record()
+            e1.synchronize()
+            if r >= 2:
+                ms.append(e0.elapsed_time(e1))
+        m = statistics.median(ms)
+        out["batched_i32"][str(s)] = {"arrays": nseg, "ms": round(m, 3), "gkeys_per_s": round(nseg * s / m / 1e6, 2)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +335,8 @@ def main():
     ap.add_argument("--config", default="f64_2e27", choices=sorted(CONFIGS))
     ap.add_argument("--extra", action="store_true", help="also run the int32, key/value and batched configs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--small", action="store_true",
+                    help="also measure small arrays: per-size latency and batched throughput")
     ap.add_argument("--driver", choices=["persistent", "host"], default="host",
                     help="partition levels in one persistent launch, or one launch per level")
     args = ap.parse_args()
@@ -336,6 +402,8 @@ def main():
         out["config"]["learned_per_distribution"] = r["learned"]
     if extra:
         out["extra"] = extra
+    if args.small:
+        out["small_arrays"] = run_small()
     print(json.dumps(out), flush=True)
 
 

@@ -5,8 +5,8 @@
  * Algorithm Vectorized using AVX-512 on Intel Skylake" (arXiv 1704.08579):
  * quicksort partitioning around a pivot (Sec. III-B, Algorithm 3; Sec. III-C,
  * Algorithm 4) with partitions below a bound sorted by a branch-free bitonic
- * network (Sec. III-A, Algorithms 1 and 2), for int32 keys, float64 keys and
- * int32 key/value pairs (Sec. III-D).
+ * network (Sec. III-A, Algorithms 1 and 2), for int32, uint32, int64 and
+ * float64 keys and int32 key/value pairs (Sec. III-D).
  *
  * Conventions shared by every entry point:
  *   - Every array pointer is a DEVICE pointer (hipMalloc memory, or e.g. a
@@ -16,8 +16,13 @@
  *     after each batch of levels) to report errors raised inside kernels,
  *     so a sort returns once its work on `stream` has completed; while the
  *     stream is being captured into a graph nothing is read back (see the
- *     plan entry points).  hs_partition_i32 and the learned method's
- *     kernel entry points return as soon as their work is enqueued.
+ *     plan entry points).  A whole-array sort of at most 1024 keys (fewer
+ *     when hs_opts.local_T or hs_opts.leaf is set lower) is one wave's
+ *     bitonic network in a single kernel that cannot fail, and returns as
+ *     soon as it is enqueued (after it completed when statistics are asked
+ *     for).  hs_partition_i32
+ *     and the learned method's kernel entry points return as soon as their
+ *     work is enqueued.
  *   - Sorts are in place, ascending and not stable: the paper's partition
  *     and bitonic network are not stable (Sec. II-A).  Equal keys of the
  *     key/value sort come out ordered by value (a valid, deterministic

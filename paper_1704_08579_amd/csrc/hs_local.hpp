@@ -439,6 +439,22 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
     }
 }
 
+// A whole array of at most LEAF keys: one wave loads it, sorts it with the
+// network and stores it back.  Nothing here can fail; lane 0 clears the
+// error word a graph plan reads after its replays.  The host sends arrays of
+// up to WAVE_NET keys this way, of either word size (one wave alone on a
+// SIMD has the registers for 16 eight-byte keys per lane).
+constexpr int WAVE_NET = 1024;
+template <int F, int LEAF>
+__global__ __launch_bounds__(WAVE) void k_sort_wave(Ctl *ctl, Raw raw, uint32_t n)
+{
+    using K = typename KeyOf<F>::type;
+    const int lane = lane_id();
+    if (lane == 0) ctl->err = 0u;
+    wave_sort<LEAF, K>(n, lane, [&](uint32_t p) { return raw_load<F>(raw, p); },
+                       [&](uint32_t j, K v) { raw_store<F>(raw, j, v); });
+}
+
 // Small tasks, one wave each (waves take tasks in a grid-stride loop from
 // the back of the task list): a range of at most LEAF keys goes straight from
 // HBM through the bitonic network to the caller's array, and a fill task

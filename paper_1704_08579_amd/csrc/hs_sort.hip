@@ -367,6 +367,26 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
         return fail(HS_EINVAL, "the host-driven level loop cannot be captured into a graph");
     const bool host_driver = drv == HS_DRIVER_HOST || (drv == HS_DRIVER_AUTO && !capturing);
 
+    // a whole array that one wave's network holds (1024 keys, unless the
+    // caller lowered the on-chip limit or the network bound to force the
+    // other tiers): a single launch, no read-back
+    const uint64_t wave_max = (o && o->leaf > 0) ? LEAF : (uint64_t)(T < WAVE_NET ? T : WAVE_NET);
+    if (!learned && !d_off && (uint64_t)n <= wave_max) {
+        if (st) HS_HIP(hipEventRecord(lev[0], stream));
+        HS_LAUNCH((k_sort_wave<F, WAVE_NET>), 1, WAVE, stream, ctl, raw, (uint32_t)n);
+        if (st && !capturing) {
+            HS_HIP(hipEventRecord(lev[1], stream));
+            HS_HIP(hipEventSynchronize(lev[1]));
+            std::memset(st, 0, sizeof *st);
+            st->tasks = 1;
+            st->bytes_alg = (int64_t)(2 * sizeof(K)) * n;
+            float ms = 0.f;
+            HS_HIP(hipEventElapsedTime(&ms, lev[0], lev[1]));
+            st->local_ms = ms;
+        }
+        return HS_OK;
+    }
+
     HS_LAUNCH(k_zero_words, zero_grid(sizeof(Ctl)), 256, stream, (uint32_t *)ctl, (uint32_t)(sizeof(Ctl) / 4));
     int level0 = 0;
     LearnCtl *lctl = nullptr;

@@ -1,8 +1,10 @@
 """The on-chip tier through the C ABI, against the oracle.
 
 * single tasks at the sizes where the on-chip sort changes regime: one
-  wave's network (512 / 1024 keys), one wave's span (1024 keys), a few spans,
-  the on-chip limit (8192 keys);
+  wave's network (512 / 1024 keys: by default a whole array of up to 1024
+  keys is a single wave's network, leaf=512 routes it through the workgroup
+  instead), one wave's span (1024 keys), a few spans, the on-chip limit
+  (8192 keys);
 * an input built by McIlroy's adversary for the block levels' ninther
   (tests/helpers.py): hundreds of block levels inside one task, each
   queueing a small child, so the wave queue fills and is drained between
@@ -53,14 +55,19 @@ def _sort_kv(hs, k, v, opts=None):
     return tk.cpu().numpy(), tv.cpu().numpy()
 
 
+@pytest.mark.parametrize("leaf", [0, 512], ids=["default", "leaf512"])
 @pytest.mark.parametrize("n", THRESHOLDS)
-def test_task_sizes(hs, oracle_mod, n):
+def test_task_sizes(hs, oracle_mod, n, leaf):
+    """Up to 1024 keys a whole array is one wave's network by default;
+    leaf=512 sends 513..1024 keys through the on-chip workgroup instead."""
+    o = hs.Opts()
+    o.leaf = leaf
     a = workloads.uniform_i32(n, seed=n)
-    assert np.array_equal(_sort(hs, a), oracle_mod.sort_i32(a))
+    assert np.array_equal(_sort(hs, a, o), oracle_mod.sort_i32(a))
     f = workloads.f64(n, "normal", seed=n + 1)
-    assert np.array_equal(_sort(hs, f).view(np.uint64), oracle_mod.sort_f64(f).view(np.uint64))
+    assert np.array_equal(_sort(hs, f, o).view(np.uint64), oracle_mod.sort_f64(f).view(np.uint64))
     k, v = workloads.kv_dup_i32(n, seed=n + 2, ndistinct=max(2, n // 8))
-    ko, vo = _sort_kv(hs, k, v)
+    ko, vo = _sort_kv(hs, k, v, o)
     assert np.array_equal(ko, oracle_mod.sort_kv_i32(k, v)[0])
     kv_index_check(k, ko, vo)
 
