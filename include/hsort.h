@@ -16,11 +16,12 @@
  *     after each batch of levels) to report errors raised inside kernels,
  *     so a sort returns once its work on `stream` has completed; while the
  *     stream is being captured into a graph nothing is read back (see the
- *     plan entry points).  A whole-array sort of at most 1024 keys (fewer
- *     when hs_opts.local_T or hs_opts.leaf is set lower) is one wave's
- *     bitonic network in a single kernel that cannot fail, and returns as
- *     soon as it is enqueued (after it completed when statistics are asked
- *     for).  hs_partition_i32
+ *     plan entry points).  A whole-array sort that is a single on-chip task
+ *     (at most the on-chip limit, 8192 keys by default) cannot fail and
+ *     reads nothing back: it returns as soon as it is enqueued (after it
+ *     completed when statistics are asked for).  Up to 1024 keys (fewer when
+ *     hs_opts.local_T or hs_opts.leaf is set lower) it is one wave's
+ *     bitonic network in a single kernel.  hs_partition_i32
  *     and the learned method's kernel entry points return as soon as their
  *     work is enqueued.
  *   - Sorts are in place, ascending and not stable: the paper's partition

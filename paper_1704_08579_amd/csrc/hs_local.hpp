@@ -455,6 +455,27 @@ __global__ __launch_bounds__(WAVE) void k_sort_wave(Ctl *ctl, Raw raw, uint32_t 
                        [&](uint32_t j, K v) { raw_store<F>(raw, j, v); });
 }
 
+// A whole array of LEAF+1 .. T keys is one on-chip task: one block clears
+// the control block and writes the task, for a one-workgroup k_local.
+template <int F>
+__global__ __launch_bounds__(256) void k_init_one_task(Ctl *ctl, Task<typename KeyOf<F>::type> *tasks, uint32_t n)
+{
+    using K = typename KeyOf<F>::type;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(sizeof(Ctl) / 4); i += blockDim.x) ((uint32_t *)ctl)[i] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Task<K> tk;
+        tk.b = 0;
+        tk.e = n;
+        tk.src = SRC_RAW;
+        tk.kind = TASK_LOCAL;
+        tk.fill = 0;
+        tasks[0] = tk;
+        ctl->ntask = 1;
+        ctl->local_keys = n;
+    }
+}
+
 // Small tasks, one wave each (waves take tasks in a grid-stride loop from
 // the back of the task list): a range of at most LEAF keys goes straight from
 // HBM through the bitonic network to the caller's array, and a fill task

@@ -386,6 +386,26 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
         }
         return HS_OK;
     }
+    // a whole array that is one on-chip task: set-up and one workgroup, no
+    // read-back (neither kernel can report an error for a single task)
+    if (!learned && !d_off && (uint64_t)n <= T && (uint64_t)n > LEAF) {
+        using LC = LocalCfg<K>;
+        HS_LAUNCH(k_init_one_task<F>, 1, 256, stream, ctl, tasks, (uint32_t)n);
+        if (st) HS_HIP(hipEventRecord(lev[0], stream));
+        HS_LAUNCH((k_local<F, LC::NT, LC::T, LC::LW, LC::WPC>), 1, LC::NT, stream, ctl, tasks, buf[0], buf[1], raw,
+                  local_rule, L.task_cap);
+        if (st && !capturing) {
+            HS_HIP(hipEventRecord(lev[1], stream));
+            HS_HIP(hipEventSynchronize(lev[1]));
+            std::memset(st, 0, sizeof *st);
+            st->tasks = 1;
+            st->bytes_alg = (int64_t)(2 * sizeof(K)) * n;
+            float ms = 0.f;
+            HS_HIP(hipEventElapsedTime(&ms, lev[0], lev[1]));
+            st->local_ms = ms;
+        }
+        return HS_OK;
+    }
 
     HS_LAUNCH(k_zero_words, zero_grid(sizeof(Ctl)), 256, stream, (uint32_t *)ctl, (uint32_t)(sizeof(Ctl) / 4));
     int level0 = 0;
