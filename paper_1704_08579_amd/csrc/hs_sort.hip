@@ -516,7 +516,11 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     } else {
         // host-driven levels: batches of fixed-grid launches, one read-back per batch
         int level = level0;
-        int batch = (!learned && !d_off && (uint64_t)n > T) ? levels_for((uint64_t)n, T) : 0;
+        // the first batch runs the levels balanced splits would need plus
+        // three: sampled pivots spread the segment sizes, so a second batch
+        // (and its read-back) usually follows otherwise, while a level with an
+        // empty list exits at once
+        int batch = (!learned && !d_off && (uint64_t)n > T) ? levels_for((uint64_t)n, T) + 3 : 0;
         for (;;) {
             for (int bi = 0; bi < batch && level < LMAX; ++bi, ++level) {
                 const int rc = launch_level(level);
