@@ -276,6 +276,25 @@ __device__ __forceinline__ void cmpx_layer(K (&x)[KPL], int lane)
 // Stage s merges sorted runs of 2^(s-1) into runs of 2^s: the mirror layer
 // (mask 2^s - 1, "extremities to the centre"), then half-cleaners at
 // distances 2^(s-2) .. 1 ("linear progression").
+// The first STAGES stages of the one-key-per-lane network: none of their
+// layers pairs lanes of different groups of 2^STAGES consecutive lanes, so
+// every such group ends up sorted on its own and one wave sorts 64 / 2^STAGES
+// independent arrays at once.
+template <int STAGES, typename K>
+__device__ __forceinline__ void bitonic_lanes(K &v, int lane)
+{
+    K x[1] = {v};
+    static_for<1, STAGES + 1>([&](auto S) {
+        constexpr int s = decltype(S)::value;
+        cmpx_layer<(1 << s) - 1, 1>(x, lane);
+        static_for<0, (s >= 2 ? s - 1 : 0)>([&](auto I) {
+            constexpr int t = s - 2 - decltype(I)::value;
+            cmpx_layer<(1 << t), 1>(x, lane);
+        });
+    });
+    v = x[0];
+}
+
 template <int KPL, typename K>
 __device__ __forceinline__ void bitonic_wave(K (&x)[KPL], int lane)
 {

@@ -476,10 +476,14 @@ __global__ __launch_bounds__(256) void k_init_one_task(Ctl *ctl, Task<typename K
     }
 }
 
-// Small tasks, one wave each (waves take tasks in a grid-stride loop from
-// the back of the task list): a range of at most LEAF keys goes straight from
-// HBM through the bitonic network to the caller's array, and a fill task
-// writes its key over its range.
+// Small tasks, from the back of the task list: a range of at most LEAF keys
+// goes straight from HBM through the bitonic network to the caller's array,
+// and a fill task writes its key over its range.  With fewer than four tasks
+// per wave, waves take one task each in a grid-stride loop.  With more, they
+// take groups of four consecutive tasks: when all four sorts of a group fit
+// 16 keys, one wave sorts them together, a quarter of its lanes each (the
+// network's first four stages stay inside 16-lane groups); when they fit 32
+// keys, two at a time on half-waves; otherwise one after another.
 template <int F, int LEAF>
 __global__ __launch_bounds__(256) void k_small(const Ctl *ctl, const Task<typename KeyOf<F>::type> *tasks,
                                                const typename KeyOf<F>::type *buf0,
@@ -489,8 +493,11 @@ __global__ __launch_bounds__(256) void k_small(const Ctl *ctl, const Task<typena
     const int lane = lane_id();
     const uint32_t nsmall = min(ctl->nsmall, task_cap);
     const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
-    for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < nsmall; i += nwaves) {
-        const Task<K> tk = tasks[task_cap - 1 - i];
+    auto task_at = [&](uint32_t i) { return tasks[task_cap - 1 - i]; };
+    auto ld = [&](const Task<K> &tk, uint32_t j) {
+        return tk.src == SRC_RAW ? raw_load<F>(raw, tk.b + j) : (tk.src == SRC_BUF0 ? buf0 : buf1)[tk.b + j];
+    };
+    auto one = [&](const Task<K> &tk) {
         const uint32_t b = tk.b, m = tk.e - tk.b;
         if (tk.kind == TASK_FILL) {
             for (uint32_t j = (uint32_t)lane; j < m; j += WAVE) raw_store<F>(raw, b + j, tk.fill);
@@ -501,6 +508,46 @@ __global__ __launch_bounds__(256) void k_small(const Ctl *ctl, const Task<typena
             const K *sbuf = tk.src == SRC_BUF0 ? buf0 : buf1;
             wave_sort<LEAF, K>(m, lane, [&](uint32_t p) { return sbuf[b + p]; },
                                [&](uint32_t j, K v) { raw_store<F>(raw, b + j, v); });
+        }
+    };
+    // lanes [gw*g, gw*(g+1)) sort task i (of m keys) with a network of gw lanes
+    auto packed = [&](uint32_t i, bool has, uint32_t r, auto STAGES) {
+        Task<K> tk;
+        tk.b = tk.e = 0;
+        tk.src = SRC_RAW;
+        if (has) tk = task_at(i);
+        const uint32_t m = tk.e - tk.b;
+        K v = key_max<K>();
+        if (has && r < m) v = ld(tk, r);
+        bitonic_lanes<decltype(STAGES)::value>(v, lane);
+        if (has && r < m) raw_store<F>(raw, tk.b + r, v);
+    };
+    const uint32_t wv = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (nsmall < 4u * nwaves) {  // too few tasks to group: one task per wave keeps every wave busy
+        for (uint32_t i = wv; i < nsmall; i += nwaves) one(task_at(i));
+        return;
+    }
+    for (uint32_t g = wv; 4ull * g < nsmall; g += nwaves) {
+        const uint32_t i0 = 4 * g;
+        // sizes of the group's four tasks, one per quarter-wave (past the end: none)
+        const uint32_t iq = i0 + (uint32_t)(lane >> 4);
+        uint32_t mq = 0;
+        bool fill = false;
+        if (iq < nsmall) {
+            const Task<K> tq = task_at(iq);
+            mq = tq.e - tq.b;
+            fill = tq.kind == TASK_FILL;
+        }
+        if (ballot(fill || mq > 16u) == 0) {
+            packed(iq, iq < nsmall, (uint32_t)(lane & 15), std::integral_constant<int, 4>{});
+        } else if (ballot(fill || mq > 32u) == 0) {
+#pragma unroll
+            for (uint32_t h = 0; h < 2; ++h) {
+                const uint32_t ih = i0 + 2 * h + (uint32_t)(lane >> 5);
+                packed(ih, ih < nsmall, (uint32_t)(lane & 31), std::integral_constant<int, 5>{});
+            }
+        } else {
+            for (uint32_t q = 0; q < 4 && i0 + q < nsmall; ++q) one(task_at(i0 + q));
         }
     }
 }

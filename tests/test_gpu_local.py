@@ -124,3 +124,28 @@ def test_queue_drains_segmented(hs, oracle_mod, adv):
     hs.sort_segmented_(t, _gpu(off))
     torch.cuda.synchronize()
     assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
+
+
+@pytest.mark.parametrize("sizes", ["all16", "all32", "mixed40", "mixed16", "ragged"])
+def test_batched_tiny_arrays(hs, oracle_mod, sizes):
+    """Batches of tiny arrays: groups of four tasks that all fit 16 (32) keys
+    are sorted by one wave four (two) at a time; mixed groups one by one."""
+    g = workloads.rng(hash(sizes) & 0xFFFF)
+    n = {"all16": 40000, "all32": 30000, "mixed40": 50001, "mixed16": 40003, "ragged": 4001}[sizes]
+    if sizes == "all16":
+        s = np.full(n, 16)
+    elif sizes == "all32":
+        s = np.full(n, 32)
+    elif sizes == "mixed40":
+        s = g.integers(1, 41, n)
+    elif sizes == "mixed16":
+        s = g.integers(0, 17, n)
+    else:  # a group count that is not a multiple of four, sizes at the packing bounds
+        s = g.choice(np.array([15, 16, 17, 31, 32, 33]), n)
+    off = np.concatenate([[0], np.cumsum(s)]).astype(np.int64)
+    keys = workloads.uniform_i32(int(off[-1]), seed=n)
+    keys[::7] = keys[0]  # duplicates inside the arrays
+    t = _gpu(keys)
+    hs.sort_segmented_(t, _gpu(off))
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
