@@ -36,6 +36,9 @@ CONFIGS = {
     "i32_2e28": ("i32", 1 << 28, None, 1, "sort_i32, 2^28 int32 keys uniform over the full range"),
     "kv_2e28": ("kv", 1 << 28, None, 4,
                 "sort_kv_i32, 2^28 int32 pairs, 2^16 distinct keys, values = original index"),
+    "kvf64_2e27": ("kvf64", 1 << 27, None, 6,
+                   "sort_kv_f64, 2^27 (float64 key, int32 value) pairs, 2^16 distinct N(0,1) keys, "
+                   "values = original index"),
     "seg_A": ("seg", 200000, (16, 1 << 13), 5,
               "sort_segmented_i32, 200,000 int32 arrays, sizes log-uniform in [16, 2^13]"),
     "seg_B": ("seg", 2840, (16, 1 << 20), 5,
@@ -70,6 +73,9 @@ def make_inputs(name):
     if kind == "kv":
         k, v = workloads.kv_dup_i32(n, seed=seed)
         return [("kv", (k, v))]
+    if kind == "kvf64":
+        k, v = workloads.kv_dup_f64(n, seed=seed)
+        return [("kvf64", (k, v))]
     if kind == "seg":
         lo, hi = extra
         off = workloads.segment_offsets(n, lo, hi, seed=seed)
@@ -88,14 +94,14 @@ class Case:
             self.work = torch.empty_like(self.src)
             self.n = data.size
             self.s = data.itemsize
-        elif kind == "kv":
+        elif kind in ("kv", "kvf64"):
             k, v = data
             self.src = torch.from_numpy(k).to(dev)
             self.vsrc = torch.from_numpy(v).to(dev)
             self.work = torch.empty_like(self.src)
             self.vwork = torch.empty_like(self.vsrc)
             self.n = k.size
-            self.s = 8
+            self.s = 8 if kind == "kv" else 16  # bytes of the order word a pair travels as
         else:
             k, off = data
             self.src = torch.from_numpy(k).to(dev)
@@ -106,7 +112,7 @@ class Case:
 
     def restore(self):
         self.work.copy_(self.src)
-        if self.kind == "kv":
+        if self.kind in ("kv", "kvf64"):
             self.vwork.copy_(self.vsrc)
 
     def sort(self, hs, opts=None):
@@ -114,7 +120,7 @@ class Case:
             return self.plan.run()
         if self.kind in ("f64", "i32"):
             return hs.sort_(self.work, opts=opts, stats=True)
-        if self.kind == "kv":
+        if self.kind in ("kv", "kvf64"):
             return hs.sort_kv_(self.work, self.vwork, opts=opts, stats=True)
         return hs.sort_segmented_(self.work, self.off, opts=opts, stats=True)
 
@@ -250,6 +256,9 @@ def cpu_baseline(name):
     elif kind0 == "kv":
         oracle.sort_kv_i32(data[0][:m], data[1][:m])
         what = f"first 2^{m.bit_length() - 1} pairs"
+    elif kind0 == "kvf64":
+        oracle.sort_kv_f64(data[0][:m], data[1][:m])
+        what = f"first 2^{m.bit_length() - 1} float64 key/value pairs"
     else:
         k, off = data
         nseg = int(np.searchsorted(off, m, side="right")) - 1
@@ -348,7 +357,7 @@ def main():
     r = run_gpu(args.config, args.steps, args.warmup, driver)
     extra = {}
     if args.extra:
-        for nm in ["i32_2e28", "kv_2e28", "seg_A", "seg_B", "i32_2e20", "learned_2e28",
+        for nm in ["i32_2e28", "kv_2e28", "kvf64_2e27", "seg_A", "seg_B", "i32_2e20", "learned_2e28",
                    "sampled_2e28_learned_inputs", "plain_2e28_learned_inputs"]:
             if nm == args.config:
                 continue
@@ -379,7 +388,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "u64", "i32": "u32", "kv": "u64", "seg": "u32"}[kind],
+        "dtype": {"f64": "u64", "i32": "u32", "kv": "u64", "kvf64": "u128", "seg": "u32"}[kind],
         "data": "synthetic",
         "config": {"workload": desc, "keys_per_step": r["keys_per_step"],
                    "bytes_per_key": round(r["bytes_per_key"], 1),

@@ -6,7 +6,8 @@
  * quicksort partitioning around a pivot (Sec. III-B, Algorithm 3; Sec. III-C,
  * Algorithm 4) with partitions below a bound sorted by a branch-free bitonic
  * network (Sec. III-A, Algorithms 1 and 2), for int32, uint32, int64 and
- * float64 keys and int32 key/value pairs (Sec. III-D).
+ * float64 keys and key/value pairs with int32 or float64 keys and int32
+ * values (Sec. III-D).
  *
  * Conventions shared by every entry point:
  *   - Every array pointer is a DEVICE pointer (hipMalloc memory, or e.g. a
@@ -17,16 +18,17 @@
  *     so a sort returns once its work on `stream` has completed; while the
  *     stream is being captured into a graph nothing is read back (see the
  *     plan entry points).  A whole-array sort that is a single on-chip task
- *     (at most the on-chip limit, 8192 keys by default) cannot fail and
- *     reads nothing back: it returns as soon as it is enqueued (after it
- *     completed when statistics are asked for).  Up to 1024 keys (fewer when
+ *     (at most the on-chip limit, 8192 keys by default, 4096 float64
+ *     key/value pairs) cannot fail and reads nothing back: it returns as
+ *     soon as it is enqueued (after it completed when statistics are asked
+ *     for).  Up to 1024 keys (512 float64 key/value pairs; fewer when
  *     hs_opts.local_T or hs_opts.leaf is set lower) it is one wave's
  *     bitonic network in a single kernel.  hs_partition_i32
  *     and the learned method's kernel entry points return as soon as their
  *     work is enqueued.
  *   - Sorts are in place, ascending and not stable: the paper's partition
  *     and bitonic network are not stable (Sec. II-A).  Equal keys of the
- *     key/value sort come out ordered by value (a valid, deterministic
+ *     key/value sorts come out ordered by value (a valid, deterministic
  *     choice among the permutations the method allows).
  *   - The caller owns every array and the stream; the library keeps no
  *     pointer once the call's work on `stream` has completed.  Scratch
@@ -68,7 +70,7 @@ typedef enum hs_status {
 /* Operation codes for hs_workspace_size(), plans and the autotuner. */
 enum { HS_OP_SORT_I32 = 0, HS_OP_SORT_F64 = 1, HS_OP_SORT_KV_I32 = 2,
        HS_OP_PARTITION_I32 = 3, HS_OP_SORT_SEGMENTED_I32 = 4,
-       HS_OP_SORT_U32 = 5, HS_OP_SORT_I64 = 6 };
+       HS_OP_SORT_U32 = 5, HS_OP_SORT_I64 = 6, HS_OP_SORT_KV_F64 = 7 };
 
 /* Pivot rules (hs_opts.pivot_rule). */
 enum { HS_PIVOT_AUTO = 0,     /* the tuned default */
@@ -124,7 +126,7 @@ typedef struct hs_stats {
 typedef struct hs_opts {
     int32_t pivot_rule;   /* HS_PIVOT_* */
     int32_t local_T;      /* on-chip segment limit in keys (ranges up to it are sorted on chip; larger ones
-                           * are partitioned again); capped at 8192 */
+                           * are partitioned again); capped at 8192 (4096 for float64 key/value) */
     int32_t method;       /* HS_METHOD_* */
     int32_t learn_flags;  /* HS_LEARN_* */
     int32_t train_steps;  /* learned method: Adam steps (default 300) */
@@ -135,7 +137,8 @@ typedef struct hs_opts {
                            * runs out fails the call with HS_EINTERNAL */
     int32_t leaf;         /* largest range one wave sorts with the bitonic network alone: a power of two in
                            * 64..1024, capped at the type's network (1024 int32, 512 float64 and
-                           * key/value; the default); larger ranges go to the workgroup on-chip sort */
+                           * key/value, 256 float64 key/value; the default); larger ranges go to the
+                           * workgroup on-chip sort */
     int32_t autotune;     /* 1: use (or first measure and remember) the tuned knobs for this operation and
                            * size class; see hs_autotune */
     int32_t reserved;
@@ -173,6 +176,17 @@ HS_API int hs_argsort_i32(const int32_t *keys, int32_t *keys_out, int32_t *idx_o
  * overlap. */
 HS_API int hs_sort_kv_i32(int32_t *keys, int32_t *vals, int64_t n, const hs_opts *opts,
                    hs_stats *stats, void *stream);
+
+/* Sort n (float64 key, int32 value) pairs held as two separate arrays
+ * (Sec. III-D) by the key's IEEE 754-2008 totalOrder, in place; every value
+ * moves with its key, and equal keys (equal bits) are ordered by their
+ * values' bits as unsigned 32-bit integers, so the output is unique.  A pair
+ * travels as one 128-bit order word (the key's totalOrder word above the
+ * value), on the same kernels as the other formats with half as many keys
+ * per on-chip task.  keys and vals must not overlap (DEVICE pointers).  The
+ * learned method is not offered for this format (HS_EINVAL). */
+HS_API int hs_sort_kv_f64(double *keys, int32_t *vals, int64_t n, const hs_opts *opts, hs_stats *stats,
+                          void *stream);
 
 /* Partition n int32 keys in place around `pivot` (Algorithm 3's contract):
  * afterwards keys[0,k) <= pivot < keys[k,n), with k = #{x <= pivot} written
@@ -238,7 +252,7 @@ HS_API int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_
 /* ---- Plans: one call captured into a HIP graph ------------------------
  *
  * hs_plan_create records one sort of the given buffers (op HS_OP_SORT_I32,
- * _U32, _I64, _F64, _KV_I32 or _SORT_SEGMENTED_I32; vals only for key/value, d_offsets
+ * _U32, _I64, _F64, _KV_I32, _KV_F64 or _SORT_SEGMENTED_I32; vals only for key/value, d_offsets
  * and nseg only for segmented) into a graph: the partition levels run in the
  * persistent driver, every clear is a kernel, and the plan owns its
  * workspace, so replaying it needs no host work beyond hipGraphLaunch.
@@ -259,9 +273,10 @@ HS_API void hs_plan_destroy(hs_plan *plan);
 /* ---- Autotuner ---------------------------------------------------------
  *
  * Measures the sort of the given input (left unchanged: the tuner sorts a
- * copy) under every combination of on-chip limit local_T (2048, 4096, 8192),
- * one-wave bitonic bound leaf (the type's network size L, L/2, L/4: 1024,
- * 512, 256 for int32; 512, 256, 128 otherwise) and global pivot rule
+ * copy) under every combination of on-chip limit local_T (2048, 4096, 8192,
+ * up to the type's limit), one-wave bitonic bound leaf (the type's network
+ * size L, L/2, L/4: 1024, 512, 256 for int32; 256, 128, 64 for float64
+ * key/value; 512, 256, 128 otherwise) and global pivot rule
  * (ninther, sample median of 64), for the driver base->driver selects, with
  * HIP events (one warm-up and two timed runs each, fastest kept).  Every
  * candidate's output is compared on the device with the first candidate's:

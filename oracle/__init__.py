@@ -47,6 +47,7 @@ def lib() -> ctypes.CDLL:
             ("oracle_sort_i32", [_P, _I64, _I64], _I64),
             ("oracle_sort_f64", [_P, _I64, _I64], _I64),
             ("oracle_sort_kv_i32", [_P, _P, _I64, _I64], _I64),
+            ("oracle_sort_kv_f64", [_P, _P, _I64, _I64], _I64),
             ("oracle_sort_u32", [_P, _I64, _I64], _I64),
             ("oracle_sort_i64", [_P, _I64, _I64], _I64),
             ("oracle_argsort_i32", [_P, _P, _I64, _I64], _I64),
@@ -140,6 +141,17 @@ def sort_kv_i32(keys: np.ndarray, vals: np.ndarray, leaf: int = LEAF):
     if lib().oracle_sort_kv_i32(_ptr(k), _ptr(v), k.size, leaf) < 0:
         raise MemoryError("oracle_sort_kv_i32")
     return k, v
+
+
+def sort_kv_f64(keys: np.ndarray, vals: np.ndarray, leaf: int = LEAF):
+    """(float64 key, int32 value) pairs by the key's totalOrder; returns the
+    permuted keys and values."""
+    k = np.ascontiguousarray(keys, dtype=np.float64).copy().view(np.uint64)
+    v = np.ascontiguousarray(vals, dtype=np.int32).copy()
+    assert k.size == v.size
+    if lib().oracle_sort_kv_f64(_ptr(k), _ptr(v), k.size, leaf) < 0:
+        raise MemoryError("oracle_sort_kv_f64")
+    return k.view(np.float64), v
 
 
 def sort_segmented_i32(keys: np.ndarray, offsets: np.ndarray, leaf: int = LEAF) -> np.ndarray:

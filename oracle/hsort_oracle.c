@@ -295,6 +295,26 @@ int64_t oracle_sort_kv_i32(int32_t *keys, int32_t *vals, int64_t n, int64_t leaf
     return d;
 }
 
+/* Key/value pairs with float64 keys (Sec. III-D): the value travels with
+ * the key's totalOrder key and never takes part in a comparison, so equal
+ * keys leave their values in whatever order the method produced. */
+int64_t oracle_sort_kv_f64(uint64_t *bits, int32_t *vals, int64_t n, int64_t leaf)
+{
+    elem_t *a = (elem_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(elem_t));
+    if (!a) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        a[i].key = oracle_key_f64(bits[i]);
+        a[i].val = vals[i];
+    }
+    int64_t d = sort_elems(a, n, leaf);
+    for (int64_t i = 0; i < n; ++i) {
+        bits[i] = oracle_unkey_f64(a[i].key);
+        vals[i] = a[i].val;
+    }
+    free(a);
+    return d;
+}
+
 /* Segmented sort: every [off[i], off[i+1]) is sorted on its own. */
 int64_t oracle_sort_segmented_i32(int32_t *keys, const int64_t *off, int64_t nseg,
                                   int64_t leaf)

@@ -9,7 +9,7 @@ calls raise.
     import torch, paper_1704_08579_amd as hsort
     x = torch.randint(-2**31, 2**31, (1 << 20,), dtype=torch.int32, device="cuda")
     hsort.sort_(x)                      # in place, ascending
-    hsort.sort_kv_(keys, vals)          # values follow their keys
+    hsort.sort_kv_(keys, vals)          # values follow their keys (int32 or float64 keys)
     k = hsort.partition_(x, pivot)      # x[:k] <= pivot < x[k:]
     hsort.sort_segmented_(x, offsets)   # each [off[i], off[i+1]) on its own
 """
@@ -25,7 +25,8 @@ __all__ = ["sort_", "sort_kv_", "argsort", "partition_", "sort_segmented_", "wor
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhsort.so")
 
 HS_OK = 0
-OP_SORT_I32, OP_SORT_F64, OP_SORT_KV_I32, OP_PARTITION_I32, OP_SORT_SEGMENTED_I32, OP_SORT_U32, OP_SORT_I64 = range(7)
+(OP_SORT_I32, OP_SORT_F64, OP_SORT_KV_I32, OP_PARTITION_I32, OP_SORT_SEGMENTED_I32, OP_SORT_U32, OP_SORT_I64,
+ OP_SORT_KV_F64) = range(8)
 PIVOT_AUTO, PIVOT_MEDIAN3, PIVOT_NINTHER, PIVOT_SAMPLE = range(4)
 
 _STATUS = {0: "HS_OK", -1: "HS_EINVAL", -2: "HS_ENOMEM", -3: "HS_EHIP", -4: "HS_EWORKSPACE",
@@ -77,6 +78,7 @@ _SIGS = {
     "hs_sort_i32": ([_P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_f64": ([_P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_kv_i32": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_sort_kv_f64": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_u32": ([_P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_i64": ([_P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_argsort_i32": ([_P, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
@@ -189,16 +191,19 @@ def argsort(keys, opts: Opts | None = None, stats: bool = False, out=None):
 
 
 def sort_kv_(keys, vals, opts: Opts | None = None, stats: bool = False):
-    """Sort int32 (key, value) pairs held in two tensors, in place, by key."""
+    """Sort (key, value) pairs held in two tensors, in place, by key: int32 or
+    float64 keys (totalOrder), int32 values; equal keys end up ordered by
+    their values' bits as unsigned integers."""
     torch = _torch()
-    _require(keys, (torch.int32,), "keys")
+    _require(keys, (torch.int32, torch.float64), "keys")
     _require(vals, (torch.int32,), "vals")
     if keys.numel() != vals.numel() or keys.device != vals.device:
         raise ValueError("keys and vals must have the same size and device")
+    fn = lib().hs_sort_kv_i32 if keys.dtype == torch.int32 else lib().hs_sort_kv_f64
     st = Stats() if stats else None
     with torch.cuda.device(keys.device):
-        _check(lib().hs_sort_kv_i32(keys.data_ptr(), vals.data_ptr(), keys.numel(), _opts_ptr(opts),
-                                    None if st is None else ctypes.addressof(st), _stream_handle(keys)))
+        _check(fn(keys.data_ptr(), vals.data_ptr(), keys.numel(), _opts_ptr(opts),
+                  None if st is None else ctypes.addressof(st), _stream_handle(keys)))
     return st.as_dict() if st is not None else (keys, vals)
 
 
@@ -327,11 +332,12 @@ def _sort_args(keys, vals=None, offsets=None):
         _require(offsets, (torch.int64,), "offsets")
         return OP_SORT_SEGMENTED_I32, keys.data_ptr(), None, keys.numel(), offsets.data_ptr(), offsets.numel() - 1
     if vals is not None:
-        _require(keys, (torch.int32,), "keys")
+        _require(keys, (torch.int32, torch.float64), "keys")
         _require(vals, (torch.int32,), "vals")
         if keys.numel() != vals.numel() or keys.device != vals.device:
             raise ValueError("keys and vals must have the same size and device")
-        return OP_SORT_KV_I32, keys.data_ptr(), vals.data_ptr(), keys.numel(), None, 0
+        op = OP_SORT_KV_I32 if keys.dtype == torch.int32 else OP_SORT_KV_F64
+        return op, keys.data_ptr(), vals.data_ptr(), keys.numel(), None, 0
     _require(keys, (torch.int32, torch.float64, torch.uint32, torch.int64), "keys")
     op = {torch.int32: OP_SORT_I32, torch.float64: OP_SORT_F64, torch.uint32: OP_SORT_U32,
           torch.int64: OP_SORT_I64}[keys.dtype]

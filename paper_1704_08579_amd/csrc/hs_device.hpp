@@ -1,9 +1,9 @@
 // hs_device.hpp -- device primitives of the gfx950 hybrid sort.
 //
 //  * order-key codecs: the caller's int32 / uint32 / int64 / float64 /
-//    (int32 key, int32 value) formats are mapped to unsigned words whose
-//    unsigned order is the key order, so every kernel compares plain
-//    unsigned integers;
+//    (int32 key, int32 value) / (float64 key, int32 value) formats are
+//    mapped to unsigned words whose unsigned order is the key order, so
+//    every kernel compares plain unsigned integers;
 //  * wavefront (64-lane) scan and lane shuffles;
 //  * the same-direction bitonic network of the paper (Sec. II-A, Fig. 2
 //    caption; Sec. III-A, Algorithms 1 and 2) held in VGPRs of one wave.
@@ -19,14 +19,21 @@ namespace hs {
 
 constexpr int WAVE = 64;
 
-enum Fmt : int { FMT_I32 = 0, FMT_F64 = 1, FMT_KV = 2, FMT_U32 = 3, FMT_I64 = 4 };
+enum Fmt : int { FMT_I32 = 0, FMT_F64 = 1, FMT_KV = 2, FMT_U32 = 3, FMT_I64 = 4, FMT_KV_F64 = 5 };
+
+// 128-bit order word of a (float64 key, int32 value) pair.
+using u128 = unsigned __int128;
 
 template <int F> struct KeyOf { using type = uint64_t; };
 template <> struct KeyOf<FMT_I32> { using type = uint32_t; };
 template <> struct KeyOf<FMT_U32> { using type = uint32_t; };
+template <> struct KeyOf<FMT_KV_F64> { using type = u128; };
 
 // Bytes of one key in the caller's key array.
-template <int F> constexpr int raw_key_bytes() { return F == FMT_F64 || F == FMT_I64 ? 8 : 4; }
+template <int F> constexpr int raw_key_bytes() { return F == FMT_F64 || F == FMT_I64 || F == FMT_KV_F64 ? 8 : 4; }
+
+// Formats with a value array beside the key array.
+template <int F> constexpr bool has_vals() { return F == FMT_KV || F == FMT_KV_F64; }
 
 // The caller's arrays, in the caller's format.
 struct Raw {
@@ -40,10 +47,11 @@ struct Raw {
 // unsigned order; uint32 keys are their own order words.  float64: IEEE
 // 754-2008 totalOrder -- negative values (sign bit set) have every bit
 // inverted, non-negative values get the sign bit set.
-// key/value: the int32 key's order word in the high half and the value's
-// bits in the low half, so a pair moves as one word and ties between equal
-// keys are broken by value (the method is unstable, so any tie order is a
-// valid output; this one is deterministic).
+// key/value: the key's order word in the high half and the value's bits in
+// the low half (int32 keys: a 64-bit word; float64 keys: a 128-bit word, the
+// value in its low 32 bits), so a pair moves as one word and ties between
+// equal keys are broken by value (the method is unstable, so any tie order
+// is a valid output; this one is deterministic).
 
 __device__ __forceinline__ uint32_t enc_i32(uint32_t bits) { return bits ^ 0x80000000u; }
 __device__ __forceinline__ uint32_t dec_i32(uint32_t k) { return k ^ 0x80000000u; }
@@ -58,6 +66,10 @@ __device__ __forceinline__ uint64_t dec_f64(uint64_t k)
 __device__ __forceinline__ uint64_t enc_kv(uint32_t key, uint32_t val)
 {
     return ((uint64_t)enc_i32(key) << 32) | val;
+}
+__device__ __forceinline__ u128 enc_kv_f64(uint64_t key_bits, uint32_t val)
+{
+    return ((u128)enc_f64(key_bits) << 64) | (u128)val;
 }
 __device__ __forceinline__ uint64_t enc_i64(uint64_t b) { return b ^ 0x8000000000000000ull; }
 __device__ __forceinline__ uint64_t dec_i64(uint64_t k) { return k ^ 0x8000000000000000ull; }
@@ -76,6 +88,8 @@ __device__ __forceinline__ typename KeyOf<F>::type raw_load(const Raw &r, uint32
 {
     if constexpr (F == FMT_KV) {
         return enc_kv(((const uint32_t *)r.keys)[i], (uint32_t)r.vals[i]);
+    } else if constexpr (F == FMT_KV_F64) {
+        return enc_kv_f64(((const uint64_t *)r.keys)[i], (uint32_t)r.vals[i]);
     } else {
         using K = typename KeyOf<F>::type;
         return enc_word<F>(((const K *)r.keys)[i]);
@@ -93,6 +107,9 @@ __device__ __forceinline__ void raw_store(const Raw &r, uint32_t i, typename Key
         ((uint64_t *)r.keys)[i] = dec_f64(k);
     } else if constexpr (F == FMT_I64) {
         ((uint64_t *)r.keys)[i] = dec_i64(k);
+    } else if constexpr (F == FMT_KV_F64) {
+        ((uint64_t *)r.keys)[i] = dec_f64((uint64_t)(k >> 64));
+        r.vals[i] = (int32_t)(uint32_t)k;
     } else {
         ((uint32_t *)r.keys)[i] = dec_i32((uint32_t)(k >> 32));
         r.vals[i] = (int32_t)(uint32_t)k;
@@ -154,6 +171,12 @@ template <int ML> __device__ __forceinline__ uint64_t xor_lanes(uint64_t v, int 
     const uint32_t hi = xor_lanes<ML>((uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
 }
+template <int ML> __device__ __forceinline__ u128 xor_lanes(u128 v, int lane)
+{
+    const uint64_t lo = xor_lanes<ML>((uint64_t)v, lane);
+    const uint64_t hi = xor_lanes<ML>((uint64_t)(v >> 64), lane);
+    return ((u128)hi << 64) | lo;
+}
 
 // Inclusive prefix sum over the 64 lanes of a wave: four DPP row shifts
 // give the scan inside each row of 16 lanes, then two row broadcasts carry
@@ -178,6 +201,10 @@ __device__ __forceinline__ uint32_t lane_bcast(uint32_t v, int src)
 __device__ __forceinline__ uint64_t lane_bcast(uint64_t v, int src)
 {
     return ((uint64_t)lane_bcast((uint32_t)(v >> 32), src) << 32) | lane_bcast((uint32_t)v, src);
+}
+__device__ __forceinline__ u128 lane_bcast(u128 v, int src)
+{
+    return ((u128)lane_bcast((uint64_t)(v >> 64), src) << 64) | lane_bcast((uint64_t)v, src);
 }
 
 // Number of set bits of a 64-bit lane mask below the calling lane.

@@ -159,6 +159,8 @@ template <typename K> struct PartCfg;
 // up to 6% slower end to end.
 template <> struct PartCfg<uint32_t> { static constexpr int NT = 1024, TILE = 16384; };
 template <> struct PartCfg<uint64_t> { static constexpr int NT = 1024, TILE = 8192; };
+// 16-byte words: the same 128 KB of keys in flight per workgroup pair.
+template <> struct PartCfg<u128> { static constexpr int NT = 1024, TILE = 4096; };
 
 // Write-cursor words of different segments sit 256 bytes apart: atomics on
 // one cache line serialize, so neighbouring segments must not share one.
@@ -504,6 +506,14 @@ __device__ __forceinline__ uint64_t rsrc_load64(__amdgpu_buffer_rsrc_t r, uint32
     return ((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0];
 }
 
+__device__ __forceinline__ u128 rsrc_load128(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0);
+    const uint64_t lo = ((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0];
+    const uint64_t hi = ((uint64_t)(uint32_t)w[3] << 32) | (uint32_t)w[2];
+    return ((u128)hi << 64) | lo;
+}
+
 // s_waitcnt on the vector-memory counter alone: at most n operations still
 // outstanding (gfx9 encoding: vmcnt bits 3:0 and 15:14; expcnt and lgkmcnt
 // left at their maxima).
@@ -596,6 +606,18 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
                 const uint32_t off = (uint32_t)(j * NT + tid) * 4u;
                 x[j] = enc_kv(rsrc_load32(rk, off), rsrc_load32(rv, off));
             }
+        } else if constexpr (SRC_IS_RAW && F == FMT_KV_F64) {
+            const auto rk = tile_rsrc((const uint64_t *)raw.keys + L.p0, L.cnt * 8u);
+            const auto rv = tile_rsrc((const uint32_t *)raw.vals + L.p0, L.cnt * 4u);
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t i = (uint32_t)(j * NT + tid);
+                x[j] = enc_kv_f64(rsrc_load64(rk, i * 8u), rsrc_load32(rv, i * 4u));
+            }
+        } else if constexpr (sizeof(K) == 16) {
+            const auto r = tile_rsrc(src + L.p0, L.cnt * 16u);
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) x[j] = rsrc_load128(r, (uint32_t)(j * NT + tid) * 16u);
         } else if constexpr (sizeof(K) == 4) {
             const auto r = tile_rsrc((SRC_IS_RAW ? (const K *)raw.keys : src) + L.p0, L.cnt * 4u);
 #pragma unroll
@@ -614,7 +636,7 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
     };
 
     // Stores issued by the write-out of one tile.
-    constexpr int STORES = ITEMS * ((DST_IS_RAW && F == FMT_KV) ? 2 : 1);
+    constexpr int STORES = ITEMS * ((DST_IS_RAW && has_vals<F>()) ? 2 : 1);
     static_assert(STORES < 64, "vmcnt is 6 bits");
 
     Seg<K> sg;

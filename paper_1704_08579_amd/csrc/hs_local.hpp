@@ -29,6 +29,8 @@ namespace hs {
 template <typename K> struct LocalCfg;
 template <> struct LocalCfg<uint32_t> { static constexpr int T = 8192, NT = 512, LEAF = 1024, LW = 1024, WPC = 4; };
 template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 512, LEAF = 512, LW = 512, WPC = 2; };
+// 16-byte words: half the keys in the same LDS, eight rows per span.
+template <> struct LocalCfg<u128> { static constexpr int T = 4096, NT = 512, LEAF = 256, LW = 256, WPC = 2; };
 
 // Sort the keys of one wave's registers (any load order) with the smallest
 // network that holds `sz` keys, and hand back key i of the sorted order to
@@ -442,9 +444,9 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
 // A whole array of at most LEAF keys: one wave loads it, sorts it with the
 // network and stores it back.  Nothing here can fail; lane 0 clears the
 // error word a graph plan reads after its replays.  The host sends arrays of
-// up to WAVE_NET keys this way, of either word size (one wave alone on a
-// SIMD has the registers for 16 eight-byte keys per lane).
-constexpr int WAVE_NET = 1024;
+// up to wave_net<K>() keys this way (one wave alone on a SIMD has the
+// registers for 16 eight-byte or 8 sixteen-byte keys per lane).
+template <typename K> constexpr int wave_net() { return sizeof(K) <= 8 ? 1024 : 512; }
 template <int F, int LEAF>
 __global__ __launch_bounds__(WAVE) void k_sort_wave(Ctl *ctl, Raw raw, uint32_t n)
 {

@@ -172,7 +172,7 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParam
         // the multiway pass routes up to NB_MAX buckets, fills in chunks
         if (P.on) L.task_cap += (uint32_t)(NB_MAX + n / FILL_CHUNK + 2);
         L.buf1 = take((size_t)n * sk);
-        if (op == HS_OP_SORT_KV_I32) L.buf0 = take((size_t)n * sk);
+        if (op == HS_OP_SORT_KV_I32 || op == HS_OP_SORT_KV_F64) L.buf0 = take((size_t)n * sk);
     }
     L.segA = take((size_t)L.cand_cap * sizeof(Seg<K>));
     L.segB = take((size_t)L.cand_cap * sizeof(Seg<K>));
@@ -257,7 +257,7 @@ int check_learn(const hs_opts *o)
 template <int F> constexpr int op_of()
 {
     return F == FMT_I32 ? HS_OP_SORT_I32 : F == FMT_F64 ? HS_OP_SORT_F64 : F == FMT_KV ? HS_OP_SORT_KV_I32
-         : F == FMT_U32 ? HS_OP_SORT_U32 : HS_OP_SORT_I64;
+         : F == FMT_U32 ? HS_OP_SORT_U32 : F == FMT_I64 ? HS_OP_SORT_I64 : HS_OP_SORT_KV_F64;
 }
 
 int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
@@ -277,6 +277,13 @@ int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
     case HS_OP_SORT_I64:
     case HS_OP_SORT_KV_I32:
         *L = make_layout<uint64_t>(op, n, nseg, local_limit<uint64_t>(o), learn_params(o, n, op));
+        return HS_OK;
+    case HS_OP_SORT_KV_F64:
+        // the learned front end (one 64-bit splitter word per bucket) is
+        // built for words of up to 64 bits
+        if (o && o->method == HS_METHOD_LEARNED)
+            return fail(HS_EINVAL, "learned splitters are not offered for float64 key/value pairs");
+        *L = make_layout<u128>(op, n, nseg, local_limit<u128>(o));
         return HS_OK;
     default:
         return fail(HS_EINVAL, "unknown op %d", op);
@@ -351,7 +358,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     const bool learned = P.on && (uint64_t)n > T;
 
     K *buf[2];
-    buf[0] = F == FMT_KV ? (K *)(ws + L.buf0) : (K *)raw.keys;
+    buf[0] = has_vals<F>() ? (K *)(ws + L.buf0) : (K *)raw.keys;
     buf[1] = (K *)(ws + L.buf1);
     Seg<K> *segs[2] = {(Seg<K> *)(ws + L.segA), (Seg<K> *)(ws + L.segB)};
     unsigned long long *curs[2] = {(unsigned long long *)(ws + L.curA), (unsigned long long *)(ws + L.curB)};
@@ -370,10 +377,11 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     // a whole array that one wave's network holds (1024 keys, unless the
     // caller lowered the on-chip limit or the network bound to force the
     // other tiers): a single launch, no read-back
-    const uint64_t wave_max = (o && o->leaf > 0) ? LEAF : (uint64_t)(T < WAVE_NET ? T : WAVE_NET);
+    constexpr uint32_t NET = (uint32_t)wave_net<K>();
+    const uint64_t wave_max = (o && o->leaf > 0) ? LEAF : (uint64_t)(T < NET ? T : NET);
     if (!learned && !d_off && (uint64_t)n <= wave_max) {
         if (st) HS_HIP(hipEventRecord(lev[0], stream));
-        HS_LAUNCH((k_sort_wave<F, WAVE_NET>), 1, WAVE, stream, ctl, raw, (uint32_t)n);
+        HS_LAUNCH((k_sort_wave<F, NET>), 1, WAVE, stream, ctl, raw, (uint32_t)n);
         if (st && !capturing) {
             HS_HIP(hipEventRecord(lev[1], stream));
             HS_HIP(hipEventSynchronize(lev[1]));
@@ -411,56 +419,60 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     int level0 = 0;
     LearnCtl *lctl = nullptr;
     if (learned) {
-        // ---- learned splitters and the multiway pass
-        lctl = (LearnCtl *)(ws + L.lctl);
-        Raw smp{ws + L.smp_k, F == FMT_KV ? (int32_t *)(ws + L.smp_v) : nullptr};
-        float *z = (float *)(ws + L.z), *y = (float *)(ws + L.y);
-        float *par = (float *)(ws + L.par), *mom = (float *)(ws + L.mom), *vel = (float *)(ws + L.vel);
-        float *part = (float *)(ws + L.part), *lossb = (float *)(ws + L.lossb);
-        K *msplit = (K *)(ws + L.msplit), *ssplit = (K *)(ws + L.ssplit), *chosen = (K *)(ws + L.chosen);
-        K *hold = (K *)(ws + L.hold);
-        uint32_t *hist = (uint32_t *)(ws + L.hist), *btot = (uint32_t *)(ws + L.btot);
-        uint32_t *bstart = (uint32_t *)(ws + L.bstart);
-        if (st) HS_HIP(hipEventRecord(lev[2], stream));
-        HS_LAUNCH(k_zero_words, 1, 256, stream, (uint32_t *)lctl, (uint32_t)(sizeof(LearnCtl) / 4));
-        // sample draws: the training sample from splitmix64(seed), the
-        // held-out sample from splitmix64(seed + 1), the weights from
-        // splitmix64(seed + 2)
-        HS_LAUNCH(k_ls_sample<F>, (P.m + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed, P.m, smp);
-        HS_LAUNCH(k_ls_holdout<F>, (P.h + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed + 1, P.h, hold);
-        const Layout S = make_layout<K>(op_of<F>(), P.m, 1, T);
-        int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
-        if (rc) return rc;
-        HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl);
-        const uint32_t gblk = (P.m + 255) / 256;
-        if (P.mode != JUDGE_SAMPLE) {
-            HS_LAUNCH(k_mlp_init, (MLP_NP + 255) / 256, 256, stream, par, mom, vel, P.seed + 2);
-            for (int t = 1; t <= P.steps; ++t) {
-                const bool last = t == P.steps;
-                HS_LAUNCH(k_mlp_grad, gblk, 256, stream, par, z, y, P.m, part, lossb);
-                HS_LAUNCH(k_mlp_update, MLP_UPDATE_GRID, 256, stream, par, mom, vel, part, gblk, t, P.lr,
-                          (float *)nullptr, lossb, last ? lossb + gblk : (float *)nullptr, P.m);
+        if constexpr (F == FMT_KV_F64) {
+            return fail(HS_EINVAL, "learned splitters are not offered for float64 key/value pairs");
+        } else {
+            // ---- learned splitters and the multiway pass
+            lctl = (LearnCtl *)(ws + L.lctl);
+            Raw smp{ws + L.smp_k, F == FMT_KV ? (int32_t *)(ws + L.smp_v) : nullptr};
+            float *z = (float *)(ws + L.z), *y = (float *)(ws + L.y);
+            float *par = (float *)(ws + L.par), *mom = (float *)(ws + L.mom), *vel = (float *)(ws + L.vel);
+            float *part = (float *)(ws + L.part), *lossb = (float *)(ws + L.lossb);
+            K *msplit = (K *)(ws + L.msplit), *ssplit = (K *)(ws + L.ssplit), *chosen = (K *)(ws + L.chosen);
+            K *hold = (K *)(ws + L.hold);
+            uint32_t *hist = (uint32_t *)(ws + L.hist), *btot = (uint32_t *)(ws + L.btot);
+            uint32_t *bstart = (uint32_t *)(ws + L.bstart);
+            if (st) HS_HIP(hipEventRecord(lev[2], stream));
+            HS_LAUNCH(k_zero_words, 1, 256, stream, (uint32_t *)lctl, (uint32_t)(sizeof(LearnCtl) / 4));
+            // sample draws: the training sample from splitmix64(seed), the
+            // held-out sample from splitmix64(seed + 1), the weights from
+            // splitmix64(seed + 2)
+            HS_LAUNCH(k_ls_sample<F>, (P.m + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed, P.m, smp);
+            HS_LAUNCH(k_ls_holdout<F>, (P.h + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed + 1, P.h, hold);
+            const Layout S = make_layout<K>(op_of<F>(), P.m, 1, T);
+            int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
+            if (rc) return rc;
+            HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl);
+            const uint32_t gblk = (P.m + 255) / 256;
+            if (P.mode != JUDGE_SAMPLE) {
+                HS_LAUNCH(k_mlp_init, (MLP_NP + 255) / 256, 256, stream, par, mom, vel, P.seed + 2);
+                for (int t = 1; t <= P.steps; ++t) {
+                    const bool last = t == P.steps;
+                    HS_LAUNCH(k_mlp_grad, gblk, 256, stream, par, z, y, P.m, part, lossb);
+                    HS_LAUNCH(k_mlp_update, MLP_UPDATE_GRID, 256, stream, par, mom, vel, part, gblk, t, P.lr,
+                              (float *)nullptr, lossb, last ? lossb + gblk : (float *)nullptr, P.m);
+                }
+                HS_LAUNCH(k_ls_invert<F>, (NSPLIT * WAVE + 255) / 256, 256, stream, par, lctl, msplit);
             }
-            HS_LAUNCH(k_ls_invert<F>, (NSPLIT * WAVE + 255) / 256, 256, stream, par, lctl, msplit);
+            HS_LAUNCH(k_ls_judge<K>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode);
+            if (st) HS_HIP(hipEventRecord(lev[3], stream));
+            uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
+            const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 8 - 1) / ((uint64_t)d->ncu * 8));
+            if (chunk < cmin) chunk = cmin;
+            chunk = (chunk + MW_TILE - 1) / MW_TILE * MW_TILE;
+            const uint32_t G = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
+            HS_LAUNCH((k_mw_hist<F, true>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk, chosen, lctl,
+                      hist);
+            HS_LAUNCH(k_mw_scan_cols, NB_MAX, 1024, stream, hist, G, lctl, btot);
+            HS_LAUNCH(k_mw_scan_starts, 1, 1024, stream, btot, lctl, bstart);
+            HS_LAUNCH((k_mw_scatter<F, true, false>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk,
+                      chosen, lctl, hist, bstart, buf[1], Raw{});
+            // the buckets are in buffer 1, where level 1 reads: they form level 1's list
+            HS_LAUNCH(k_mw_route<F>, (NB_MAX + 255) / 256, 256, stream, ctl, lctl, bstart, chosen, buf[1], SRC_BUF1,
+                      segs[1], curs[1], tasks, T, LEAF, rule, L.cand_cap, L.task_cap);
+            if (st) HS_HIP(hipEventRecord(lev[4], stream));
+            level0 = 1;
         }
-        HS_LAUNCH(k_ls_judge<K>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode);
-        if (st) HS_HIP(hipEventRecord(lev[3], stream));
-        uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
-        const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 8 - 1) / ((uint64_t)d->ncu * 8));
-        if (chunk < cmin) chunk = cmin;
-        chunk = (chunk + MW_TILE - 1) / MW_TILE * MW_TILE;
-        const uint32_t G = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
-        HS_LAUNCH((k_mw_hist<F, true>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk, chosen, lctl,
-                  hist);
-        HS_LAUNCH(k_mw_scan_cols, NB_MAX, 1024, stream, hist, G, lctl, btot);
-        HS_LAUNCH(k_mw_scan_starts, 1, 1024, stream, btot, lctl, bstart);
-        HS_LAUNCH((k_mw_scatter<F, true, false>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk,
-                  chosen, lctl, hist, bstart, buf[1], Raw{});
-        // the buckets are in buffer 1, where level 1 reads: they form level 1's list
-        HS_LAUNCH(k_mw_route<F>, (NB_MAX + 255) / 256, 256, stream, ctl, lctl, bstart, chosen, buf[1], SRC_BUF1,
-                  segs[1], curs[1], tasks, T, LEAF, rule, L.cand_cap, L.task_cap);
-        if (st) HS_HIP(hipEventRecord(lev[4], stream));
-        level0 = 1;
     } else if (d_off) {
         const uint32_t g = (uint32_t)((nseg + 255) / 256);  // one wave per 64 segments
         HS_LAUNCH(k_init_segmented<F>, g, 256, stream, ctl, segs[0], curs[0], tasks, raw, d_off, (uint32_t)nseg,
@@ -691,7 +703,7 @@ int autotune_impl(DevState *d, int op, Raw raw, int64_t n, const int64_t *d_off,
             return HS_OK;
         }
     }
-    const size_t kb = (size_t)n * raw_key_bytes<F>(), vb = F == FMT_KV ? (size_t)n * 4 : 0;
+    const size_t kb = (size_t)n * raw_key_bytes<F>(), vb = has_vals<F>() ? (size_t)n * 4 : 0;
     DevBuf src, work, ref, cnt;
     auto alloc = [&](DevBuf &x, size_t bytes) -> int {
         if (hipMalloc(&x.p, bytes ? bytes : 8) != hipSuccess) {
@@ -816,9 +828,12 @@ int check_sort_args(int op, const void *keys, const int32_t *vals, int64_t n, co
     case HS_OP_SORT_I64:
         break;
     case HS_OP_SORT_KV_I32:
+    case HS_OP_SORT_KV_F64: {
+        const size_t kb = op == HS_OP_SORT_KV_F64 ? 8 : 4;
         if (n > 0 && !vals) return fail(HS_EINVAL, "vals is NULL");
-        if (n > 0 && overlap(keys, (size_t)n * 4, vals, (size_t)n * 4)) return fail(HS_EINVAL, "keys and vals overlap");
+        if (n > 0 && overlap(keys, (size_t)n * kb, vals, (size_t)n * 4)) return fail(HS_EINVAL, "keys and vals overlap");
         break;
+    }
     case HS_OP_SORT_SEGMENTED_I32:
         if (nseg < 0 || nseg >= ((int64_t)1 << 31)) return fail(HS_EINVAL, "nseg = %lld out of range", (long long)nseg);
         if (nseg > 0 && !d_off) return fail(HS_EINVAL, "d_offsets is NULL");
@@ -845,6 +860,8 @@ template <typename Fn> int with_format(int op, Fn &&fn)
         return fn(std::integral_constant<int, FMT_U32>());
     case HS_OP_SORT_I64:
         return fn(std::integral_constant<int, FMT_I64>());
+    case HS_OP_SORT_KV_F64:
+        return fn(std::integral_constant<int, FMT_KV_F64>());
     default:
         return fail(HS_EINVAL, "op %d is not a sort", op);
     }
@@ -982,6 +999,22 @@ int hs_sort_kv_i32(int32_t *keys, int32_t *vals, int64_t n, const hs_opts *opts,
     DevState *d;
     if ((rc = get_device(&d))) return rc;
     return run_sort<FMT_KV>(d, Raw{keys, vals}, n, nullptr, 0, opts, stats, (hipStream_t)stream);
+}
+
+int hs_sort_kv_f64(double *keys, int32_t *vals, int64_t n, const hs_opts *opts, hs_stats *stats, void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n > 0 && (!keys || !vals)) return fail(HS_EINVAL, "keys or vals is NULL");
+    if (n > 0 && overlap(keys, (size_t)n * 8, vals, (size_t)n * 4))
+        return fail(HS_EINVAL, "keys and vals overlap");
+    if (opts && opts->method == HS_METHOD_LEARNED)
+        return fail(HS_EINVAL, "learned splitters are not offered for float64 key/value pairs");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n <= 1) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    return run_sort<FMT_KV_F64>(d, Raw{keys, vals}, n, nullptr, 0, opts, stats, (hipStream_t)stream);
 }
 
 int hs_sort_segmented_i32(int32_t *keys, int64_t n_total, const int64_t *d_offsets, int64_t nseg,
@@ -1294,7 +1327,8 @@ int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *
     int graph_levels = 0;
     {
         const bool w32 = op == HS_OP_SORT_I32 || op == HS_OP_SORT_U32 || op == HS_OP_SORT_SEGMENTED_I32;
-        const uint32_t T = w32 ? local_limit<uint32_t>(&o) : local_limit<uint64_t>(&o);
+        const uint32_t T = w32 ? local_limit<uint32_t>(&o)
+                         : op == HS_OP_SORT_KV_F64 ? local_limit<u128>(&o) : local_limit<uint64_t>(&o);
         uint64_t biggest = (uint64_t)n;
         if (op == HS_OP_SORT_SEGMENTED_I32) {
             std::vector<int64_t> h_off((size_t)nseg + 1);

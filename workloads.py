@@ -8,8 +8,8 @@ The paper benchmarks "randomly generated values" (Sec. IV-A).  The recipes
 below add the distributions of the workloads this library is measured on:
   * uniform int32 over the full range;
   * float64 uniform [0,1), standard normal, already sorted, reverse sorted;
-  * int32 key/value pairs with 2^16 distinct keys (heavy duplicates) and the
-    original index as value;
+  * int32 and float64 key/value pairs with 2^16 distinct keys (heavy
+    duplicates) and the original index as value;
   * batched segments with log-uniform sizes;
   * float64 lognormal(0, 2), Zipf(1.1) ranks over 2^24 values, and an
     8-component Gaussian mixture.
@@ -76,6 +76,23 @@ def kv_dup_i32(n: int, seed: int = 4, ndistinct: int = 1 << 16, force_extremes: 
         table[0] = -(2 ** 31)
         table[-1] = 2 ** 31 - 1
     table = table.astype(np.int32)
+    keys = table[g.integers(0, ndistinct, n)]
+    vals = np.arange(n, dtype=np.int32)
+    return keys, vals
+
+
+def kv_dup_f64(n: int, seed: int = 6, ndistinct: int = 1 << 16, specials: bool = False):
+    """float64 keys drawn from a table of `ndistinct` distinct N(0,1) values
+    (with `specials`, the table's first entries are signed zeros, NaNs,
+    infinities and denormals); values = index."""
+    g = rng(seed)
+    if not 2 <= ndistinct <= (1 << 24):
+        raise ValueError("ndistinct out of range")
+    table = np.unique(g.standard_normal(ndistinct + 64))
+    table = g.permutation(table)[:ndistinct]
+    if specials:
+        s = f64_specials().view(np.uint64)  # NaN payloads copied as bits
+        table.view(np.uint64)[:min(s.size, ndistinct)] = s[:ndistinct]
     keys = table[g.integers(0, ndistinct, n)]
     vals = np.arange(n, dtype=np.int32)
     return keys, vals
