@@ -286,15 +286,15 @@ def run_small(reps=40):
     dev = torch.device("cuda")
     out = {"single": {}, "batched_i32": {}}
     sizes = [2, 16, 64, 256, 512, 1024, 2048, 8192, 65536]
-    for kind in ("i32", "f64", "kv"):
+    for kind in ("i32", "f64", "kv", "kvf64"):
         rows = {}
         for n in sizes:
-            if kind == "f64":
+            if kind in ("f64", "kvf64"):
                 src = torch.from_numpy(workloads.f64(n, "uniform", seed=n)).to(dev)
             else:
                 src = torch.from_numpy(workloads.uniform_i32(n, seed=n)).to(dev)
             t = src.clone()
-            v = torch.arange(n, dtype=torch.int32, device=dev) if kind == "kv" else None
+            v = torch.arange(n, dtype=torch.int32, device=dev) if kind in ("kv", "kvf64") else None
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             gpu_us, wall_us = [], []
             for r in range(reps + 5):
@@ -302,7 +302,7 @@ def run_small(reps=40):
                 torch.cuda.synchronize()
                 w0 = time.perf_counter()
                 e0.record()
-                if kind == "kv":
+                if v is not None:
                     hs.sort_kv_(t, v)
                 else:
                     hs.sort_(t)
