@@ -51,7 +51,15 @@ CONFIGS = {
                                     "(no training) on the inputs of learned_2e28"),
     "plain_2e28_learned_inputs": ("f64", 1 << 28, ["lognormal", "zipf", "mixture"], 6,
                                   "sort_f64 (plain method) on the inputs of learned_2e28"),
+    "f64_2e27_inplace": ("f64", 1 << 27, ["uniform", "normal", "sorted", "reverse"], 2,
+                         "sort_f64 with the partition levels in place (no second copy of the keys), "
+                         "2^27 float64 keys x 4 distributions"),
+    "i32_2e28_inplace": ("i32", 1 << 28, None, 1,
+                         "sort_i32 with the partition levels in place, 2^28 int32 keys uniform over the full range"),
 }
+
+# configurations sorted with the partition levels in place
+INPLACE = {"f64_2e27_inplace", "i32_2e28_inplace"}
 
 # configurations sorted with the learned-splitter method: name -> learn_flags
 LEARNED = {"learned_2e28": 0, "sampled_2e28_learned_inputs": 2}
@@ -136,6 +144,7 @@ def run_gpu(name, steps, warmup, driver=0):
     del inputs
     opts = hs.learned_opts(seed=100, flags=LEARNED[name]) if name in LEARNED else hs.Opts()
     opts.driver = driver
+    opts.inplace = 1 if name in INPLACE else 0
     learn = {d: [] for d in dists} if name in LEARNED else None
     graph = None
     if CONFIGS[name][0] == "seg":
@@ -358,7 +367,8 @@ def main():
     extra = {}
     if args.extra:
         for nm in ["i32_2e28", "kv_2e28", "kvf64_2e27", "seg_A", "seg_B", "i32_2e20", "learned_2e28",
-                   "sampled_2e28_learned_inputs", "plain_2e28_learned_inputs"]:
+                   "sampled_2e28_learned_inputs", "plain_2e28_learned_inputs", "f64_2e27_inplace",
+                   "i32_2e28_inplace"]:
             if nm == args.config:
                 continue
             e = run_gpu(nm, max(3, args.steps // 2), 1, driver)

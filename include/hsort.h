@@ -141,7 +141,10 @@ typedef struct hs_opts {
                            * workgroup on-chip sort */
     int32_t autotune;     /* 1: use (or first measure and remember) the tuned knobs for this operation and
                            * size class; see hs_autotune */
-    int32_t reserved;
+    int32_t inplace;      /* 1: partition levels in place in the caller's arrays (no second copy of the keys
+                           * in the workspace: one bit per key and 4 bytes per 64 keys instead); host-driven
+                           * levels only (not with HS_DRIVER_PERSISTENT, a plan, the autotuner or the learned
+                           * method, which return HS_EINVAL).  Output identical, slower per level */
     uint64_t seed;        /* learned method: seed of the sample draws and the initial weights */
     void *workspace;      /* caller-owned device scratch, or NULL */
     size_t workspace_bytes;

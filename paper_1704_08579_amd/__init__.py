@@ -65,7 +65,7 @@ class Opts(ctypes.Structure):
                 ("train_steps", ctypes.c_int32), ("sample_log2", ctypes.c_int32),
                 ("learning_rate", ctypes.c_float), ("driver", ctypes.c_int32),
                 ("spin_limit", ctypes.c_int32), ("leaf", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("inplace", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 

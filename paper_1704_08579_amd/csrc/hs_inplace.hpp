@@ -1,0 +1,424 @@
+// hs_inplace.hpp -- partition levels in place, without the ping-pong buffers.
+//
+// The paper partitions in place (Sec. III-B, Algorithm 3): vectors are loaded
+// from both ends of the array and written back into the space already freed
+// at the left or right end, so that no second array is needed.  That scheme
+// is sequential in its two write cursors.  Here every segment of a level is
+// partitioned in place by many workgroups at once, in four passes that
+// never wait on each other inside a kernel:
+//
+//   classify  every key of the level is compared with its segment's pivot
+//             once; the outcome is kept as one bit per key (64-key rows of
+//             the level's tiles) and the segment's count of keys on the low
+//             side is added up.  That count fixes the split point `mid`;
+//   rows      for every row, the keys on the wrong side of `mid` are counted:
+//             high keys before `mid` ("left-misplaced") and low keys from
+//             `mid` on ("right-misplaced"), with an exclusive prefix over the
+//             rows of each tile;
+//   scan      one workgroup turns the tiles' totals into level-wide exclusive
+//             prefixes;
+//   swap      the k-th left-misplaced key of a segment trades places with its
+//             k-th right-misplaced key.  Both counts are equal (the low side
+//             holds exactly `mid - b` slots), ranks come from the prefixes,
+//             and a wave finds the partner of its first key by binary search
+//             over the segment's tiles and the tile's rows, then walks on
+//             through the rows' masks.  Every position is read and written by
+//             exactly one lane, and the passes that located it only read the
+//             masks, so no key can be seen half-moved.
+//
+// Extra memory: one bit per key plus 32 bits per 64-key row and a few words
+// per tile, against a second copy of the keys for the out-of-place levels.
+// The keys stay in the caller's format between levels (order words are
+// formed on each read; a swap moves the caller's bits, and its values too).
+#pragma once
+
+#include "hs_kernels.hpp"
+
+namespace hs {
+
+// 64-key rows per partition tile.
+template <typename K> constexpr int ip_rows() { return PartCfg<K>::TILE / WAVE; }
+
+constexpr int IP_NT = 256;  // threads per workgroup of the row and swap passes
+
+// The level's tile count, bounded by the tiles of the segments in its list
+// (as in the out-of-place pass).
+template <typename K>
+__device__ __forceinline__ uint32_t ip_level_tiles(const Ctl *ctl, int par, const Seg<K> *segs, uint32_t cap,
+                                                   uint32_t &nseg)
+{
+    const unsigned long long st = ctl->lev[par].segs_tiles;
+    nseg = level_segs(st, cap);
+    if (nseg == 0) return 0;
+    const Seg<K> last = segs[nseg - 1];
+    return min((uint32_t)(st >> 32), last.tile0 + seg_tiles<K>(last.b, last.e));
+}
+
+// Tile t of a segment: its first key and key count.
+template <typename K>
+__device__ __forceinline__ void ip_tile_range(const Seg<K> &sg, uint32_t t, uint32_t &p0, uint32_t &cnt)
+{
+    constexpr uint32_t TILE = PartCfg<K>::TILE;
+    const uint32_t a = sg.b / TILE + (t - sg.tile0);
+    p0 = max(sg.b, a * TILE);
+    cnt = min(sg.e, (a + 1) * TILE) - p0;
+}
+
+// Segment holding tile t (every tile holds at least one key).
+template <typename K>
+__device__ __forceinline__ uint32_t ip_find_seg(const Seg<K> *segs, uint32_t nseg, uint32_t t)
+{
+    uint32_t lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (segs[m].tile0 <= t) lo = m; else hi = m;
+    }
+    return lo;
+}
+
+// Local indices [0, lim) of a tile starting at p0 with cnt keys lie before mid.
+__device__ __forceinline__ uint32_t ip_left_limit(uint32_t mid, uint32_t p0, uint32_t cnt)
+{
+    return mid > p0 ? min(mid - p0, cnt) : 0u;
+}
+
+// Position (0..63) of the k-th set bit of m (k < popcount(m)): halve the
+// window while keeping the bit inside it.
+__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const uint64_t low = m & ((1ull << s) - 1ull);
+        const uint32_t c = popc(low);
+        if (k >= c) {
+            k -= c;
+            m >>= s;
+            pos += (uint32_t)s;
+        } else {
+            m = low;
+        }
+    }
+    return pos;
+}
+
+// Pass 1: classify.  Workgroups take tiles in a grid-stride loop; lane `tid`
+// reads keys j*NT + tid of the tile (consecutive lanes, consecutive
+// addresses), so wave w's j-th ballot is row j*NT/64 + w of the tile.  One
+// 64-bit atomic per tile adds (low count, high count) to the segment's cursor
+// word, which the finalize step reads like that of the out-of-place pass.
+// With begin_level set, the first thread also does the level's bookkeeping.
+template <int F>
+__global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_ip_classify(
+    Ctl *ctl, int par, int begin_level, const Seg<typename KeyOf<F>::type> *segs, unsigned long long *cur, Raw raw,
+    uint64_t *mask, uint32_t cap)
+{
+    using K = typename KeyOf<F>::type;
+    constexpr int NT = PartCfg<K>::NT, TILE = PartCfg<K>::TILE, ITEMS = TILE / NT, RPT = ip_rows<K>();
+    constexpr int NW = NT / WAVE;
+    __shared__ uint32_t s_le[NW];
+    if (begin_level && blockIdx.x == 0 && threadIdx.x == 0) level_begin(ctl, par);
+    uint32_t nseg = 0;
+    const uint32_t ntiles = ip_level_tiles<K>(ctl, par, segs, cap, nseg);
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t s = ip_find_seg<K>(segs, nseg, t);
+        const Seg<K> sg = segs[s];
+        uint32_t p0, cnt;
+        ip_tile_range<K>(sg, t, p0, cnt);
+        const bool strict = (sg.flags & SEG_STRICT) != 0;
+        const bool none = strict && sg.piv == K(0);
+        const K lim = strict ? sg.piv - K(1) : sg.piv;
+        K x[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) x[j] = raw_load<F>(raw, p0 + min((uint32_t)(j * NT + tid), cnt - 1));
+        uint32_t le = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const bool lo = (uint32_t)(j * NT + tid) < cnt && !none && x[j] <= lim;
+            const uint64_t m = ballot(lo);
+            if (lane == 0) mask[(size_t)t * RPT + (uint32_t)(j * NW + w)] = m;
+            le += (uint32_t)lo;
+        }
+        const uint32_t ws = wave_sum(le);
+        if (lane == 0) s_le[w] = ws;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t tot = 0;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) tot += s_le[k];
+            atomicAdd(&cur[(size_t)s * CUR_STRIDE], (unsigned long long)tot | ((unsigned long long)(cnt - tot) << 32));
+        }
+        __syncthreads();
+    }
+}
+
+// Pass 2: rows.  Thread r of a workgroup takes row r of the tile; rowpre
+// receives the exclusive prefix over the tile's rows of (left-misplaced |
+// right-misplaced << 16) and tot the tile's two totals.
+template <int F>
+__global__ __launch_bounds__(IP_NT) void k_ip_rows(const Ctl *ctl, int par, const Seg<typename KeyOf<F>::type> *segs,
+                                                   const unsigned long long *cur, const uint64_t *mask,
+                                                   uint32_t *rowpre, uint32_t *tot, uint32_t cap)
+{
+    using K = typename KeyOf<F>::type;
+    constexpr int RPT = ip_rows<K>();
+    constexpr int NW = IP_NT / WAVE;
+    static_assert(RPT <= IP_NT, "one thread per row");
+    __shared__ uint32_t s_w[NW];
+    uint32_t nseg = 0;
+    const uint32_t ntiles = ip_level_tiles<K>(ctl, par, segs, cap, nseg);
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t s = ip_find_seg<K>(segs, nseg, t);
+        const Seg<K> sg = segs[s];
+        uint32_t p0, cnt;
+        ip_tile_range<K>(sg, t, p0, cnt);
+        const uint32_t mid = sg.b + (uint32_t)cur[(size_t)s * CUR_STRIDE];
+        const uint32_t lim = ip_left_limit(mid, p0, cnt);
+        uint32_t c = 0;
+        if (tid < RPT) {
+            const uint32_t r0 = (uint32_t)tid * WAVE;
+            const uint64_t lo = mask[(size_t)t * RPT + tid];  // no bits past the tile's keys
+            const uint64_t valid = r0 < cnt ? lanes_below(cnt - r0) : 0ull;
+            const uint64_t left = r0 < lim ? lanes_below(lim - r0) : 0ull;
+            c = popc(~lo & valid & left) | (popc(lo & ~left) << 16);
+        }
+        const uint32_t incl = wave_incl_scan(c);
+        if (lane == WAVE - 1) s_w[w] = incl;
+        __syncthreads();
+        uint32_t pre = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const uint32_t v = s_w[k];
+            if (k < w) pre += v;
+            all += v;
+        }
+        if (tid < RPT) rowpre[(size_t)t * RPT + tid] = pre + incl - c;
+        if (tid == 0) {
+            tot[2 * (size_t)t] = all & 0xFFFFu;
+            tot[2 * (size_t)t + 1] = all >> 16;
+        }
+        __syncthreads();
+    }
+}
+
+// Pass 3: scan.  One workgroup: gp[2t] and gp[2t+1] receive the exclusive
+// prefixes over the level's tiles of the left- and right-misplaced totals.
+template <int F>
+__global__ __launch_bounds__(1024) void k_ip_scan(const Ctl *ctl, int par, const Seg<typename KeyOf<F>::type> *segs,
+                                                  const uint32_t *tot, uint32_t *gp, uint32_t cap)
+{
+    using K = typename KeyOf<F>::type;
+    constexpr int NW = 1024 / WAVE;
+    __shared__ uint32_t s_l[NW], s_r[NW];
+    uint32_t nseg = 0;
+    const uint32_t ntiles = ip_level_tiles<K>(ctl, par, segs, cap, nseg);
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
+    uint32_t carry_l = 0, carry_r = 0;
+    for (uint32_t base = 0; base < ntiles; base += 1024) {
+        const uint32_t i = base + (uint32_t)tid;
+        const uint32_t vl = i < ntiles ? tot[2 * (size_t)i] : 0u, vr = i < ntiles ? tot[2 * (size_t)i + 1] : 0u;
+        const uint32_t il = wave_incl_scan(vl), ir = wave_incl_scan(vr);
+        if (lane == WAVE - 1) {
+            s_l[w] = il;
+            s_r[w] = ir;
+        }
+        __syncthreads();
+        uint32_t pl = 0, pr = 0, al = 0, ar = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const uint32_t a = s_l[k], b = s_r[k];
+            if (k < w) {
+                pl += a;
+                pr += b;
+            }
+            al += a;
+            ar += b;
+        }
+        if (i < ntiles) {
+            gp[2 * (size_t)i] = carry_l + pl + il - vl;
+            gp[2 * (size_t)i + 1] = carry_r + pr + ir - vr;
+        }
+        carry_l += al;
+        carry_r += ar;
+        __syncthreads();
+    }
+}
+
+// Load and store halves of an exchange (keys, and values for the key/value
+// formats), so that the loads of several exchanges can be in flight at once.
+template <int F> struct RawElem {
+    uint64_t k;
+    int32_t v;
+};
+template <int F> __device__ __forceinline__ RawElem<F> raw_get(const Raw &r, uint32_t i)
+{
+    RawElem<F> e;
+    if constexpr (raw_key_bytes<F>() == 8) e.k = ((const uint64_t *)r.keys)[i];
+    else e.k = ((const uint32_t *)r.keys)[i];
+    if constexpr (has_vals<F>()) e.v = r.vals[i];
+    else e.v = 0;
+    return e;
+}
+template <int F> __device__ __forceinline__ void raw_put(const Raw &r, uint32_t i, const RawElem<F> &e)
+{
+    if constexpr (raw_key_bytes<F>() == 8) ((uint64_t *)r.keys)[i] = e.k;
+    else ((uint32_t *)r.keys)[i] = (uint32_t)e.k;
+    if constexpr (has_vals<F>()) r.vals[i] = e.v;
+}
+
+// Lane `src` (wave-uniform) of a 64-bit value.
+__device__ __forceinline__ uint64_t lane_get64(uint64_t v, uint32_t src)
+{
+    return ((uint64_t)lane_bcast((uint32_t)(v >> 32), (int)src) << 32) | lane_bcast((uint32_t)v, (int)src);
+}
+
+// Pass 4: swap.  Workgroups take tiles with left-misplaced keys; wave w
+// takes a contiguous run of the tile's rows before mid.  The partners of a
+// run's left-misplaced keys are consecutive right-misplaced keys of the
+// segment, so the wave finds the first one by binary search (over the
+// segment's tiles, then the tile's rows: wave-uniform) and then walks
+// forward through the right-misplaced bits row by row, handing partners to
+// its lanes in rank order.  The masks of the run's rows and of the next 64
+// right rows sit one per lane (one load each), so the walk itself reads
+// registers; the exchanges of SB rows are issued together, their loads all
+// in flight before the first store.
+template <int F>
+__global__ __launch_bounds__(IP_NT) void k_ip_swap(Ctl *ctl, int par, const Seg<typename KeyOf<F>::type> *segs,
+                                                   const unsigned long long *cur, const uint64_t *mask,
+                                                   const uint32_t *rowpre, const uint32_t *tot, const uint32_t *gp,
+                                                   Raw raw, uint32_t cap)
+{
+    using K = typename KeyOf<F>::type;
+    constexpr int RPT = ip_rows<K>();
+    constexpr int NW = IP_NT / WAVE;
+    constexpr uint32_t CH = (RPT + NW - 1) / NW;  // rows per wave
+    constexpr int SB = 8;                         // rows whose exchanges are issued together
+    static_assert(CH <= (uint32_t)WAVE && CH % SB == 0, "a wave's rows fit one mask per lane");
+    uint32_t nseg = 0;
+    const uint32_t ntiles = ip_level_tiles<K>(ctl, par, segs, cap, nseg);
+    const int tid = threadIdx.x, lane = lane_id();
+    const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane(tid / WAVE);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        if (tot[2 * (size_t)t] == 0) continue;
+        const uint32_t s = ip_find_seg<K>(segs, nseg, t);
+        const Seg<K> sg = segs[s];
+        uint32_t p0, cnt;
+        ip_tile_range<K>(sg, t, p0, cnt);
+        const uint32_t t0 = sg.tile0, tend = t0 + seg_tiles<K>(sg.b, sg.e);
+        const uint32_t mid = sg.b + (uint32_t)cur[(size_t)s * CUR_STRIDE];
+        const uint32_t lim = ip_left_limit(mid, p0, cnt);
+        const uint32_t rbeg = w * CH, rend = min(rbeg + CH, (lim + WAVE - 1) / WAVE);
+        if (rbeg >= rend) continue;
+        const uint32_t pre_beg = rowpre[(size_t)t * RPT + rbeg] & 0xFFFFu;
+        const uint32_t pre_end = rend < (uint32_t)RPT ? rowpre[(size_t)t * RPT + rend] & 0xFFFFu : tot[2 * (size_t)t];
+        if (pre_beg == pre_end) continue;  // no left-misplaced key in this run of rows
+        // the run's left-misplaced masks, row rbeg + k in lane k
+        uint64_t own = 0;
+        {
+            const uint32_t r = rbeg + (uint32_t)lane;
+            if (r < rend) {
+                const uint32_t r0 = r * WAVE;
+                own = ~mask[(size_t)t * RPT + r] & lanes_below(cnt - r0) & lanes_below(lim - r0);
+            }
+        }
+        // global right index of the run's first partner
+        const uint32_t g = gp[2 * (size_t)t0 + 1] + (gp[2 * (size_t)t] - gp[2 * (size_t)t0]) + pre_beg;
+        uint32_t t2 = t0, hi_t = tend;
+        while (hi_t - t2 > 1) {
+            const uint32_t m = (t2 + hi_t) >> 1;
+            if (gp[2 * (size_t)m + 1] <= g) t2 = m; else hi_t = m;
+        }
+        const uint32_t q = g - gp[2 * (size_t)t2 + 1];
+        uint32_t r2 = 0, hi_r = RPT;
+        while (hi_r - r2 > 1) {
+            const uint32_t m = (r2 + hi_r) >> 1;
+            if ((rowpre[(size_t)t2 * RPT + m] >> 16) <= q) r2 = m; else hi_r = m;
+        }
+        const uint32_t k2 = q - (rowpre[(size_t)t2 * RPT + r2] >> 16);
+        // the walk: tile t2 (keys p02.., lim2 of them before mid), row r2, a
+        // block of right-misplaced masks (row blk0 + k in lane k), and the bits
+        // of row r2 not handed out yet
+        uint32_t p02 = 0, cnt2 = 0, lim2 = 0, blk0 = 0;
+        uint64_t blk = 0;
+        auto load_block = [&]() {
+            blk0 = r2;
+            const uint32_t rr = r2 + (uint32_t)lane;
+            blk = 0;
+            if (rr < (uint32_t)RPT) {
+                const uint32_t r0 = rr * WAVE;
+                const uint64_t left = r0 < lim2 ? lanes_below(lim2 - r0) : 0ull;
+                blk = mask[(size_t)t2 * RPT + rr] & ~left;
+            }
+        };
+        ip_tile_range<K>(sg, t2, p02, cnt2);
+        lim2 = ip_left_limit(mid, p02, cnt2);
+        load_block();
+        uint64_t m2 = lane_get64(blk, 0);
+        bool bad = k2 >= popc(m2);
+        if (!bad) m2 &= ~lanes_below(select_bit(m2, k2));  // drop the bits of earlier ranks
+        for (uint32_t rb = rbeg; rb < rend && !bad; rb += SB) {
+            uint32_t pl[SB], pr[SB];
+            bool me[SB];
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const uint32_t r = rb + (uint32_t)u;
+                me[u] = false;
+                pl[u] = pr[u] = 0;
+                if (r >= rend || bad) continue;
+                const uint64_t mis = lane_get64(own, r - rbeg);
+                const uint32_t c = popc(mis);
+                if (c == 0) continue;
+                const uint32_t j = mask_below(mis);
+                me[u] = (mis >> lane) & 1ull;
+                pl[u] = p0 + r * WAVE + (uint32_t)lane;
+                uint32_t done = 0;
+                while (done < c) {
+                    if (m2 == 0) {  // next row of the segment
+                        if (++r2 == (uint32_t)RPT) {
+                            r2 = 0;
+                            if (++t2 >= tend) {
+                                bad = true;
+                                break;
+                            }
+                            ip_tile_range<K>(sg, t2, p02, cnt2);
+                            lim2 = ip_left_limit(mid, p02, cnt2);
+                            load_block();
+                        } else if (r2 - blk0 >= (uint32_t)WAVE) {
+                            load_block();
+                        }
+                        m2 = lane_get64(blk, r2 - blk0);
+                        continue;
+                    }
+                    const uint32_t a = popc(m2), take = min(a, c - done);
+                    if (me[u] && j >= done && j < done + take) pr[u] = p02 + r2 * WAVE + select_bit(m2, j - done);
+                    m2 = take == a ? 0ull : (m2 & ~lanes_below(select_bit(m2, take)));
+                    done += take;
+                }
+                // the partner is a right-misplaced key of this segment; anything
+                // else would mean inconsistent counts: flag it, move nothing
+                if (me[u] && (bad || pr[u] < mid || pr[u] >= sg.e)) {
+                    atomicOr(&ctl->err, ERR_CURSOR);
+                    me[u] = false;
+                }
+            }
+            RawElem<F> a[SB], b[SB];
+#pragma unroll
+            for (int u = 0; u < SB; ++u)
+                if (me[u]) {
+                    a[u] = raw_get<F>(raw, pl[u]);
+                    b[u] = raw_get<F>(raw, pr[u]);
+                }
+#pragma unroll
+            for (int u = 0; u < SB; ++u)
+                if (me[u]) {
+                    raw_put<F>(raw, pl[u], b[u]);
+                    raw_put<F>(raw, pr[u], a[u]);
+                }
+        }
+        if (bad && lane == 0) atomicOr(&ctl->err, ERR_CURSOR);
+    }
+}
+
+}  // namespace hs

@@ -794,13 +794,15 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
                                                const unsigned long long *cur, Seg<typename KeyOf<F>::type> *cand,
                                                unsigned long long *ncur, LevelCounts *nlev,
                                                Task<typename KeyOf<F>::type> *tasks,
-                                               const typename KeyOf<F>::type *out, uint32_t out_id, uint32_t T,
-                                               uint32_t leaf, int rule, uint32_t cand_cap, uint32_t task_cap,
-                                               uint32_t w, uint32_t nwaves)
+                                               const typename KeyOf<F>::type *out, uint32_t out_id, Raw raw,
+                                               uint32_t T, uint32_t leaf, int rule, uint32_t cand_cap,
+                                               uint32_t task_cap, uint32_t w, uint32_t nwaves)
 {
     using K = typename KeyOf<F>::type;
     const int lane = lane_id();
-    SrcReader<F> rd{out, Raw{nullptr, nullptr}, false};
+    // the level's output: an internal buffer, or the caller's arrays (levels
+    // partitioned in place)
+    SrcReader<F> rd{out, raw, out_id == SRC_RAW};
     unsigned long long lkeys = 0, fkeys = 0, ekeys = 0;
     uint32_t emax = 0;
 
@@ -895,12 +897,12 @@ __global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, int par, const Seg<t
                                                   const unsigned long long *cur,
                                                   Seg<typename KeyOf<F>::type> *cand, unsigned long long *ncur,
                                                   Task<typename KeyOf<F>::type> *tasks,
-                                                  const typename KeyOf<F>::type *out, uint32_t out_id,
+                                                  const typename KeyOf<F>::type *out, uint32_t out_id, Raw raw,
                                                   uint32_t T, uint32_t leaf, int rule, uint32_t cand_cap,
                                                   uint32_t task_cap)
 {
     const uint32_t nseg = level_segs(ctl->lev[par].segs_tiles, cand_cap);
-    finalize_level<F>(ctl, nseg, segs, cur, cand, ncur, &ctl->lev[1 - par], tasks, out, out_id, T, leaf, rule,
+    finalize_level<F>(ctl, nseg, segs, cur, cand, ncur, &ctl->lev[1 - par], tasks, out, out_id, raw, T, leaf, rule,
                       cand_cap, task_cap, (blockIdx.x * blockDim.x + threadIdx.x) / WAVE,
                       gridDim.x * (blockDim.x / WAVE));
 }
@@ -951,7 +953,7 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_levels
                                              gridDim.x, stage, wsum, sbase);
         if (!grid_barrier(ctl, gen, spin_limit)) break;
         const int lrule = level > guard ? PIVOT_SAMPLE : rule;
-        finalize_level<F>(ctl, nseg, segs, cur, next, ncur, &ctl->lev[1 - p], tasks, dst, (uint32_t)(1 - p), T,
+        finalize_level<F>(ctl, nseg, segs, cur, next, ncur, &ctl->lev[1 - p], tasks, dst, (uint32_t)(1 - p), raw, T,
                           leaf, lrule, cand_cap, task_cap, wave_id, nwaves);
         if (!grid_barrier(ctl, gen, spin_limit)) break;
     }

@@ -14,6 +14,7 @@
 #include <tuple>
 #include <vector>
 
+#include "hs_inplace.hpp"
 #include "hs_kernels.hpp"
 #include "hs_learned.hpp"
 #include "hs_local.hpp"
@@ -144,6 +145,8 @@ LearnParams learn_params(const hs_opts *o, int64_t n, int op)
 
 struct Layout {
     size_t buf0 = 0, buf1 = 0, segA = 0, segB = 0, curA = 0, curB = 0, tasks = 0, ctl = 0, total = 0;
+    // levels partitioned in place: key bits, row prefixes, tile totals and prefixes
+    size_t ipmask = 0, iprow = 0, iptot = 0, ipgp = 0;
     uint32_t cand_cap = 0, task_cap = 0;
     // learned front end (LearnParams::on)
     size_t smp_k = 0, smp_v = 0, sub = 0, z = 0, y = 0, par = 0, mom = 0, vel = 0, part = 0, lossb = 0,
@@ -152,7 +155,8 @@ struct Layout {
 };
 
 template <typename K>
-Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParams &P = LearnParams())
+Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParams &P = LearnParams(),
+                   bool inplace = false)
 {
     Layout L;
     size_t off = 0;
@@ -165,14 +169,26 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParam
     if (op == HS_OP_PARTITION_I32) {
         L.cand_cap = 1;
         L.task_cap = 1;
-        L.buf1 = take((size_t)n * 4);
+        if (!inplace) L.buf1 = take((size_t)n * 4);
     } else {
         L.cand_cap = (uint32_t)(n / ((int64_t)T + 1) + 2);
         L.task_cap = (uint32_t)((op == HS_OP_SORT_SEGMENTED_I32 ? nseg : 1) + 2ll * LMAX * L.cand_cap + 4);
         // the multiway pass routes up to NB_MAX buckets, fills in chunks
         if (P.on) L.task_cap += (uint32_t)(NB_MAX + n / FILL_CHUNK + 2);
-        L.buf1 = take((size_t)n * sk);
-        if (op == HS_OP_SORT_KV_I32 || op == HS_OP_SORT_KV_F64) L.buf0 = take((size_t)n * sk);
+        if (!inplace) {
+            L.buf1 = take((size_t)n * sk);
+            if (op == HS_OP_SORT_KV_I32 || op == HS_OP_SORT_KV_F64) L.buf0 = take((size_t)n * sk);
+        }
+    }
+    if (inplace) {
+        // a level's tiles: the full tiles of its keys plus at most two partial
+        // tiles per segment
+        const size_t tiles = (size_t)n / PartCfg<K>::TILE + 2ull * L.cand_cap + 2;
+        const size_t rows = tiles * (size_t)ip_rows<K>();
+        L.ipmask = take(rows * 8);
+        L.iprow = take(rows * 4);
+        L.iptot = take(tiles * 8);
+        L.ipgp = take(tiles * 8);
     }
     L.segA = take((size_t)L.cand_cap * sizeof(Seg<K>));
     L.segB = take((size_t)L.cand_cap * sizeof(Seg<K>));
@@ -250,6 +266,15 @@ int check_learn(const hs_opts *o)
             o->learn_flags == (HS_LEARN_FORCE_MODEL | HS_LEARN_FORCE_SAMPLE))
             return fail(HS_EINVAL, "learn_flags = 0x%x is invalid", o->learn_flags);
     }
+    if (o->inplace != 0 && o->inplace != 1) return fail(HS_EINVAL, "inplace = %d is not 0 or 1", o->inplace);
+    if (o->inplace) {
+        // the in-place levels run with the host-driven loop; the multiway pass
+        // and the persistent driver write to a second buffer
+        if (o->method == HS_METHOD_LEARNED) return fail(HS_EINVAL, "inplace is not offered with the learned method");
+        if (o->driver == HS_DRIVER_PERSISTENT)
+            return fail(HS_EINVAL, "inplace levels run with the host-driven loop, not the persistent driver");
+        if (o->autotune) return fail(HS_EINVAL, "inplace is not offered with the autotuner");
+    }
     return HS_OK;
 }
 
@@ -264,26 +289,27 @@ int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
 {
     int rc = check_learn(o);
     if (rc) return rc;
+    const bool ip = o && o->inplace;
     switch (op) {
     case HS_OP_SORT_I32:
     case HS_OP_SORT_U32:
     case HS_OP_SORT_SEGMENTED_I32:
-        *L = make_layout<uint32_t>(op, n, nseg, local_limit<uint32_t>(o), learn_params(o, n, op));
+        *L = make_layout<uint32_t>(op, n, nseg, local_limit<uint32_t>(o), learn_params(o, n, op), ip);
         return HS_OK;
     case HS_OP_PARTITION_I32:
-        *L = make_layout<uint32_t>(op, n, nseg, 0);
+        *L = make_layout<uint32_t>(op, n, nseg, 0, LearnParams(), ip);
         return HS_OK;
     case HS_OP_SORT_F64:
     case HS_OP_SORT_I64:
     case HS_OP_SORT_KV_I32:
-        *L = make_layout<uint64_t>(op, n, nseg, local_limit<uint64_t>(o), learn_params(o, n, op));
+        *L = make_layout<uint64_t>(op, n, nseg, local_limit<uint64_t>(o), learn_params(o, n, op), ip);
         return HS_OK;
     case HS_OP_SORT_KV_F64:
         // the learned front end (one 64-bit splitter word per bucket) is
         // built for words of up to 64 bits
         if (o && o->method == HS_METHOD_LEARNED)
             return fail(HS_EINVAL, "learned splitters are not offered for float64 key/value pairs");
-        *L = make_layout<u128>(op, n, nseg, local_limit<u128>(o));
+        *L = make_layout<u128>(op, n, nseg, local_limit<u128>(o), LearnParams(), ip);
         return HS_OK;
     default:
         return fail(HS_EINVAL, "unknown op %d", op);
@@ -357,9 +383,11 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     const int local_rule = (o && o->pivot_rule > 0) ? o->pivot_rule : PIVOT_NINTHER;
     const bool learned = P.on && (uint64_t)n > T;
 
+    // in-place levels keep every key in the caller's arrays: no buffers
+    const bool inplace = o && o->inplace;
     K *buf[2];
-    buf[0] = has_vals<F>() ? (K *)(ws + L.buf0) : (K *)raw.keys;
-    buf[1] = (K *)(ws + L.buf1);
+    buf[0] = inplace ? nullptr : has_vals<F>() ? (K *)(ws + L.buf0) : (K *)raw.keys;
+    buf[1] = inplace ? nullptr : (K *)(ws + L.buf1);
     Seg<K> *segs[2] = {(Seg<K> *)(ws + L.segA), (Seg<K> *)(ws + L.segB)};
     unsigned long long *curs[2] = {(unsigned long long *)(ws + L.curA), (unsigned long long *)(ws + L.curB)};
     Task<K> *tasks = (Task<K> *)(ws + L.tasks);
@@ -370,9 +398,9 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     HS_HIP(hipStreamIsCapturing(stream, &cap));
     const bool capturing = cap != hipStreamCaptureStatusNone;
     const int drv = o ? o->driver : HS_DRIVER_AUTO;
-    if (capturing && drv == HS_DRIVER_HOST)
+    if (capturing && (drv == HS_DRIVER_HOST || inplace))
         return fail(HS_EINVAL, "the host-driven level loop cannot be captured into a graph");
-    const bool host_driver = drv == HS_DRIVER_HOST || (drv == HS_DRIVER_AUTO && !capturing);
+    const bool host_driver = drv == HS_DRIVER_HOST || inplace || (drv == HS_DRIVER_AUTO && !capturing);
 
     // a whole array that one wave's network holds (1024 keys, unless the
     // caller lowered the on-chip limit or the network bound to force the
@@ -492,10 +520,27 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     if (occ_p < 1) occ_p = 1;
     const int part_grid = d->ncu * occ_p;
     const int fin_grid = d->ncu * 2;
+    uint64_t *ipmask = (uint64_t *)(ws + L.ipmask);
+    uint32_t *iprow = (uint32_t *)(ws + L.iprow), *iptot = (uint32_t *)(ws + L.iptot), *ipgp = (uint32_t *)(ws + L.ipgp);
     auto launch_level = [&](int level) -> int {
         const int p = level & 1;
         const int lrule = level > guard ? PIVOT_SAMPLE : rule;
         if (st) HS_HIP(hipEventRecord(d->ev[2 * level], stream));
+        if (inplace) {
+            // classify, rows, scan, swap: the level's keys stay where they are
+            HS_LAUNCH((k_ip_classify<F>), part_grid, PartCfg<K>::NT, stream, ctl, p, 1, segs[p], curs[p], raw, ipmask,
+                      L.cand_cap);
+            HS_LAUNCH((k_ip_rows<F>), d->ncu * 8, IP_NT, stream, ctl, p, segs[p], curs[p], ipmask, iprow, iptot,
+                      L.cand_cap);
+            HS_LAUNCH((k_ip_scan<F>), 1, 1024, stream, ctl, p, segs[p], iptot, ipgp, L.cand_cap);
+            HS_LAUNCH((k_ip_swap<F>), d->ncu * 8, IP_NT, stream, ctl, p, segs[p], curs[p], ipmask, iprow, iptot, ipgp,
+                      raw, L.cand_cap);
+            if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
+            HS_LAUNCH(k_finalize<F>, fin_grid, 256, stream, ctl, p, segs[p], curs[p], segs[1 - p], curs[1 - p], tasks,
+                      (const K *)nullptr, SRC_RAW, raw, T, LEAF, lrule, L.cand_cap, L.task_cap);
+            ++launches;
+            return HS_OK;
+        }
         if (level == 0)
             HS_LAUNCH((k_partition<F, true, false>), part_grid, PartCfg<K>::NT, stream, ctl, p, 1, segs[p], curs[p],
                       (const K *)nullptr, raw, buf[1 - p], Raw{}, L.cand_cap);
@@ -504,7 +549,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
                       (const K *)buf[p], raw, buf[1 - p], Raw{}, L.cand_cap);
         if (st) HS_HIP(hipEventRecord(d->ev[2 * level + 1], stream));
         HS_LAUNCH(k_finalize<F>, fin_grid, 256, stream, ctl, p, segs[p], curs[p], segs[1 - p], curs[1 - p], tasks,
-                  buf[1 - p], (uint32_t)(1 - p), T, LEAF, lrule, L.cand_cap, L.task_cap);
+                  buf[1 - p], (uint32_t)(1 - p), raw, T, LEAF, lrule, L.cand_cap, L.task_cap);
         ++launches;
         return HS_OK;
     };
@@ -1053,23 +1098,37 @@ int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_l
     if ((rc = bind_workspace(d, opts, L, &ws))) return rc;
     const bool shared_ws = !(opts && opts->workspace);
     if (shared_ws) HS_HIP(hipStreamWaitEvent(s, d->last, 0));
-    int32_t *copy = (int32_t *)(ws + L.buf1);
     Seg<uint32_t> *segs = (Seg<uint32_t> *)(ws + L.segA);
     unsigned long long *cur = (unsigned long long *)(ws + L.curA);
     Task<uint32_t> *tasks = (Task<uint32_t> *)(ws + L.tasks);
     Ctl *ctl = (Ctl *)(ws + L.ctl);
-    // The pass is out of place: stage the input in the workspace, then
-    // partition it back into the caller's array.
-    HS_HIP(hipMemcpyAsync(copy, keys, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
-    HS_LAUNCH(k_zero_words, zero_grid(sizeof(Ctl)), 256, s, (uint32_t *)ctl, (uint32_t)(sizeof(Ctl) / 4));
     const uint32_t upiv = (uint32_t)pivot ^ 0x80000000u;
-    HS_LAUNCH(k_init_single<FMT_I32>, 1, 64, s, ctl, segs, cur, tasks, Raw{copy, nullptr}, (uint32_t)n, 0u, 0u,
-              L.task_cap, PIVOT_MEDIAN3, 1, upiv);
     const uint32_t ntiles = seg_tiles<uint32_t>(0, (uint32_t)n);
     const uint32_t maxg = (uint32_t)d->ncu * 8;
     const int g = (int)(ntiles < maxg ? ntiles : maxg);
-    HS_LAUNCH((k_partition<FMT_I32, true, true>), g, PartCfg<uint32_t>::NT, s, ctl, 0, 0, segs, cur,
-              (const uint32_t *)nullptr, Raw{copy, nullptr}, (uint32_t *)nullptr, Raw{keys, nullptr}, L.cand_cap);
+    HS_LAUNCH(k_zero_words, zero_grid(sizeof(Ctl)), 256, s, (uint32_t *)ctl, (uint32_t)(sizeof(Ctl) / 4));
+    if (opts && opts->inplace) {
+        // in place: classify, count the misplaced keys, scan, swap
+        const Raw raw{keys, nullptr};
+        HS_LAUNCH(k_init_single<FMT_I32>, 1, 64, s, ctl, segs, cur, tasks, raw, (uint32_t)n, 0u, 0u, L.task_cap,
+                  PIVOT_MEDIAN3, 1, upiv);
+        uint64_t *ipmask = (uint64_t *)(ws + L.ipmask);
+        uint32_t *iprow = (uint32_t *)(ws + L.iprow), *iptot = (uint32_t *)(ws + L.iptot);
+        uint32_t *ipgp = (uint32_t *)(ws + L.ipgp);
+        HS_LAUNCH((k_ip_classify<FMT_I32>), g, PartCfg<uint32_t>::NT, s, ctl, 0, 0, segs, cur, raw, ipmask, L.cand_cap);
+        HS_LAUNCH((k_ip_rows<FMT_I32>), g, IP_NT, s, ctl, 0, segs, cur, ipmask, iprow, iptot, L.cand_cap);
+        HS_LAUNCH((k_ip_scan<FMT_I32>), 1, 1024, s, ctl, 0, segs, iptot, ipgp, L.cand_cap);
+        HS_LAUNCH((k_ip_swap<FMT_I32>), g, IP_NT, s, ctl, 0, segs, cur, ipmask, iprow, iptot, ipgp, raw, L.cand_cap);
+    } else {
+        // out of place: stage the input in the workspace, then partition it
+        // back into the caller's array
+        int32_t *copy = (int32_t *)(ws + L.buf1);
+        HS_HIP(hipMemcpyAsync(copy, keys, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+        HS_LAUNCH(k_init_single<FMT_I32>, 1, 64, s, ctl, segs, cur, tasks, Raw{copy, nullptr}, (uint32_t)n, 0u, 0u,
+                  L.task_cap, PIVOT_MEDIAN3, 1, upiv);
+        HS_LAUNCH((k_partition<FMT_I32, true, true>), g, PartCfg<uint32_t>::NT, s, ctl, 0, 0, segs, cur,
+                  (const uint32_t *)nullptr, Raw{copy, nullptr}, (uint32_t *)nullptr, Raw{keys, nullptr}, L.cand_cap);
+    }
     HS_LAUNCH(k_write_count, 1, 64, s, cur, d_count_le);
     if (shared_ws) HS_HIP(hipEventRecord(d->last, s));
     return HS_OK;
@@ -1249,6 +1308,7 @@ int hs_autotune(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_o
     int rc = check_sort_args(op, keys, vals, n, d_offsets, nseg);
     if (rc) return rc;
     if ((rc = check_learn(base))) return rc;
+    if (base && base->inplace) return fail(HS_EINVAL, "inplace is not offered with the autotuner");
     if (n < 2 || (op == HS_OP_SORT_SEGMENTED_I32 && nseg == 0)) {
         *best = base ? *base : hs_opts{};
         best->autotune = 0;
@@ -1272,6 +1332,7 @@ int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *
     int rc = check_sort_args(op, keys, vals, n, d_offsets, nseg);
     if (rc) return rc;
     if ((rc = check_learn(opts))) return rc;
+    if (opts && opts->inplace) return fail(HS_EINVAL, "in-place levels cannot be captured into a graph");
     if (opts && opts->driver == HS_DRIVER_HOST)
         return fail(HS_EINVAL, "a plan runs the persistent level driver; HS_DRIVER_HOST cannot be captured");
     if (opts && opts->workspace) return fail(HS_EINVAL, "a plan owns its workspace; pass none");
