@@ -102,7 +102,8 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
     return pos;
 }
 
-// Pass 1: classify.  Workgroups take tiles in a grid-stride loop; lane `tid`
+// Pass 1: classify.  Workgroups take tiles in a grid-stride loop, the next
+// tile's loads in flight while the current one is classified; lane `tid`
 // reads keys j*NT + tid of the tile (consecutive lanes, consecutive
 // addresses), so wave w's j-th ballot is row j*NT/64 + w of the tile.  One
 // 64-bit atomic per tile adds (low count, high count) to the segment's cursor
@@ -121,17 +122,29 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_ip_cla
     uint32_t nseg = 0;
     const uint32_t ntiles = ip_level_tiles<K>(ctl, par, segs, cap, nseg);
     const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const uint32_t s = ip_find_seg<K>(segs, nseg, t);
-        const Seg<K> sg = segs[s];
-        uint32_t p0, cnt;
-        ip_tile_range<K>(sg, t, p0, cnt);
+    // the next tile's keys are loaded while the current one is classified
+    auto fetch = [&](uint32_t tt, uint32_t &s, Seg<K> &sg, uint32_t &p0, uint32_t &cnt, K (&x)[ITEMS]) {
+        s = ip_find_seg<K>(segs, nseg, tt);
+        sg = segs[s];
+        ip_tile_range<K>(sg, tt, p0, cnt);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) x[j] = raw_load<F>(raw, p0 + min((uint32_t)(j * NT + tid), cnt - 1));
+    };
+    uint32_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    uint32_t s, p0, cnt;
+    Seg<K> sg;
+    K x[ITEMS];
+    fetch(t, s, sg, p0, cnt, x);
+    for (; t < ntiles; t += gridDim.x) {
+        uint32_t sn = 0, p0n = 0, cntn = 0;
+        Seg<K> sgn = sg;
+        K xn[ITEMS];
+        const bool more = t + gridDim.x < ntiles;
+        if (more) fetch(t + gridDim.x, sn, sgn, p0n, cntn, xn);
         const bool strict = (sg.flags & SEG_STRICT) != 0;
         const bool none = strict && sg.piv == K(0);
         const K lim = strict ? sg.piv - K(1) : sg.piv;
-        K x[ITEMS];
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) x[j] = raw_load<F>(raw, p0 + min((uint32_t)(j * NT + tid), cnt - 1));
         uint32_t le = 0;
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
@@ -150,6 +163,14 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_ip_cla
             atomicAdd(&cur[(size_t)s * CUR_STRIDE], (unsigned long long)tot | ((unsigned long long)(cnt - tot) << 32));
         }
         __syncthreads();
+        if (more) {
+            s = sn;
+            sg = sgn;
+            p0 = p0n;
+            cnt = cntn;
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) x[j] = xn[j];
+        }
     }
 }
 
@@ -246,6 +267,24 @@ __global__ __launch_bounds__(1024) void k_ip_scan(const Ctl *ctl, int par, const
     }
 }
 
+// Largest i in [lo, hi) with key(i) <= g, for a non-decreasing key with
+// key(lo) <= g (lo, hi, g wave-uniform): each step probes 64 evenly spaced
+// points at once, one per lane, and keeps the interval after the last probe
+// that is still <= g, so 2^18 candidates take three dependent loads.
+template <typename Fn>
+__device__ __forceinline__ uint32_t wave_search(uint32_t lo, uint32_t hi, uint32_t g, const Fn &key, int lane)
+{
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + WAVE - 1) / WAVE;
+        const uint32_t i = lo + (uint32_t)lane * step;
+        const uint64_t ok = ballot(i < hi && key(i) <= g);  // a prefix of the lanes, lane 0 included
+        const uint32_t last = (uint32_t)(WAVE - 1 - __builtin_clzll(ok));
+        lo += last * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
 // Load and store halves of an exchange (keys, and values for the key/value
 // formats), so that the loads of several exchanges can be in flight at once.
 template <int F> struct RawElem {
@@ -296,6 +335,8 @@ __global__ __launch_bounds__(IP_NT) void k_ip_swap(Ctl *ctl, int par, const Seg<
     constexpr uint32_t CH = (RPT + NW - 1) / NW;  // rows per wave
     constexpr int SB = 8;                         // rows whose exchanges are issued together
     static_assert(CH <= (uint32_t)WAVE && CH % SB == 0, "a wave's rows fit one mask per lane");
+    // per wave: position of the r-th set bit of the current right row in slot r
+    __shared__ uint32_t s_pos[NW][WAVE];
     uint32_t nseg = 0;
     const uint32_t ntiles = ip_level_tiles<K>(ctl, par, segs, cap, nseg);
     const int tid = threadIdx.x, lane = lane_id();
@@ -325,17 +366,10 @@ __global__ __launch_bounds__(IP_NT) void k_ip_swap(Ctl *ctl, int par, const Seg<
         }
         // global right index of the run's first partner
         const uint32_t g = gp[2 * (size_t)t0 + 1] + (gp[2 * (size_t)t] - gp[2 * (size_t)t0]) + pre_beg;
-        uint32_t t2 = t0, hi_t = tend;
-        while (hi_t - t2 > 1) {
-            const uint32_t m = (t2 + hi_t) >> 1;
-            if (gp[2 * (size_t)m + 1] <= g) t2 = m; else hi_t = m;
-        }
+        uint32_t t2 = wave_search(t0, tend, g, [&](uint32_t i) { return gp[2 * (size_t)i + 1]; }, lane);
         const uint32_t q = g - gp[2 * (size_t)t2 + 1];
-        uint32_t r2 = 0, hi_r = RPT;
-        while (hi_r - r2 > 1) {
-            const uint32_t m = (r2 + hi_r) >> 1;
-            if ((rowpre[(size_t)t2 * RPT + m] >> 16) <= q) r2 = m; else hi_r = m;
-        }
+        uint32_t r2 = wave_search(0u, (uint32_t)RPT, q, [&](uint32_t i) { return rowpre[(size_t)t2 * RPT + i] >> 16; },
+                                  lane);
         const uint32_t k2 = q - (rowpre[(size_t)t2 * RPT + r2] >> 16);
         // the walk: tile t2 (keys p02.., lim2 of them before mid), row r2, a
         // block of right-misplaced masks (row blk0 + k in lane k), and the bits
@@ -392,8 +426,16 @@ __global__ __launch_bounds__(IP_NT) void k_ip_swap(Ctl *ctl, int par, const Seg<
                         continue;
                     }
                     const uint32_t a = popc(m2), take = min(a, c - done);
-                    if (me[u] && j >= done && j < done + take) pr[u] = p02 + r2 * WAVE + select_bit(m2, j - done);
-                    m2 = take == a ? 0ull : (m2 & ~lanes_below(select_bit(m2, take)));
+                    // the row's set bits, in rank order, to this wave's slots (LDS
+                    // operations of one wave take effect in issue order)
+                    if ((m2 >> lane) & 1ull) s_pos[w][mask_below(m2)] = (uint32_t)lane;
+                    if (me[u] && j >= done && j < done + take) pr[u] = p02 + r2 * WAVE + s_pos[w][j - done];
+                    if (take == a) {
+                        m2 = 0ull;
+                    } else {
+                        const uint32_t cut = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pos[w][take]);
+                        m2 &= ~lanes_below(cut);
+                    }
                     done += take;
                 }
                 // the partner is a right-misplaced key of this segment; anything
