@@ -186,8 +186,9 @@ HS_API int hs_sort_kv_i32(int32_t *keys, int32_t *vals, int64_t n, const hs_opts
  * values' bits as unsigned 32-bit integers, so the output is unique.  A pair
  * travels as one 128-bit order word (the key's totalOrder word above the
  * value), on the same kernels as the other formats with half as many keys
- * per on-chip task.  keys and vals must not overlap (DEVICE pointers).  The
- * learned method is not offered for this format (HS_EINVAL). */
+ * per on-chip task.  keys and vals must not overlap (DEVICE pointers).  With
+ * the learned method the model sees the keys (its splitters are the
+ * smallest words of their keys). */
 HS_API int hs_sort_kv_f64(double *keys, int32_t *vals, int64_t n, const hs_opts *opts, hs_stats *stats,
                           void *stream);
 

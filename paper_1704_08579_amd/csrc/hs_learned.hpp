@@ -98,6 +98,13 @@ template <> struct LearnKey<FMT_KV> {
     static __device__ __forceinline__ K word(S s) { return (K)s << 32; }  // smallest word with that key
     static __device__ __forceinline__ double value(S s) { return (double)(int32_t)dec_i32(s); }
 };
+template <> struct LearnKey<FMT_KV_F64> {
+    using K = u128;
+    using S = uint64_t;
+    static __device__ __forceinline__ S search(K k) { return (S)(k >> 64); }
+    static __device__ __forceinline__ K word(S s) { return (K)s << 64; }  // smallest word with that key
+    static __device__ __forceinline__ double value(S s) { return LearnKey<FMT_F64>::value(s); }
+};
 
 // Scalars of the learned front end, in device memory.
 struct LearnCtl {
@@ -117,12 +124,9 @@ __global__ void k_ls_sample(Raw raw, uint32_t n, uint64_t seed, uint32_t m, Raw 
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     const uint32_t i = (uint32_t)__umul64hi(splitmix64_at(seed, k), (uint64_t)n);
-    if constexpr (raw_key_bytes<F>() == 8) {
-        ((uint64_t *)out.keys)[k] = ((const uint64_t *)raw.keys)[i];
-    } else {
-        ((uint32_t *)out.keys)[k] = ((const uint32_t *)raw.keys)[i];
-        if constexpr (F == FMT_KV) out.vals[k] = raw.vals[i];
-    }
+    if constexpr (raw_key_bytes<F>() == 8) ((uint64_t *)out.keys)[k] = ((const uint64_t *)raw.keys)[i];
+    else ((uint32_t *)out.keys)[k] = ((const uint32_t *)raw.keys)[i];
+    if constexpr (has_vals<F>()) out.vals[k] = raw.vals[i];
 }
 
 // Held-out sample as order words.
@@ -566,6 +570,18 @@ __device__ __forceinline__ void mw_load(Raw raw, const typename KeyOf<F>::type *
             const uint32_t off = (uint32_t)(j * MW_NT + threadIdx.x) * 4u;
             x[j] = enc_kv(rsrc_load32(rk, off), rsrc_load32(rv, off));
         }
+    } else if constexpr (SRC_IS_RAW && F == FMT_KV_F64) {
+        const auto rk = tile_rsrc((const uint64_t *)raw.keys + p0, cnt * 8u);
+        const auto rv = tile_rsrc((const uint32_t *)raw.vals + p0, cnt * 4u);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t i = (uint32_t)(j * MW_NT + threadIdx.x);
+            x[j] = enc_kv_f64(rsrc_load64(rk, i * 8u), rsrc_load32(rv, i * 4u));
+        }
+    } else if constexpr (sizeof(K) == 16) {
+        const auto r = tile_rsrc(src + p0, cnt * 16u);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) x[j] = rsrc_load128(r, (uint32_t)(j * MW_NT + threadIdx.x) * 16u);
     } else if constexpr (sizeof(K) == 4) {
         const auto r = tile_rsrc((SRC_IS_RAW ? (const K *)raw.keys : src) + p0, cnt * 4u);
 #pragma unroll
@@ -679,7 +695,7 @@ __global__ __launch_bounds__(MW_NT) void k_mw_scatter(Raw raw, const typename Ke
 {
     using K = typename KeyOf<F>::type;
     constexpr int ITEMS = MW_TILE / MW_NT;
-    constexpr int STORES = ITEMS * ((DST_IS_RAW && F == FMT_KV) ? 2 : 1);
+    constexpr int STORES = ITEMS * ((DST_IS_RAW && has_vals<F>()) ? 2 : 1);
     __shared__ K sd[NBUCKET];
     __shared__ uint32_t cnt[NB_MAX], tbase[NB_MAX], run[NB_MAX];
     __shared__ K stage[MW_TILE];

@@ -200,9 +200,9 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParam
         // The training sample is sorted by a nested plain sort with its own
         // sub-workspace.
         const Layout S = make_layout<K>(op, P.m, 1, T);
-        const size_t rk = op == HS_OP_SORT_F64 || op == HS_OP_SORT_I64 ? 8 : 4;
+        const size_t rk = op == HS_OP_SORT_F64 || op == HS_OP_SORT_I64 || op == HS_OP_SORT_KV_F64 ? 8 : 4;
         L.smp_k = take((size_t)P.m * rk);
-        if (op == HS_OP_SORT_KV_I32) L.smp_v = take((size_t)P.m * 4);
+        if (op == HS_OP_SORT_KV_I32 || op == HS_OP_SORT_KV_F64) L.smp_v = take((size_t)P.m * 4);
         L.sub = take(S.total);
         L.sub_bytes = S.total;
         L.z = take((size_t)P.m * 4);
@@ -305,11 +305,7 @@ int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
         *L = make_layout<uint64_t>(op, n, nseg, local_limit<uint64_t>(o), learn_params(o, n, op), ip);
         return HS_OK;
     case HS_OP_SORT_KV_F64:
-        // the learned front end (one 64-bit splitter word per bucket) is
-        // built for words of up to 64 bits
-        if (o && o->method == HS_METHOD_LEARNED)
-            return fail(HS_EINVAL, "learned splitters are not offered for float64 key/value pairs");
-        *L = make_layout<u128>(op, n, nseg, local_limit<u128>(o), LearnParams(), ip);
+        *L = make_layout<u128>(op, n, nseg, local_limit<u128>(o), learn_params(o, n, op), ip);
         return HS_OK;
     default:
         return fail(HS_EINVAL, "unknown op %d", op);
@@ -447,12 +443,10 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     int level0 = 0;
     LearnCtl *lctl = nullptr;
     if (learned) {
-        if constexpr (F == FMT_KV_F64) {
-            return fail(HS_EINVAL, "learned splitters are not offered for float64 key/value pairs");
-        } else {
+        {
             // ---- learned splitters and the multiway pass
             lctl = (LearnCtl *)(ws + L.lctl);
-            Raw smp{ws + L.smp_k, F == FMT_KV ? (int32_t *)(ws + L.smp_v) : nullptr};
+            Raw smp{ws + L.smp_k, has_vals<F>() ? (int32_t *)(ws + L.smp_v) : nullptr};
             float *z = (float *)(ws + L.z), *y = (float *)(ws + L.y);
             float *par = (float *)(ws + L.par), *mom = (float *)(ws + L.mom), *vel = (float *)(ws + L.vel);
             float *part = (float *)(ws + L.part), *lossb = (float *)(ws + L.lossb);
@@ -1053,8 +1047,6 @@ int hs_sort_kv_f64(double *keys, int32_t *vals, int64_t n, const hs_opts *opts, 
     if (n > 0 && (!keys || !vals)) return fail(HS_EINVAL, "keys or vals is NULL");
     if (n > 0 && overlap(keys, (size_t)n * 8, vals, (size_t)n * 4))
         return fail(HS_EINVAL, "keys and vals overlap");
-    if (opts && opts->method == HS_METHOD_LEARNED)
-        return fail(HS_EINVAL, "learned splitters are not offered for float64 key/value pairs");
     if (stats) std::memset(stats, 0, sizeof *stats);
     if (n <= 1) return HS_OK;
     DevState *d;

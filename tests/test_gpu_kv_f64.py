@@ -131,3 +131,20 @@ def test_kv_f64_full_size_properties(hs):
     assert np.array_equal(keys.view(np.uint64)[idx], kb)
     same = ok[1:] == ok[:-1]
     assert np.all(idx[1:][same] > idx[:-1][same])
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2], ids=["judged", "model", "sample"])
+def test_kv_f64_learned(hs, oracle_mod, flags):
+    """The learned front end (sample, model, 256-way pass) on float64 keys with
+    values: bit-exact with the oracle whichever splitters drive the pass."""
+    n = (1 << 21) + 5
+    keys = np.exp(2.0 * workloads.rng(50 + flags).standard_normal(n))  # lognormal(0, 2)
+    keys[:: 97] = keys[7]  # a heavy key: an equality bucket
+    vals = workloads.rng(60 + flags).integers(-(2 ** 31), 2 ** 31, n, dtype=np.int64).astype(np.int32)
+    k, v = _gpu(keys), _gpu(vals)
+    st = hs.sort_kv_(k, v, opts=hs.learned_opts(steps=40, seed=3, flags=flags), stats=True)
+    _check(oracle_mod, keys, vals, k.cpu().numpy(), v.cpu().numpy())
+    assert st["splitters"] > 0
+    if flags == 2:
+        assert st["fallback_used"] == 1
+
