@@ -195,7 +195,11 @@ HS_API int hs_sort_kv_f64(double *keys, int32_t *vals, int64_t n, const hs_opts 
 /* Partition n int32 keys in place around `pivot` (Algorithm 3's contract):
  * afterwards keys[0,k) <= pivot < keys[k,n), with k = #{x <= pivot} written
  * to the DEVICE int64 *d_count_le.  The order inside each side is
- * unspecified. */
+ * unspecified.  By default the keys are staged in the workspace and
+ * partitioned back (one read and one write of each key after the copy);
+ * with opts->inplace set they never leave the array (classify, count the
+ * misplaced keys, exchange them pairwise), and the workspace holds one bit
+ * per key and 4 bytes per 64 keys instead of a copy. */
 HS_API int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_le,
                      const hs_opts *opts, void *stream);
 
