@@ -443,58 +443,56 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     int level0 = 0;
     LearnCtl *lctl = nullptr;
     if (learned) {
-        {
-            // ---- learned splitters and the multiway pass
-            lctl = (LearnCtl *)(ws + L.lctl);
-            Raw smp{ws + L.smp_k, has_vals<F>() ? (int32_t *)(ws + L.smp_v) : nullptr};
-            float *z = (float *)(ws + L.z), *y = (float *)(ws + L.y);
-            float *par = (float *)(ws + L.par), *mom = (float *)(ws + L.mom), *vel = (float *)(ws + L.vel);
-            float *part = (float *)(ws + L.part), *lossb = (float *)(ws + L.lossb);
-            K *msplit = (K *)(ws + L.msplit), *ssplit = (K *)(ws + L.ssplit), *chosen = (K *)(ws + L.chosen);
-            K *hold = (K *)(ws + L.hold);
-            uint32_t *hist = (uint32_t *)(ws + L.hist), *btot = (uint32_t *)(ws + L.btot);
-            uint32_t *bstart = (uint32_t *)(ws + L.bstart);
-            if (st) HS_HIP(hipEventRecord(lev[2], stream));
-            HS_LAUNCH(k_zero_words, 1, 256, stream, (uint32_t *)lctl, (uint32_t)(sizeof(LearnCtl) / 4));
-            // sample draws: the training sample from splitmix64(seed), the
-            // held-out sample from splitmix64(seed + 1), the weights from
-            // splitmix64(seed + 2)
-            HS_LAUNCH(k_ls_sample<F>, (P.m + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed, P.m, smp);
-            HS_LAUNCH(k_ls_holdout<F>, (P.h + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed + 1, P.h, hold);
-            const Layout S = make_layout<K>(op_of<F>(), P.m, 1, T);
-            int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
-            if (rc) return rc;
-            HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl);
-            const uint32_t gblk = (P.m + 255) / 256;
-            if (P.mode != JUDGE_SAMPLE) {
-                HS_LAUNCH(k_mlp_init, (MLP_NP + 255) / 256, 256, stream, par, mom, vel, P.seed + 2);
-                for (int t = 1; t <= P.steps; ++t) {
-                    const bool last = t == P.steps;
-                    HS_LAUNCH(k_mlp_grad, gblk, 256, stream, par, z, y, P.m, part, lossb);
-                    HS_LAUNCH(k_mlp_update, MLP_UPDATE_GRID, 256, stream, par, mom, vel, part, gblk, t, P.lr,
-                              (float *)nullptr, lossb, last ? lossb + gblk : (float *)nullptr, P.m);
-                }
-                HS_LAUNCH(k_ls_invert<F>, (NSPLIT * WAVE + 255) / 256, 256, stream, par, lctl, msplit);
+        // ---- learned splitters and the multiway pass
+        lctl = (LearnCtl *)(ws + L.lctl);
+        Raw smp{ws + L.smp_k, has_vals<F>() ? (int32_t *)(ws + L.smp_v) : nullptr};
+        float *z = (float *)(ws + L.z), *y = (float *)(ws + L.y);
+        float *par = (float *)(ws + L.par), *mom = (float *)(ws + L.mom), *vel = (float *)(ws + L.vel);
+        float *part = (float *)(ws + L.part), *lossb = (float *)(ws + L.lossb);
+        K *msplit = (K *)(ws + L.msplit), *ssplit = (K *)(ws + L.ssplit), *chosen = (K *)(ws + L.chosen);
+        K *hold = (K *)(ws + L.hold);
+        uint32_t *hist = (uint32_t *)(ws + L.hist), *btot = (uint32_t *)(ws + L.btot);
+        uint32_t *bstart = (uint32_t *)(ws + L.bstart);
+        if (st) HS_HIP(hipEventRecord(lev[2], stream));
+        HS_LAUNCH(k_zero_words, 1, 256, stream, (uint32_t *)lctl, (uint32_t)(sizeof(LearnCtl) / 4));
+        // sample draws: the training sample from splitmix64(seed), the
+        // held-out sample from splitmix64(seed + 1), the weights from
+        // splitmix64(seed + 2)
+        HS_LAUNCH(k_ls_sample<F>, (P.m + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed, P.m, smp);
+        HS_LAUNCH(k_ls_holdout<F>, (P.h + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed + 1, P.h, hold);
+        const Layout S = make_layout<K>(op_of<F>(), P.m, 1, T);
+        int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
+        if (rc) return rc;
+        HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl);
+        const uint32_t gblk = (P.m + 255) / 256;
+        if (P.mode != JUDGE_SAMPLE) {
+            HS_LAUNCH(k_mlp_init, (MLP_NP + 255) / 256, 256, stream, par, mom, vel, P.seed + 2);
+            for (int t = 1; t <= P.steps; ++t) {
+                const bool last = t == P.steps;
+                HS_LAUNCH(k_mlp_grad, gblk, 256, stream, par, z, y, P.m, part, lossb);
+                HS_LAUNCH(k_mlp_update, MLP_UPDATE_GRID, 256, stream, par, mom, vel, part, gblk, t, P.lr,
+                          (float *)nullptr, lossb, last ? lossb + gblk : (float *)nullptr, P.m);
             }
-            HS_LAUNCH(k_ls_judge<K>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode);
-            if (st) HS_HIP(hipEventRecord(lev[3], stream));
-            uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
-            const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 8 - 1) / ((uint64_t)d->ncu * 8));
-            if (chunk < cmin) chunk = cmin;
-            chunk = (chunk + MW_TILE - 1) / MW_TILE * MW_TILE;
-            const uint32_t G = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
-            HS_LAUNCH((k_mw_hist<F, true>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk, chosen, lctl,
-                      hist);
-            HS_LAUNCH(k_mw_scan_cols, NB_MAX, 1024, stream, hist, G, lctl, btot);
-            HS_LAUNCH(k_mw_scan_starts, 1, 1024, stream, btot, lctl, bstart);
-            HS_LAUNCH((k_mw_scatter<F, true, false>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk,
-                      chosen, lctl, hist, bstart, buf[1], Raw{});
-            // the buckets are in buffer 1, where level 1 reads: they form level 1's list
-            HS_LAUNCH(k_mw_route<F>, (NB_MAX + 255) / 256, 256, stream, ctl, lctl, bstart, chosen, buf[1], SRC_BUF1,
-                      segs[1], curs[1], tasks, T, LEAF, rule, L.cand_cap, L.task_cap);
-            if (st) HS_HIP(hipEventRecord(lev[4], stream));
-            level0 = 1;
+            HS_LAUNCH(k_ls_invert<F>, (NSPLIT * WAVE + 255) / 256, 256, stream, par, lctl, msplit);
         }
+        HS_LAUNCH(k_ls_judge<K>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode);
+        if (st) HS_HIP(hipEventRecord(lev[3], stream));
+        uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
+        const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 8 - 1) / ((uint64_t)d->ncu * 8));
+        if (chunk < cmin) chunk = cmin;
+        chunk = (chunk + MW_TILE - 1) / MW_TILE * MW_TILE;
+        const uint32_t G = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
+        HS_LAUNCH((k_mw_hist<F, true>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk, chosen, lctl,
+                  hist);
+        HS_LAUNCH(k_mw_scan_cols, NB_MAX, 1024, stream, hist, G, lctl, btot);
+        HS_LAUNCH(k_mw_scan_starts, 1, 1024, stream, btot, lctl, bstart);
+        HS_LAUNCH((k_mw_scatter<F, true, false>), G, MW_NT, stream, raw, (const K *)nullptr, (uint32_t)n, chunk,
+                  chosen, lctl, hist, bstart, buf[1], Raw{});
+        // the buckets are in buffer 1, where level 1 reads: they form level 1's list
+        HS_LAUNCH(k_mw_route<F>, (NB_MAX + 255) / 256, 256, stream, ctl, lctl, bstart, chosen, buf[1], SRC_BUF1,
+                  segs[1], curs[1], tasks, T, LEAF, rule, L.cand_cap, L.task_cap);
+        if (st) HS_HIP(hipEventRecord(lev[4], stream));
+        level0 = 1;
     } else if (d_off) {
         const uint32_t g = (uint32_t)((nseg + 255) / 256);  // one wave per 64 segments
         HS_LAUNCH(k_init_segmented<F>, g, 256, stream, ctl, segs[0], curs[0], tasks, raw, d_off, (uint32_t)nseg,
