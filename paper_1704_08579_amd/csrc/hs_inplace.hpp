@@ -20,9 +20,9 @@
 //   swap      the k-th left-misplaced key of a segment trades places with its
 //             k-th right-misplaced key.  Both counts are equal (the low side
 //             holds exactly `mid - b` slots), ranks come from the prefixes,
-//             and a wave finds the partner of its first key by binary search
-//             over the segment's tiles and the tile's rows, then walks on
-//             through the rows' masks.  Every position is read and written by
+//             and a wave finds the partner of its first key by a 64-way
+//             search over the segment's tiles and the tile's rows, then walks
+//             on through the rows' masks.  Every position is read and written by
 //             exactly one lane, and the passes that located it only read the
 //             masks, so no key can be seen half-moved.
 //
@@ -316,7 +316,7 @@ __device__ __forceinline__ uint64_t lane_get64(uint64_t v, uint32_t src)
 // Pass 4: swap.  Workgroups take tiles with left-misplaced keys; wave w
 // takes a contiguous run of the tile's rows before mid.  The partners of a
 // run's left-misplaced keys are consecutive right-misplaced keys of the
-// segment, so the wave finds the first one by binary search (over the
+// segment, so the wave finds the first one by a 64-way search (over the
 // segment's tiles, then the tile's rows: wave-uniform) and then walks
 // forward through the right-misplaced bits row by row, handing partners to
 // its lanes in rank order.  The masks of the run's rows and of the next 64
