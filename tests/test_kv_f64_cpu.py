@@ -124,3 +124,15 @@ def test_kv_f64_binding_dtypes(hs):
         hs.sort_kv_(torch.zeros(4, dtype=torch.float64), torch.zeros(4, dtype=torch.int32))
     with pytest.raises(TypeError):
         hs.sort_kv_(torch.zeros(4, dtype=torch.float32), torch.zeros(4, dtype=torch.int32))
+
+
+def test_kv_dup_f64_recipe():
+    """The float64 key/value inputs: the requested number of distinct keys,
+    values = positions, and the special keys kept bit for bit (NaN payloads
+    and signed zeros included)."""
+    keys, vals = workloads.kv_dup_f64(200000, seed=9, ndistinct=1000)
+    assert np.unique(keys.view(np.uint64)).size == 1000
+    assert np.array_equal(vals, np.arange(200000, dtype=np.int32))
+    keys, _ = workloads.kv_dup_f64(50000, seed=9, ndistinct=40, specials=True)
+    specials = set(int(b) for b in workloads.f64_specials().view(np.uint64))
+    assert specials <= set(int(b) for b in np.unique(keys.view(np.uint64)))
