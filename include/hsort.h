@@ -303,7 +303,10 @@ HS_API int hs_autotune(int op, void *keys, int32_t *vals, int64_t n, const int64
                        const hs_opts *base, hs_opts *best, hs_tune_report *report, void *stream);
 
 /* Bytes of workspace that operation `op` needs for n keys (and nseg
- * segments) with the given options. */
+ * segments) with the given options.  With HSORT_GUARD=1 in the environment
+ * (a debugging aid), every region of the workspace is followed by 256 guard
+ * bytes that a sort fills before it runs and checks after it (a sort that
+ * finds them changed returns HS_EINTERNAL); the size then includes them. */
 HS_API int hs_workspace_size(int op, int64_t n, int64_t nseg, const hs_opts *opts, size_t *bytes);
 
 /* Thread-local description of the last non-OK return ("" if none). */

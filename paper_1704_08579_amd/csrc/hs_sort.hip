@@ -7,6 +7,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -143,8 +144,40 @@ LearnParams learn_params(const hs_opts *o, int64_t n, int op)
     return P;
 }
 
+// Guard words (HSORT_GUARD=1 in the environment): 256 bytes after every
+// region of the workspace, filled with a pattern before a sort and checked
+// after it, so a kernel writing past the end of a buffer, list or counter
+// block fails the call instead of going unnoticed.
+constexpr int MAX_GUARDS = 40;
+constexpr uint32_t GUARD_WORD = 0x5AFE6A2Du;
+bool guards_on()
+{
+    const char *e = std::getenv("HSORT_GUARD");
+    return e && e[0] && !(e[0] == '0' && e[1] == 0);
+}
+struct Guards {
+    uint32_t n;
+    uint64_t off[MAX_GUARDS];
+};
+
+// One workgroup of 64 threads per 256-byte guard: fill it with the pattern,
+// and count the words that no longer hold it.
+__global__ void k_guard_fill(char *ws, Guards g, uint32_t word)
+{
+    if (blockIdx.x < g.n) ((uint32_t *)(ws + g.off[blockIdx.x]))[threadIdx.x] = word;
+}
+__global__ void k_guard_check(const char *ws, Guards g, uint32_t word, unsigned long long *bad)
+{
+    if (blockIdx.x >= g.n) return;
+    const bool diff = ((const uint32_t *)(ws + g.off[blockIdx.x]))[threadIdx.x] != word;
+    const uint64_t m = ballot(diff);
+    if (lane_id() == 0 && m) atomicAdd(bad, (unsigned long long)popc(m));
+}
+
 struct Layout {
     size_t buf0 = 0, buf1 = 0, segA = 0, segB = 0, curA = 0, curB = 0, tasks = 0, ctl = 0, total = 0;
+    Guards guards{};
+    size_t guard_count = 0;  // one counter word for the check
     // levels partitioned in place: key bits, row prefixes, tile totals and prefixes
     size_t ipmask = 0, iprow = 0, iptot = 0, ipgp = 0;
     uint32_t cand_cap = 0, task_cap = 0;
@@ -160,9 +193,14 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParam
 {
     Layout L;
     size_t off = 0;
+    const bool guards = guards_on();
     auto take = [&](size_t bytes) {
         size_t at = off;
         off = align_up(off + bytes, 256);
+        if (guards && L.guards.n < (uint32_t)MAX_GUARDS) {
+            L.guards.off[L.guards.n++] = off;
+            off += 256;
+        }
         return at;
     };
     const size_t sk = sizeof(K);
@@ -222,6 +260,7 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParam
         L.btot = take(NB_MAX * 4);
         L.bstart = take((NB_MAX + 1) * 4);
     }
+    if (guards) L.guard_count = take(8);
     L.total = off;
     return L;
 }
@@ -667,7 +706,20 @@ int run_sort_tuned(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_
     if (rc) return rc;
     const bool shared_ws = !(o && o->workspace);
     if (shared_ws) HS_HIP(hipStreamWaitEvent(stream, d->last, 0));
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HS_HIP(hipStreamIsCapturing(stream, &cs));
+    const bool guard = L.guards.n > 0 && cs == hipStreamCaptureStatusNone;
+    if (guard) HS_LAUNCH(k_guard_fill, L.guards.n, 64, stream, ws, L.guards, GUARD_WORD);
     rc = sort_body<F>(d, ws, L, raw, n, d_off, nseg, o, P, st, stream, graph_levels);
+    if (rc == HS_OK && guard) {
+        unsigned long long *cnt = (unsigned long long *)(ws + L.guard_count);
+        HS_LAUNCH(k_zero_words, 1, 64, stream, (uint32_t *)cnt, 2u);
+        HS_LAUNCH(k_guard_check, L.guards.n, 64, stream, ws, L.guards, GUARD_WORD, cnt);
+        unsigned long long bad = 0;
+        HS_HIP(hipMemcpyAsync(&bad, cnt, 8, hipMemcpyDeviceToHost, stream));
+        HS_HIP(hipStreamSynchronize(stream));
+        if (bad) rc = fail(HS_EINTERNAL, "%llu workspace guard words were overwritten", bad);
+    }
     if (shared_ws) HS_HIP(hipEventRecord(d->last, stream));
     return rc;
 }

@@ -59,3 +59,14 @@ def test_inplace_refusals(hs):
     best, rep = hs.Opts(), hs.TuneReport()
     assert L.hs_autotune(hs.OP_SORT_I32, p(0x1000), None, 1 << 20, None, 0, ctypes.byref(_ip(hs)),
                          ctypes.byref(best), ctypes.byref(rep), None) == -1
+
+
+def test_guard_words_enlarge_the_workspace(hs, monkeypatch):
+    """HSORT_GUARD=1 adds 256 guard bytes after every workspace region."""
+    n = 1 << 20
+    plain = hs.workspace_size(hs.OP_SORT_F64, n)
+    monkeypatch.setenv("HSORT_GUARD", "1")
+    guarded = hs.workspace_size(hs.OP_SORT_F64, n)
+    assert guarded >= plain + 8 * 256
+    monkeypatch.setenv("HSORT_GUARD", "0")
+    assert hs.workspace_size(hs.OP_SORT_F64, n) == plain
