@@ -37,7 +37,10 @@
  *   - Errors are reported by return code only (hs_status); nothing is
  *     thrown across the ABI.  Argument errors are detected before any
  *     launch.  hs_last_error() returns a thread-local message describing
- *     the last non-OK return of the calling thread.
+ *     the last non-OK return of the calling thread.  With HSORT_LOG=1 in the
+ *     environment every sort call prints one line to stderr (operation,
+ *     size, options, result and, when statistics are asked for, levels and
+ *     times).
  *   - Limits: 0 <= n < 2^31 elements per call (positions fit 32 bits inside
  *     the kernels; byte offsets are 64-bit).
  */

@@ -873,8 +873,40 @@ int autotune_impl(DevState *d, int op, Raw raw, int64_t n, const int64_t *d_off,
 }
 
 template <int F>
+int run_sort_logged(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
+                    hs_stats *st, hipStream_t stream);
+
+// HSORT_LOG=1 in the environment: one line per sort call on stderr (the
+// operation, size, method, level mode and result; with statistics asked for,
+// the levels, keys partitioned and times).
+int log_level()
+{
+    const char *e = std::getenv("HSORT_LOG");
+    return e && e[0] ? std::atoi(e) : 0;
+}
+
+template <int F>
 int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
              hs_stats *st, hipStream_t stream)
+{
+    const int rc = run_sort_logged<F>(d, raw, n, d_off, nseg, o, st, stream);
+    if (log_level() > 0) {
+        const int op = d_off ? HS_OP_SORT_SEGMENTED_I32 : op_of<F>();
+        std::fprintf(stderr, "[hsort] op=%d n=%lld nseg=%lld method=%d inplace=%d autotune=%d rc=%d", op,
+                     (long long)n, (long long)nseg, o ? o->method : 0, o ? o->inplace : 0, o ? o->autotune : 0, rc);
+        if (rc) std::fprintf(stderr, " error=\"%s\"", g_err.c_str());
+        if (st && rc == HS_OK)
+            std::fprintf(stderr, " levels=%d keys_partitioned=%lld tasks=%lld partition_ms=%.3f local_ms=%.3f",
+                         (int)st->passes, (long long)st->keys_partitioned, (long long)st->tasks,
+                         (double)st->partition_ms, (double)st->local_ms);
+        std::fprintf(stderr, "\n");
+    }
+    return rc;
+}
+
+template <int F>
+int run_sort_logged(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
+                    hs_stats *st, hipStream_t stream)
 {
     if (o && o->autotune) {
         int rc = check_learn(o);

@@ -1,7 +1,7 @@
-"""Workspace guard words (HSORT_GUARD=1): every sort path runs with 256
+"""Diagnostics.  Workspace guard words (HSORT_GUARD=1): every sort path runs with 256
 guard bytes after each workspace region, filled with a pattern before the
 call and checked after it; none may be overwritten, and the outputs stay
-bit-exact with the oracle."""
+bit-exact with the oracle.  HSORT_LOG=1: one line per call on stderr."""
 import numpy as np
 import pytest
 
@@ -64,3 +64,16 @@ def test_guards_in_place_learned_segmented(hs, oracle_mod, guarded):
     t = _gpu(keys)
     hs.sort_segmented_(t, _gpu(off))
     assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
+
+
+def test_log_line(hs, monkeypatch, capfd):
+    """HSORT_LOG=1: one line per sort call on stderr, with the statistics
+    when they were asked for."""
+    monkeypatch.setenv("HSORT_LOG", "1")
+    t = _gpu(workloads.uniform_i32(100003, seed=5))
+    hs.sort_(t, stats=True)
+    torch.cuda.synchronize()
+    err = capfd.readouterr().err
+    lines = [l for l in err.splitlines() if l.startswith("[hsort]")]
+    assert len(lines) == 1
+    assert "op=0 n=100003" in lines[0] and "rc=0" in lines[0] and "levels=" in lines[0]
