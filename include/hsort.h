@@ -177,6 +177,15 @@ HS_API int hs_sort_i64(int64_t *keys, int64_t n, const hs_opts *opts, hs_stats *
 HS_API int hs_argsort_i32(const int32_t *keys, int32_t *keys_out, int32_t *idx_out, int64_t n,
                           const hs_opts *opts, hs_stats *stats, void *stream);
 
+/* Stable argsort of n float64 keys by IEEE 754-2008 totalOrder: keys_out
+ * receives the keys in order (bits unchanged) and idx_out[i] the position in
+ * `keys` of keys_out[i]; keys with equal bits keep their input order.  It is
+ * the float64 key/value sort with the indices 0..n-1 as values.  keys_out
+ * may be `keys` or a separate array; idx_out must not overlap either (DEVICE
+ * pointers). */
+HS_API int hs_argsort_f64(const double *keys, double *keys_out, int32_t *idx_out, int64_t n,
+                          const hs_opts *opts, hs_stats *stats, void *stream);
+
 /* Sort n (key, value) pairs held as two separate arrays (Sec. III-D) by key,
  * in place; every value moves with its key.  keys and vals must not
  * overlap. */

@@ -48,6 +48,7 @@ def lib() -> ctypes.CDLL:
             ("oracle_sort_f64", [_P, _I64, _I64], _I64),
             ("oracle_sort_kv_i32", [_P, _P, _I64, _I64], _I64),
             ("oracle_sort_kv_f64", [_P, _P, _I64, _I64], _I64),
+            ("oracle_argsort_f64", [_P, _P, _I64, _I64], _I64),
             ("oracle_sort_u32", [_P, _I64, _I64], _I64),
             ("oracle_sort_i64", [_P, _I64, _I64], _I64),
             ("oracle_argsort_i32", [_P, _P, _I64, _I64], _I64),
@@ -152,6 +153,15 @@ def sort_kv_f64(keys: np.ndarray, vals: np.ndarray, leaf: int = LEAF):
     if lib().oracle_sort_kv_f64(_ptr(k), _ptr(v), k.size, leaf) < 0:
         raise MemoryError("oracle_sort_kv_f64")
     return k.view(np.float64), v
+
+
+def argsort_f64(keys: np.ndarray, leaf: int = LEAF):
+    """Stable argsort by totalOrder: (sorted keys, int32 positions of them in `keys`)."""
+    k = np.ascontiguousarray(keys, dtype=np.float64).copy().view(np.uint64)
+    idx = np.empty(k.size, dtype=np.int32)
+    if lib().oracle_argsort_f64(_ptr(k), _ptr(idx), k.size, leaf) < 0:
+        raise MemoryError("oracle_argsort_f64")
+    return k.view(np.float64), idx
 
 
 def sort_segmented_i32(keys: np.ndarray, offsets: np.ndarray, leaf: int = LEAF) -> np.ndarray:

@@ -315,6 +315,32 @@ int64_t oracle_sort_kv_f64(uint64_t *bits, int32_t *vals, int64_t n, int64_t lea
     return d;
 }
 
+/* Stable argsort of float64 keys by definition: the pairs (key, position)
+ * in lexicographic order.  The key/value sort above (Sec. III-D) orders the
+ * keys; every run of equal keys (equal bits) then has its positions put in
+ * ascending order (insertion sort over the run). */
+int64_t oracle_argsort_f64(uint64_t *bits, int32_t *idx, int64_t n, int64_t leaf)
+{
+    for (int64_t i = 0; i < n; ++i) idx[i] = (int32_t)i;
+    int64_t d = oracle_sort_kv_f64(bits, idx, n, leaf);
+    if (d < 0) return d;
+    for (int64_t lo = 0; lo < n;) {
+        int64_t hi = lo + 1;
+        while (hi < n && bits[hi] == bits[lo]) ++hi;
+        for (int64_t i = lo + 1; i < hi; ++i) {
+            const int32_t v = idx[i];
+            int64_t j = i - 1;
+            while (j >= lo && idx[j] > v) {
+                idx[j + 1] = idx[j];
+                --j;
+            }
+            idx[j + 1] = v;
+        }
+        lo = hi;
+    }
+    return d;
+}
+
 /* Segmented sort: every [off[i], off[i+1]) is sorted on its own. */
 int64_t oracle_sort_segmented_i32(int32_t *keys, const int64_t *off, int64_t nseg,
                                   int64_t leaf)

@@ -82,6 +82,7 @@ _SIGS = {
     "hs_sort_u32": ([_P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_i64": ([_P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_argsort_i32": ([_P, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_argsort_f64": ([_P, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_partition_i32": ([_P, _I64, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
     "hs_sort_segmented_i32": ([_P, _I64, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_workspace_size": ([ctypes.c_int, _I64, _I64, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -169,24 +170,26 @@ def sort_(t, opts: Opts | None = None, stats: bool = False):
 
 
 def argsort(keys, opts: Opts | None = None, stats: bool = False, out=None):
-    """Stable argsort of a 1-D int32 CUDA tensor: returns (sorted keys, int32
-    indices) with keys[idx] == sorted keys and equal keys in input order.
-    `keys` is left as it is unless out=(keys, idx) names it."""
+    """Stable argsort of a 1-D int32 or float64 (totalOrder) CUDA tensor:
+    returns (sorted keys, int32 indices) with keys[idx] == sorted keys and
+    equal keys in input order.  `keys` is left as it is unless
+    out=(keys, idx) names it."""
     torch = _torch()
-    _require(keys, (torch.int32,), "keys")
+    _require(keys, (torch.int32, torch.float64), "keys")
     if out is None:
         ko = torch.empty_like(keys)
-        idx = torch.empty_like(keys)
+        idx = torch.empty(keys.shape, dtype=torch.int32, device=keys.device)
     else:
         ko, idx = out
-        _require(ko, (torch.int32,), "out[0]")
+        _require(ko, (keys.dtype,), "out[0]")
         _require(idx, (torch.int32,), "out[1]")
         if ko.numel() != keys.numel() or idx.numel() != keys.numel():
             raise ValueError("out tensors must have the size of keys")
+    fn = lib().hs_argsort_i32 if keys.dtype == torch.int32 else lib().hs_argsort_f64
     st = Stats() if stats else None
     with torch.cuda.device(keys.device):
-        _check(lib().hs_argsort_i32(keys.data_ptr(), ko.data_ptr(), idx.data_ptr(), keys.numel(), _opts_ptr(opts),
-                                    None if st is None else ctypes.addressof(st), _stream_handle(keys)))
+        _check(fn(keys.data_ptr(), ko.data_ptr(), idx.data_ptr(), keys.numel(), _opts_ptr(opts),
+                  None if st is None else ctypes.addressof(st), _stream_handle(keys)))
     return (ko, idx, st.as_dict()) if st is not None else (ko, idx)
 
 

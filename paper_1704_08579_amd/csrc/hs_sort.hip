@@ -1107,6 +1107,29 @@ int hs_argsort_i32(const int32_t *keys, int32_t *keys_out, int32_t *idx_out, int
     return run_sort<FMT_KV>(d, Raw{keys_out, idx_out}, n, nullptr, 0, opts, stats, s);
 }
 
+int hs_argsort_f64(const double *keys, double *keys_out, int32_t *idx_out, int64_t n, const hs_opts *opts,
+                   hs_stats *stats, void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n > 0 && (!keys || !keys_out || !idx_out)) return fail(HS_EINVAL, "keys, keys_out or idx_out is NULL");
+    if (n > 0 && keys != keys_out && overlap(keys, (size_t)n * 8, keys_out, (size_t)n * 8))
+        return fail(HS_EINVAL, "keys and keys_out overlap without being the same array");
+    if (n > 0 && (overlap(idx_out, (size_t)n * 4, keys_out, (size_t)n * 8) ||
+                  overlap(idx_out, (size_t)n * 4, keys, (size_t)n * 8)))
+        return fail(HS_EINVAL, "idx_out overlaps the keys");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n == 0) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (keys != keys_out) HS_HIP(hipMemcpyAsync(keys_out, keys, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    HS_LAUNCH(k_iota, (unsigned)((n + 255) / 256), 256, s, idx_out, (uint32_t)n);
+    if (n == 1) return HS_OK;
+    // the 128-bit (key, index) word orders equal keys by index: the sort comes out stable
+    return run_sort<FMT_KV_F64>(d, Raw{keys_out, idx_out}, n, nullptr, 0, opts, stats, s);
+}
+
 int hs_sort_kv_i32(int32_t *keys, int32_t *vals, int64_t n, const hs_opts *opts, hs_stats *stats,
                    void *stream)
 {

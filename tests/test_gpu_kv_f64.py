@@ -148,3 +148,26 @@ def test_kv_f64_learned(hs, oracle_mod, flags):
     if flags == 2:
         assert st["fallback_used"] == 1
 
+
+
+@pytest.mark.parametrize("n", [1, 2, 513, 4097, 100003, (1 << 20) + 7])
+def test_argsort_f64(hs, oracle_mod, n):
+    """Stable argsort of float64 keys (specials and heavy duplicates): keys
+    and positions identical to the oracle's, which are unique."""
+    keys, _ = workloads.kv_dup_f64(n, seed=n + 70, ndistinct=max(2, min(n // 8, 5000)), specials=n > 100)
+    ko, idx = hs.argsort(_gpu(keys))
+    ok, oi = oracle_mod.argsort_f64(keys)
+    assert np.array_equal(ko.cpu().numpy().view(np.uint64), ok.view(np.uint64))
+    assert np.array_equal(idx.cpu().numpy(), oi)
+
+
+def test_argsort_f64_in_place(hs, oracle_mod):
+    keys = workloads.f64(300007, "normal", seed=71)
+    keys[::3] = keys[5]
+    t = _gpu(keys)
+    idx = torch.empty(t.shape, dtype=torch.int32, device="cuda")
+    k, i = hs.argsort(t, out=(t, idx))
+    assert k.data_ptr() == t.data_ptr()
+    ok, oi = oracle_mod.argsort_f64(keys)
+    assert np.array_equal(t.cpu().numpy().view(np.uint64), ok.view(np.uint64))
+    assert np.array_equal(idx.cpu().numpy(), oi)

@@ -136,3 +136,41 @@ def test_kv_dup_f64_recipe():
     keys, _ = workloads.kv_dup_f64(50000, seed=9, ndistinct=40, specials=True)
     specials = set(int(b) for b in workloads.f64_specials().view(np.uint64))
     assert specials <= set(int(b) for b in np.unique(keys.view(np.uint64)))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 257, 40000])
+def test_oracle_argsort_f64_against_numpy(oracle_mod, n):
+    """Without NaNs and zeros totalOrder is the numeric order, so numpy's
+    stable argsort decides every position (heavy duplicates: stability
+    matters)."""
+    keys, _ = workloads.kv_dup_f64(n, seed=n + 5, ndistinct=max(2, n // 50))
+    k, idx = oracle_mod.argsort_f64(keys)
+    want = np.argsort(keys, kind="stable").astype(np.int32)
+    assert np.array_equal(idx, want)
+    assert np.array_equal(k.view(np.uint64), keys[want].view(np.uint64))
+
+
+def test_oracle_argsort_f64_brute_force(oracle_mod):
+    """Special keys: insertion sort of (totalOrder rank, position) pairs."""
+    table = [int(r.split()[0], 16) for r in open(os.path.join(ROOT, "tests", "golden",
+                                                             "ieee754_total_order.txt"))
+             if r.strip() and not r.startswith("#")]
+    rank = {b: i for i, b in enumerate(table)}
+    g = workloads.rng(7)
+    for n in (1, 2, 5, 9, 30):
+        bits = np.array([table[i] for i in g.integers(0, len(table), n)], dtype=np.uint64)
+        want = [p for _, p in insertion_sort([(rank[int(b)], p) for p, b in enumerate(bits)])]
+        for leaf in (1, 256):
+            _, idx = oracle_mod.argsort_f64(bits.view(np.float64), leaf=leaf)
+            assert list(idx) == want
+
+
+def test_argsort_f64_abi(hs):
+    L = hs.lib()
+    p = ctypes.c_void_p
+    assert hasattr(L, "hs_argsort_f64")
+    assert L.hs_argsort_f64(None, p(0x1000), p(0x8000), 3, None, None, None) == -1
+    # idx_out inside keys_out (8-byte keys: 3 of them end at 0x1018)
+    assert L.hs_argsort_f64(p(0x4000), p(0x1000), p(0x1010), 3, None, None, None) == -1
+    assert "overlap" in L.hs_last_error().decode()
+    assert L.hs_argsort_f64(None, None, None, 0, None, None, None) == 0
