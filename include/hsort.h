@@ -73,7 +73,7 @@ typedef enum hs_status {
 /* Operation codes for hs_workspace_size(), plans and the autotuner. */
 enum { HS_OP_SORT_I32 = 0, HS_OP_SORT_F64 = 1, HS_OP_SORT_KV_I32 = 2,
        HS_OP_PARTITION_I32 = 3, HS_OP_SORT_SEGMENTED_I32 = 4,
-       HS_OP_SORT_U32 = 5, HS_OP_SORT_I64 = 6, HS_OP_SORT_KV_F64 = 7 };
+       HS_OP_SORT_U32 = 5, HS_OP_SORT_I64 = 6, HS_OP_SORT_KV_F64 = 7, HS_OP_SORT_SEGMENTED_F64 = 8 };
 
 /* Pivot rules (hs_opts.pivot_rule). */
 enum { HS_PIVOT_AUTO = 0,     /* the tuned default */
@@ -222,6 +222,11 @@ HS_API int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_
 HS_API int hs_sort_segmented_i32(int32_t *keys, int64_t n_total, const int64_t *d_offsets,
                           int64_t nseg, const hs_opts *opts, hs_stats *stats, void *stream);
 
+/* The same for float64 segments (IEEE 754-2008 totalOrder, output bits = input
+ * bits permuted within each segment). */
+HS_API int hs_sort_segmented_f64(double *keys, int64_t n_total, const int64_t *d_offsets,
+                                 int64_t nseg, const hs_opts *opts, hs_stats *stats, void *stream);
+
 /* ---- The learned-splitter method (HS_METHOD_LEARNED) -------------------
  *
  * Not in the paper, which partitions around one pivot at a time (Sec. III-B,
@@ -272,7 +277,7 @@ HS_API int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_
 /* ---- Plans: one call captured into a HIP graph ------------------------
  *
  * hs_plan_create records one sort of the given buffers (op HS_OP_SORT_I32,
- * _U32, _I64, _F64, _KV_I32, _KV_F64 or _SORT_SEGMENTED_I32; vals only for key/value, d_offsets
+ * _U32, _I64, _F64, _KV_I32, _KV_F64, _SORT_SEGMENTED_I32 or _SORT_SEGMENTED_F64; vals only for key/value, d_offsets
  * and nseg only for segmented) into a graph: the partition levels run in the
  * persistent driver, every clear is a kernel, and the plan owns its
  * workspace, so replaying it needs no host work beyond hipGraphLaunch.

@@ -53,6 +53,7 @@ def lib() -> ctypes.CDLL:
             ("oracle_sort_i64", [_P, _I64, _I64], _I64),
             ("oracle_argsort_i32", [_P, _P, _I64, _I64], _I64),
             ("oracle_sort_segmented_i32", [_P, _P, _I64, _I64], _I64),
+            ("oracle_sort_segmented_f64", [_P, _P, _I64, _I64], _I64),
             ("oracle_partition_le_i32", [_P, _I64, ctypes.c_int32], _I64),
             ("oracle_simd_partition_i32", [_P, _I64, ctypes.c_int32, ctypes.c_int], _I64),
             ("oracle_qs_appendix_i32", [_P, _I64, _P], None),
@@ -170,6 +171,15 @@ def sort_segmented_i32(keys: np.ndarray, offsets: np.ndarray, leaf: int = LEAF) 
     if lib().oracle_sort_segmented_i32(_ptr(k), _ptr(off), off.size - 1, leaf) < 0:
         raise MemoryError("oracle_sort_segmented_i32")
     return k
+
+
+def sort_segmented_f64(keys: np.ndarray, offsets: np.ndarray, leaf: int = LEAF) -> np.ndarray:
+    """Every [off[i], off[i+1]) of a float64 array sorted on its own (totalOrder)."""
+    a = np.ascontiguousarray(keys, dtype=np.float64).copy().view(np.uint64)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    if lib().oracle_sort_segmented_f64(_ptr(a), _ptr(off), off.size - 1, leaf) < 0:
+        raise MemoryError("oracle_sort_segmented_f64")
+    return a.view(np.float64)
 
 
 def partition_le_i32(keys: np.ndarray, pivot: int):

@@ -354,6 +354,17 @@ int64_t oracle_sort_segmented_i32(int32_t *keys, const int64_t *off, int64_t nse
     return dmax;
 }
 
+int64_t oracle_sort_segmented_f64(uint64_t *bits, const int64_t *off, int64_t nseg, int64_t leaf)
+{
+    int64_t dmax = 0;
+    for (int64_t s = 0; s < nseg; ++s) {
+        int64_t d = oracle_sort_f64(bits + off[s], off[s + 1] - off[s], leaf);
+        if (d < 0) return -1;
+        if (d > dmax) dmax = d;
+    }
+    return dmax;
+}
+
 /* Partition contract of Algorithm 3: afterwards keys[0,k) <= pivot < keys[k,n)
  * and k is returned.  One pass with a read cursor and a write cursor. */
 int64_t oracle_partition_le_i32(int32_t *keys, int64_t n, int32_t pivot)

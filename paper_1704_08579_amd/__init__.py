@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhsort.so
 
 HS_OK = 0
 (OP_SORT_I32, OP_SORT_F64, OP_SORT_KV_I32, OP_PARTITION_I32, OP_SORT_SEGMENTED_I32, OP_SORT_U32, OP_SORT_I64,
- OP_SORT_KV_F64) = range(8)
+ OP_SORT_KV_F64, OP_SORT_SEGMENTED_F64) = range(9)
 PIVOT_AUTO, PIVOT_MEDIAN3, PIVOT_NINTHER, PIVOT_SAMPLE = range(4)
 
 _STATUS = {0: "HS_OK", -1: "HS_EINVAL", -2: "HS_ENOMEM", -3: "HS_EHIP", -4: "HS_EWORKSPACE",
@@ -85,6 +85,7 @@ _SIGS = {
     "hs_argsort_f64": ([_P, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_partition_i32": ([_P, _I64, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
     "hs_sort_segmented_i32": ([_P, _I64, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_sort_segmented_f64": ([_P, _I64, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_workspace_size": ([ctypes.c_int, _I64, _I64, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hs_mlp_forward_f32": ([_P, _P, _I64, _P, _P], ctypes.c_int),
     "hs_mlp_grad_f32": ([_P, _P, _P, _I64, _P, _P], ctypes.c_int),
@@ -226,17 +227,17 @@ def partition_(t, pivot: int, count_out=None, opts: Opts | None = None):
 
 
 def sort_segmented_(t, offsets, opts: Opts | None = None, stats: bool = False):
-    """Sort every segment t[off[i]:off[i+1]] of an int32 tensor in place.
-    `offsets` is an int64 CUDA tensor of nseg+1 entries, off[0] = 0,
+    """Sort every segment t[off[i]:off[i+1]] of an int32 or float64 tensor in
+    place.  `offsets` is an int64 CUDA tensor of nseg+1 entries, off[0] = 0,
     non-decreasing, off[-1] = t.numel()."""
     torch = _torch()
-    _require(t, (torch.int32,), "t")
+    _require(t, (torch.int32, torch.float64), "t")
     _require(offsets, (torch.int64,), "offsets")
+    fn = lib().hs_sort_segmented_i32 if t.dtype == torch.int32 else lib().hs_sort_segmented_f64
     st = Stats() if stats else None
     with torch.cuda.device(t.device):
-        _check(lib().hs_sort_segmented_i32(t.data_ptr(), t.numel(), offsets.data_ptr(), offsets.numel() - 1,
-                                           _opts_ptr(opts), None if st is None else ctypes.addressof(st),
-                                           _stream_handle(t)))
+        _check(fn(t.data_ptr(), t.numel(), offsets.data_ptr(), offsets.numel() - 1, _opts_ptr(opts),
+                  None if st is None else ctypes.addressof(st), _stream_handle(t)))
     return st.as_dict() if st is not None else t
 
 
@@ -331,9 +332,10 @@ def _sort_args(keys, vals=None, offsets=None):
     """(op, keys ptr, vals ptr, n, offsets ptr, nseg) of a sort over tensors."""
     torch = _torch()
     if offsets is not None:
-        _require(keys, (torch.int32,), "keys")
+        _require(keys, (torch.int32, torch.float64), "keys")
         _require(offsets, (torch.int64,), "offsets")
-        return OP_SORT_SEGMENTED_I32, keys.data_ptr(), None, keys.numel(), offsets.data_ptr(), offsets.numel() - 1
+        op = OP_SORT_SEGMENTED_I32 if keys.dtype == torch.int32 else OP_SORT_SEGMENTED_F64
+        return op, keys.data_ptr(), None, keys.numel(), offsets.data_ptr(), offsets.numel() - 1
     if vals is not None:
         _require(keys, (torch.int32, torch.float64), "keys")
         _require(vals, (torch.int32,), "vals")

@@ -129,7 +129,8 @@ constexpr uint32_t MW_GMAX = 2048;  // multiway workgroups at most
 LearnParams learn_params(const hs_opts *o, int64_t n, int op)
 {
     LearnParams P;
-    if (!o || o->method != HS_METHOD_LEARNED || op == HS_OP_SORT_SEGMENTED_I32 || op == HS_OP_PARTITION_I32)
+    if (!o || o->method != HS_METHOD_LEARNED || op == HS_OP_SORT_SEGMENTED_I32 || op == HS_OP_SORT_SEGMENTED_F64 ||
+        op == HS_OP_PARTITION_I32)
         return P;
     P.on = true;
     P.mode = (o->learn_flags & HS_LEARN_FORCE_SAMPLE) ? JUDGE_SAMPLE
@@ -210,7 +211,8 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParam
         if (!inplace) L.buf1 = take((size_t)n * 4);
     } else {
         L.cand_cap = (uint32_t)(n / ((int64_t)T + 1) + 2);
-        L.task_cap = (uint32_t)((op == HS_OP_SORT_SEGMENTED_I32 ? nseg : 1) + 2ll * LMAX * L.cand_cap + 4);
+        const bool seg = op == HS_OP_SORT_SEGMENTED_I32 || op == HS_OP_SORT_SEGMENTED_F64;
+        L.task_cap = (uint32_t)((seg ? nseg : 1) + 2ll * LMAX * L.cand_cap + 4);
         // the multiway pass routes up to NB_MAX buckets, fills in chunks
         if (P.on) L.task_cap += (uint32_t)(NB_MAX + n / FILL_CHUNK + 2);
         if (!inplace) {
@@ -324,6 +326,10 @@ template <int F> constexpr int op_of()
          : F == FMT_U32 ? HS_OP_SORT_U32 : F == FMT_I64 ? HS_OP_SORT_I64 : HS_OP_SORT_KV_F64;
 }
 
+// Batched (segmented) sorts: int32 and float64 keys.
+constexpr bool is_seg(int op) { return op == HS_OP_SORT_SEGMENTED_I32 || op == HS_OP_SORT_SEGMENTED_F64; }
+template <int F> constexpr int seg_op_of() { return F == FMT_F64 ? HS_OP_SORT_SEGMENTED_F64 : HS_OP_SORT_SEGMENTED_I32; }
+
 int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
 {
     int rc = check_learn(o);
@@ -341,6 +347,7 @@ int layout_for(int op, int64_t n, int64_t nseg, const hs_opts *o, Layout *L)
     case HS_OP_SORT_F64:
     case HS_OP_SORT_I64:
     case HS_OP_SORT_KV_I32:
+    case HS_OP_SORT_SEGMENTED_F64:
         *L = make_layout<uint64_t>(op, n, nseg, local_limit<uint64_t>(o), learn_params(o, n, op), ip);
         return HS_OK;
     case HS_OP_SORT_KV_F64:
@@ -694,8 +701,7 @@ template <int F>
 int run_sort_tuned(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg, const hs_opts *o,
                    hs_stats *st, hipStream_t stream, int graph_levels = 0)
 {
-    const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
-                         : op_of<F>();
+    const int op = d_off ? seg_op_of<F>() : op_of<F>();
     Layout L;
     int rc = layout_for(op, n, nseg, o, &L);
     if (rc) return rc;
@@ -891,7 +897,7 @@ int run_sort(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg
 {
     const int rc = run_sort_logged<F>(d, raw, n, d_off, nseg, o, st, stream);
     if (log_level() > 0) {
-        const int op = d_off ? HS_OP_SORT_SEGMENTED_I32 : op_of<F>();
+        const int op = d_off ? seg_op_of<F>() : op_of<F>();
         std::fprintf(stderr, "[hsort] op=%d n=%lld nseg=%lld method=%d inplace=%d autotune=%d rc=%d", op,
                      (long long)n, (long long)nseg, o ? o->method : 0, o ? o->inplace : 0, o ? o->autotune : 0, rc);
         if (rc) std::fprintf(stderr, " error=\"%s\"", g_err.c_str());
@@ -911,8 +917,7 @@ int run_sort_logged(DevState *d, Raw raw, int64_t n, const int64_t *d_off, int64
     if (o && o->autotune) {
         int rc = check_learn(o);
         if (rc) return rc;
-        const int op = d_off ? HS_OP_SORT_SEGMENTED_I32
-                             : op_of<F>();
+        const int op = d_off ? seg_op_of<F>() : op_of<F>();
         hs_opts tuned;
         if ((rc = autotune_impl<F>(d, op, raw, n, d_off, nseg, o, &tuned, nullptr, stream))) return rc;
         tuned.workspace = o->workspace;
@@ -956,6 +961,7 @@ int check_sort_args(int op, const void *keys, const int32_t *vals, int64_t n, co
         break;
     }
     case HS_OP_SORT_SEGMENTED_I32:
+    case HS_OP_SORT_SEGMENTED_F64:
         if (nseg < 0 || nseg >= ((int64_t)1 << 31)) return fail(HS_EINVAL, "nseg = %lld out of range", (long long)nseg);
         if (nseg > 0 && !d_off) return fail(HS_EINVAL, "d_offsets is NULL");
         break;
@@ -974,6 +980,7 @@ template <typename Fn> int with_format(int op, Fn &&fn)
     case HS_OP_SORT_SEGMENTED_I32:
         return fn(std::integral_constant<int, FMT_I32>());
     case HS_OP_SORT_F64:
+    case HS_OP_SORT_SEGMENTED_F64:
         return fn(std::integral_constant<int, FMT_F64>());
     case HS_OP_SORT_KV_I32:
         return fn(std::integral_constant<int, FMT_KV>());
@@ -1157,6 +1164,21 @@ int hs_sort_kv_f64(double *keys, int32_t *vals, int64_t n, const hs_opts *opts, 
     DevState *d;
     if ((rc = get_device(&d))) return rc;
     return run_sort<FMT_KV_F64>(d, Raw{keys, vals}, n, nullptr, 0, opts, stats, (hipStream_t)stream);
+}
+
+int hs_sort_segmented_f64(double *keys, int64_t n_total, const int64_t *d_offsets, int64_t nseg,
+                          const hs_opts *opts, hs_stats *stats, void *stream)
+{
+    int rc = check_n(n_total);
+    if (rc) return rc;
+    if (nseg < 0 || nseg >= ((int64_t)1 << 31)) return fail(HS_EINVAL, "nseg = %lld out of range", (long long)nseg);
+    if (nseg > 0 && !d_offsets) return fail(HS_EINVAL, "d_offsets is NULL");
+    if (n_total > 0 && !keys) return fail(HS_EINVAL, "keys is NULL");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n_total <= 1 || nseg == 0) return HS_OK;
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    return run_sort<FMT_F64>(d, Raw{keys, nullptr}, n_total, d_offsets, nseg, opts, stats, (hipStream_t)stream);
 }
 
 int hs_sort_segmented_i32(int32_t *keys, int64_t n_total, const int64_t *d_offsets, int64_t nseg,
@@ -1406,7 +1428,7 @@ int hs_autotune(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_o
     if (rc) return rc;
     if ((rc = check_learn(base))) return rc;
     if (base && base->inplace) return fail(HS_EINVAL, "inplace is not offered with the autotuner");
-    if (n < 2 || (op == HS_OP_SORT_SEGMENTED_I32 && nseg == 0)) {
+    if (n < 2 || (is_seg(op) && nseg == 0)) {
         *best = base ? *base : hs_opts{};
         best->autotune = 0;
         if (report) *report = hs_tune_report{};
@@ -1414,7 +1436,7 @@ int hs_autotune(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_o
     }
     DevState *d;
     if ((rc = get_device(&d))) return rc;
-    const int64_t *off = op == HS_OP_SORT_SEGMENTED_I32 ? d_offsets : nullptr;
+    const int64_t *off = is_seg(op) ? d_offsets : nullptr;
     return with_format(op, [&](auto fmt) {
         return autotune_impl<decltype(fmt)::value>(d, op, Raw{keys, vals}, n, off, nseg, base, best, report,
                                                    (hipStream_t)stream);
@@ -1437,11 +1459,11 @@ int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *
     if ((rc = get_device(&d))) return rc;
     hs_plan *p = new hs_plan();
     HS_HIP(hipGetDevice(&p->device));
-    if (n < 2 || (op == HS_OP_SORT_SEGMENTED_I32 && nseg == 0)) {  // nothing to sort: an empty plan
+    if (n < 2 || (is_seg(op) && nseg == 0)) {  // nothing to sort: an empty plan
         *plan = p;
         return HS_OK;
     }
-    const int64_t *off = op == HS_OP_SORT_SEGMENTED_I32 ? d_offsets : nullptr;
+    const int64_t *off = is_seg(op) ? d_offsets : nullptr;
     hs_opts o = opts ? *opts : hs_opts{};
     o.driver = HS_DRIVER_PERSISTENT;
     if (o.autotune) {
@@ -1488,7 +1510,7 @@ int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *
         const uint32_t T = w32 ? local_limit<uint32_t>(&o)
                          : op == HS_OP_SORT_KV_F64 ? local_limit<u128>(&o) : local_limit<uint64_t>(&o);
         uint64_t biggest = (uint64_t)n;
-        if (op == HS_OP_SORT_SEGMENTED_I32) {
+        if (is_seg(op)) {
             std::vector<int64_t> h_off((size_t)nseg + 1);
             HS_HIP(hipMemcpy(h_off.data(), d_offsets, h_off.size() * 8, hipMemcpyDeviceToHost));
             biggest = 0;
