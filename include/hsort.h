@@ -180,9 +180,10 @@ HS_API int hs_argsort_i32(const int32_t *keys, int32_t *keys_out, int32_t *idx_o
 /* Stable argsort of n float64 keys by IEEE 754-2008 totalOrder: keys_out
  * receives the keys in order (bits unchanged) and idx_out[i] the position in
  * `keys` of keys_out[i]; keys with equal bits keep their input order.  It is
- * the float64 key/value sort with the indices 0..n-1 as values.  keys_out
- * may be `keys` or a separate array; idx_out must not overlap either (DEVICE
- * pointers). */
+ * the key/value sort of Sec. III-D on float64 keys with the indices 0..n-1
+ * as values (the value breaks ties, so the order is unique).  keys_out may
+ * be `keys` or a separate array; idx_out must not overlap either (DEVICE
+ * pointers; HS_EINVAL otherwise, before any launch). */
 HS_API int hs_argsort_f64(const double *keys, double *keys_out, int32_t *idx_out, int64_t n,
                           const hs_opts *opts, hs_stats *stats, void *stream);
 
@@ -222,8 +223,10 @@ HS_API int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_
 HS_API int hs_sort_segmented_i32(int32_t *keys, int64_t n_total, const int64_t *d_offsets,
                           int64_t nseg, const hs_opts *opts, hs_stats *stats, void *stream);
 
-/* The same for float64 segments (IEEE 754-2008 totalOrder, output bits = input
- * bits permuted within each segment). */
+/* The same for float64 segments: every segment is sorted by Algorithm 4 on
+ * its own (IEEE 754-2008 totalOrder; output bits = input bits permuted within
+ * each segment).  Offsets as for hs_sort_segmented_i32; malformed offsets
+ * found by the kernels return HS_EINTERNAL. */
 HS_API int hs_sort_segmented_f64(double *keys, int64_t n_total, const int64_t *d_offsets,
                                  int64_t nseg, const hs_opts *opts, hs_stats *stats, void *stream);
 
