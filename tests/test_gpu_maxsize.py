@@ -54,3 +54,19 @@ def test_max_size_f64(hs):
     torch.cuda.synchronize()
     assert bool((t[1:] >= t[:-1]).all().item())
     assert _fingerprints(t.view(torch.int64)) == before
+
+
+def test_max_size_i32_in_place(hs):
+    """The in-place partition levels at the limit: their key bits, row and
+    tile prefixes are indexed across 2^31 - 1 keys."""
+    n = (1 << 31) - 1
+    g = torch.Generator(device="cuda")
+    g.manual_seed(33)
+    t = torch.randint(-1000, 1000, (n,), dtype=torch.int32, device="cuda", generator=g)  # heavy duplicates
+    before = _fingerprints(t)
+    o = hs.Opts()
+    o.inplace = 1
+    hs.sort_(t, opts=o)
+    torch.cuda.synchronize()
+    assert bool((t[1:] >= t[:-1]).all().item())
+    assert _fingerprints(t) == before
