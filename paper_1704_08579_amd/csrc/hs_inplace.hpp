@@ -76,6 +76,23 @@ __device__ __forceinline__ uint32_t ip_find_seg(const Seg<K> *segs, uint32_t nse
     return lo;
 }
 
+// Segment record i, read through the constant address space: for a list
+// that no thread writes while the kernel runs, a uniform index gives scalar
+// loads, which the waits on vector loads do not cover (nor the other way
+// round).
+template <typename K> __device__ __forceinline__ Seg<K> seg_const_load(const Seg<K> *segs, uint32_t i)
+{
+    const auto *c = (const __attribute__((address_space(4))) Seg<K> *)segs + i;
+    Seg<K> s;
+    s.b = c->b;
+    s.e = c->e;
+    s.tile0 = c->tile0;
+    s.flags = c->flags;
+    s.piv = c->piv;
+    s.ub = c->ub;
+    return s;
+}
+
 // Local indices [0, lim) of a tile starting at p0 with cnt keys lie before mid.
 __device__ __forceinline__ uint32_t ip_left_limit(uint32_t mid, uint32_t p0, uint32_t cnt)
 {
@@ -102,8 +119,41 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
     return pos;
 }
 
-// Pass 1: classify.  Workgroups take tiles in a grid-stride loop, the next
-// tile's loads in flight while the current one is classified; lane `tid`
+// An element in the caller's format (key, and value for the key/value
+// formats), split into a load and a store so that the loads of several tiles
+// or exchanges can be in flight at once: nothing is computed from the loaded
+// bits until raw_word is called.
+template <int F> struct RawElem {
+    uint64_t k;
+    int32_t v;
+};
+template <int F> __device__ __forceinline__ RawElem<F> raw_get(const Raw &r, uint32_t i)
+{
+    RawElem<F> e;
+    if constexpr (raw_key_bytes<F>() == 8) e.k = ((const uint64_t *)r.keys)[i];
+    else e.k = ((const uint32_t *)r.keys)[i];
+    if constexpr (has_vals<F>()) e.v = r.vals[i];
+    else e.v = 0;
+    return e;
+}
+template <int F> __device__ __forceinline__ void raw_put(const Raw &r, uint32_t i, const RawElem<F> &e)
+{
+    if constexpr (raw_key_bytes<F>() == 8) ((uint64_t *)r.keys)[i] = e.k;
+    else ((uint32_t *)r.keys)[i] = (uint32_t)e.k;
+    if constexpr (has_vals<F>()) r.vals[i] = e.v;
+}
+template <int F> __device__ __forceinline__ typename KeyOf<F>::type raw_word(const RawElem<F> &e)
+{
+    if constexpr (F == FMT_KV) return enc_kv((uint32_t)e.k, (uint32_t)e.v);
+    else if constexpr (F == FMT_KV_F64) return enc_kv_f64(e.k, (uint32_t)e.v);
+    else return enc_word<F>((typename KeyOf<F>::type)e.k);
+}
+
+// Pass 1: classify.  Workgroup wg takes a contiguous run of the level's
+// tiles and walks the segment list forward along it (one search for its
+// first tile, then a look-ahead copy of the next segment, read with scalar
+// loads), with the loads of the next two tiles in flight while the current
+// one is classified; lane `tid`
 // reads keys j*NT + tid of the tile (consecutive lanes, consecutive
 // addresses), so wave w's j-th ballot is row j*NT/64 + w of the tile.  One
 // 64-bit atomic per tile adds (low count, high count) to the segment's cursor
@@ -111,66 +161,111 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
 // With begin_level set, the first thread also does the level's bookkeeping.
 template <int F>
 __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_ip_classify(
-    Ctl *ctl, int par, int begin_level, const Seg<typename KeyOf<F>::type> *segs, unsigned long long *cur, Raw raw,
-    uint64_t *mask, uint32_t cap)
+    Ctl *__restrict__ ctl, int par, int begin_level, const Seg<typename KeyOf<F>::type> *__restrict__ segs,
+    unsigned long long *__restrict__ cur, Raw raw, uint64_t *__restrict__ mask, uint32_t cap)
 {
     using K = typename KeyOf<F>::type;
     constexpr int NT = PartCfg<K>::NT, TILE = PartCfg<K>::TILE, ITEMS = TILE / NT, RPT = ip_rows<K>();
     constexpr int NW = NT / WAVE;
-    __shared__ uint32_t s_le[NW];
+    __shared__ uint32_t s_le[2][NW];
     if (begin_level && blockIdx.x == 0 && threadIdx.x == 0) level_begin(ctl, par);
     uint32_t nseg = 0;
     const uint32_t ntiles = ip_level_tiles<K>(ctl, par, segs, cap, nseg);
+    nseg = (uint32_t)__builtin_amdgcn_readfirstlane((int)nseg);
+    const uint32_t per = (uint32_t)__builtin_amdgcn_readfirstlane((int)((ntiles + gridDim.x - 1) / gridDim.x));
+    uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * per));
+    const uint32_t tend = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(ntiles, t + per));
+    if (t >= tend) return;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
-    // the next tile's keys are loaded while the current one is classified
-    auto fetch = [&](uint32_t tt, uint32_t &s, Seg<K> &sg, uint32_t &p0, uint32_t &cnt, K (&x)[ITEMS]) {
-        s = ip_find_seg<K>(segs, nseg, tt);
-        sg = segs[s];
-        ip_tile_range<K>(sg, tt, p0, cnt);
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) x[j] = raw_load<F>(raw, p0 + min((uint32_t)(j * NT + tid), cnt - 1));
+    // the segment of the first tile, then a forward walk (the level's list
+    // does not change while this kernel runs: scalar loads)
+    uint32_t s_cur = (uint32_t)__builtin_amdgcn_readfirstlane((int)ip_find_seg<K>(segs, nseg, t));
+    Seg<K> sg_cur = seg_const_load<K>(segs, s_cur);
+    Seg<K> sg_after = sg_cur;
+    if (s_cur + 1 < nseg) sg_after = seg_const_load<K>(segs, s_cur + 1);
+    struct Tile {
+        uint32_t s, p0, cnt;
+        Seg<K> sg;
+        RawElem<F> x[ITEMS];
     };
-    uint32_t t = blockIdx.x;
-    if (t >= ntiles) return;
-    uint32_t s, p0, cnt;
-    Seg<K> sg;
-    K x[ITEMS];
-    fetch(t, s, sg, p0, cnt, x);
-    for (; t < ntiles; t += gridDim.x) {
-        uint32_t sn = 0, p0n = 0, cntn = 0;
-        Seg<K> sgn = sg;
-        K xn[ITEMS];
-        const bool more = t + gridDim.x < ntiles;
-        if (more) fetch(t + gridDim.x, sn, sgn, p0n, cntn, xn);
-        const bool strict = (sg.flags & SEG_STRICT) != 0;
-        const bool none = strict && sg.piv == K(0);
-        const K lim = strict ? sg.piv - K(1) : sg.piv;
+    // Tile tt's place and keys.  Past the run's last tile the range is empty:
+    // the buffer loads are still issued (so the number of loads in flight
+    // is the same on every path) and return zeros without touching memory.
+    auto fetch = [&](uint32_t tt, Tile &d) {
+        d.p0 = 0;
+        d.cnt = 0;
+        if (tt < tend) {
+            while (s_cur + 1 < nseg && tt >= sg_after.tile0) {
+                ++s_cur;
+                sg_cur = sg_after;
+                if (s_cur + 1 < nseg) sg_after = seg_const_load<K>(segs, s_cur + 1);
+            }
+            ip_tile_range<K>(sg_cur, tt, d.p0, d.cnt);
+        }
+        d.s = s_cur;
+        d.sg = sg_cur;
+        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d.p0);
+        const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)d.cnt);
+        if constexpr (raw_key_bytes<F>() == 8) {
+            const auto rk = tile_rsrc((const uint64_t *)raw.keys + p0, cnt * 8u);
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) d.x[j].k = rsrc_load64(rk, (uint32_t)(j * NT + tid) * 8u);
+        } else {
+            const auto rk = tile_rsrc((const uint32_t *)raw.keys + p0, cnt * 4u);
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) d.x[j].k = rsrc_load32(rk, (uint32_t)(j * NT + tid) * 4u);
+        }
+        if constexpr (has_vals<F>()) {
+            const auto rv = tile_rsrc((const uint32_t *)raw.vals + p0, cnt * 4u);
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) d.x[j].v = (int32_t)rsrc_load32(rv, (uint32_t)(j * NT + tid) * 4u);
+        } else {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) d.x[j].v = 0;
+        }
+    };
+    auto classify = [&](uint32_t tt, const Tile &c) {
+        const bool strict = (c.sg.flags & SEG_STRICT) != 0;
+        const bool none = strict && c.sg.piv == K(0);
+        const K lim = strict ? c.sg.piv - K(1) : c.sg.piv;
         uint32_t le = 0;
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
-            const bool lo = (uint32_t)(j * NT + tid) < cnt && !none && x[j] <= lim;
+            const bool lo = (uint32_t)(j * NT + tid) < c.cnt && !none && raw_word<F>(c.x[j]) <= lim;
             const uint64_t m = ballot(lo);
-            if (lane == 0) mask[(size_t)t * RPT + (uint32_t)(j * NW + w)] = m;
+            if (lane == 0) mask[(size_t)tt * RPT + (uint32_t)(j * NW + w)] = m;
             le += (uint32_t)lo;
         }
+        // the wave sums go to one of two slots by tile parity: a wave can
+        // only write the slot again after the next barrier, which thread 0
+        // passes once it has read this tile's sums
         const uint32_t ws = wave_sum(le);
-        if (lane == 0) s_le[w] = ws;
+        if (lane == 0) s_le[tt & 1][w] = ws;
         __syncthreads();
         if (tid == 0) {
             uint32_t tot = 0;
 #pragma unroll
-            for (int k = 0; k < NW; ++k) tot += s_le[k];
-            atomicAdd(&cur[(size_t)s * CUR_STRIDE], (unsigned long long)tot | ((unsigned long long)(cnt - tot) << 32));
+            for (int k = 0; k < NW; ++k) tot += s_le[tt & 1][k];
+            atomicAdd(&cur[(size_t)c.s * CUR_STRIDE],
+                      (unsigned long long)tot | ((unsigned long long)(c.cnt - tot) << 32));
         }
-        __syncthreads();
-        if (more) {
-            s = sn;
-            sg = sgn;
-            p0 = p0n;
-            cnt = cntn;
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) x[j] = xn[j];
-        }
+    };
+    // Three tile buffers in turn: tile t is classified while the loads of
+    // t + 1 and t + 2 are in flight.  The loop is unrolled over the buffers
+    // so that no buffer is copied (a copy would wait for its loads).
+    Tile ta, tb, tc;
+    fetch(t, ta);
+    fetch(t + 1, tb);
+    for (;;) {
+        fetch(t + 2, tc);
+        classify(t, ta);
+        if (++t >= tend) break;
+        fetch(t + 2, ta);
+        classify(t, tb);
+        if (++t >= tend) break;
+        fetch(t + 2, tb);
+        classify(t, tc);
+        if (++t >= tend) break;
     }
 }
 
@@ -283,28 +378,6 @@ __device__ __forceinline__ uint32_t wave_search(uint32_t lo, uint32_t hi, uint32
         hi = min(hi, lo + step);
     }
     return lo;
-}
-
-// Load and store halves of an exchange (keys, and values for the key/value
-// formats), so that the loads of several exchanges can be in flight at once.
-template <int F> struct RawElem {
-    uint64_t k;
-    int32_t v;
-};
-template <int F> __device__ __forceinline__ RawElem<F> raw_get(const Raw &r, uint32_t i)
-{
-    RawElem<F> e;
-    if constexpr (raw_key_bytes<F>() == 8) e.k = ((const uint64_t *)r.keys)[i];
-    else e.k = ((const uint32_t *)r.keys)[i];
-    if constexpr (has_vals<F>()) e.v = r.vals[i];
-    else e.v = 0;
-    return e;
-}
-template <int F> __device__ __forceinline__ void raw_put(const Raw &r, uint32_t i, const RawElem<F> &e)
-{
-    if constexpr (raw_key_bytes<F>() == 8) ((uint64_t *)r.keys)[i] = e.k;
-    else ((uint32_t *)r.keys)[i] = (uint32_t)e.k;
-    if constexpr (has_vals<F>()) r.vals[i] = e.v;
 }
 
 // Lane `src` (wave-uniform) of a 64-bit value.
