@@ -76,6 +76,32 @@ __device__ __forceinline__ uint32_t ip_find_seg(const Seg<K> *segs, uint32_t nse
     return lo;
 }
 
+// Largest i in [lo, hi) with key(i) <= g, for a non-decreasing key with
+// key(lo) <= g (lo, hi, g wave-uniform): each step probes 64 evenly spaced
+// points at once, one per lane, and keeps the interval after the last probe
+// that is still <= g, so 2^18 candidates take three dependent loads.
+template <typename Fn>
+__device__ __forceinline__ uint32_t wave_search(uint32_t lo, uint32_t hi, uint32_t g, const Fn &key, int lane)
+{
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + WAVE - 1) / WAVE;
+        const uint32_t i = lo + (uint32_t)lane * step;
+        const uint64_t ok = ballot(i < hi && key(i) <= g);  // a prefix of the lanes, lane 0 included
+        const uint32_t last = (uint32_t)(WAVE - 1 - __builtin_clzll(ok));
+        lo += last * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
+// ip_find_seg for a whole wave at once (t wave-uniform, every lane active):
+// a few rounds of 64 probes instead of log2(nseg) dependent loads.
+template <typename K>
+__device__ __forceinline__ uint32_t ip_find_seg_wave(const Seg<K> *segs, uint32_t nseg, uint32_t t, int lane)
+{
+    return wave_search(0u, nseg, t, [&](uint32_t i) { return segs[i].tile0; }, lane);
+}
+
 // Segment record i, read through the constant address space: for a list
 // that no thread writes while the kernel runs, a uniform index gives scalar
 // loads, which the waits on vector loads do not cover (nor the other way
@@ -286,7 +312,7 @@ __global__ __launch_bounds__(IP_NT) void k_ip_rows(const Ctl *ctl, int par, cons
     const uint32_t ntiles = ip_level_tiles<K>(ctl, par, segs, cap, nseg);
     const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const uint32_t s = ip_find_seg<K>(segs, nseg, t);
+        const uint32_t s = ip_find_seg_wave<K>(segs, nseg, t, lane);
         const Seg<K> sg = segs[s];
         uint32_t p0, cnt;
         ip_tile_range<K>(sg, t, p0, cnt);
@@ -362,24 +388,6 @@ __global__ __launch_bounds__(1024) void k_ip_scan(const Ctl *ctl, int par, const
     }
 }
 
-// Largest i in [lo, hi) with key(i) <= g, for a non-decreasing key with
-// key(lo) <= g (lo, hi, g wave-uniform): each step probes 64 evenly spaced
-// points at once, one per lane, and keeps the interval after the last probe
-// that is still <= g, so 2^18 candidates take three dependent loads.
-template <typename Fn>
-__device__ __forceinline__ uint32_t wave_search(uint32_t lo, uint32_t hi, uint32_t g, const Fn &key, int lane)
-{
-    while (hi - lo > 1) {
-        const uint32_t step = (hi - lo + WAVE - 1) / WAVE;
-        const uint32_t i = lo + (uint32_t)lane * step;
-        const uint64_t ok = ballot(i < hi && key(i) <= g);  // a prefix of the lanes, lane 0 included
-        const uint32_t last = (uint32_t)(WAVE - 1 - __builtin_clzll(ok));
-        lo += last * step;
-        hi = min(hi, lo + step);
-    }
-    return lo;
-}
-
 // Lane `src` (wave-uniform) of a 64-bit value.
 __device__ __forceinline__ uint64_t lane_get64(uint64_t v, uint32_t src)
 {
@@ -416,7 +424,7 @@ __global__ __launch_bounds__(IP_NT) void k_ip_swap(Ctl *ctl, int par, const Seg<
     const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane(tid / WAVE);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         if (tot[2 * (size_t)t] == 0) continue;
-        const uint32_t s = ip_find_seg<K>(segs, nseg, t);
+        const uint32_t s = ip_find_seg_wave<K>(segs, nseg, t, lane);
         const Seg<K> sg = segs[s];
         uint32_t p0, cnt;
         ip_tile_range<K>(sg, t, p0, cnt);
