@@ -414,7 +414,10 @@ __global__ __launch_bounds__(IP_NT) void k_ip_swap(Ctl *ctl, int par, const Seg<
     constexpr int RPT = ip_rows<K>();
     constexpr int NW = IP_NT / WAVE;
     constexpr uint32_t CH = (RPT + NW - 1) / NW;  // rows per wave
-    constexpr int SB = 8;                         // rows whose exchanges are issued together
+    // rows whose exchanges are issued together: 4 keeps the kernel under 64
+    // VGPRs, so 8 waves per SIMD stay resident to hide the walk's latencies
+    // (8 rows in flight per wave, at 5 waves per SIMD, was slower)
+    constexpr int SB = 4;
     static_assert(CH <= (uint32_t)WAVE && CH % SB == 0, "a wave's rows fit one mask per lane");
     // per wave: position of the r-th set bit of the current right row in slot r
     __shared__ uint32_t s_pos[NW][WAVE];
