@@ -105,7 +105,9 @@ __device__ __forceinline__ uint32_t ip_find_seg_wave(const Seg<K> *segs, uint32_
 // Segment record i, read through the constant address space: for a list
 // that no thread writes while the kernel runs, a uniform index gives scalar
 // loads, which the waits on vector loads do not cover (nor the other way
-// round).
+// round).  The list is written by an earlier kernel (the finalize step of
+// the level before); a kernel launch invalidates the scalar cache, so these
+// loads see it.  Not for lists that the same kernel writes.
 template <typename K> __device__ __forceinline__ Seg<K> seg_const_load(const Seg<K> *segs, uint32_t i)
 {
     const auto *c = (const __attribute__((address_space(4))) Seg<K> *)segs + i;
