@@ -51,6 +51,29 @@ def test_inplace_i32_f64(hs, oracle_mod, n, local_T):
     assert np.array_equal(t.cpu().numpy().view(np.uint64), oracle_mod.sort_f64(f).view(np.uint64))
 
 
+# The classify pass gives each workgroup (one per compute unit) a contiguous
+# run of ceil(tiles / workgroups) tiles of a level and has the loads of the
+# two tiles after the current one in flight, past the run's end too.  A
+# first level of one tile more than a multiple of the workgroup count leaves
+# runs of two or three tiles, one workgroup with a single tile and others
+# with none.
+@pytest.mark.parametrize("mult", [1, 2])
+def test_inplace_tile_runs(hs, oracle_mod, mult):
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    n = mult * ncu * 16384 + 1  # int32: 16384-key tiles
+    print(f"inplace tile runs i32 n={n}", flush=True)
+    a = workloads.uniform_i32(n, seed=40 + mult)
+    t = _gpu(a)
+    hs.sort_(t, opts=_ip(hs))
+    assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_i32(a))
+    n = mult * ncu * 8192 + 1  # float64: 8192-key tiles
+    print(f"inplace tile runs f64 n={n}", flush=True)
+    f = workloads.f64(n, "uniform", seed=50 + mult)
+    t = _gpu(f)
+    hs.sort_(t, opts=_ip(hs))
+    assert np.array_equal(t.cpu().numpy().view(np.uint64), oracle_mod.sort_f64(f).view(np.uint64))
+
+
 def test_inplace_duplicates_and_specials(hs, oracle_mod):
     g = workloads.rng(3)
     for n, nd in ((300007, 5), (200003, 1)):
