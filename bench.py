@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the gfx950 hybrid quicksort + bitonic sort.
 
-One step sorts one batch of synthetic keys resident in HBM.  The default
-workload sorts four arrays of 2^27 float64 keys (uniform [0,1), N(0,1),
-already sorted, reverse sorted; IEEE totalOrder), so one step is 2^29 keys.
+One step sorts one array of 2^28 int32 keys (uniform over the full range)
+resident in HBM; `value` is its median throughput over the timed steps.
+Beside it, with the same protocol, the same run measures the other 2^28
+sorts (float64 keys by totalOrder, int32 key/value pairs with 2^16 distinct
+keys), the learned-splitter form next to the plain one on a lognormal(0,2)
+float64 input, the batched form (200,000 int32 arrays, one graph replay),
+the 2^20 int32 case and the four 2^27 float64 distributions.
 
-Printed: ONE JSON line with the sort throughput (Gkeys/s, from HIP events on
-the sort stream around each sort call; the restore copy of the unsorted input
-before each sort is outside the events), the roofline of the dominant kernel
-(the partition pass: algorithmic bytes 2*s per key per level over its event
-time), and the CPU oracle timed on a bounded sample of the same workload.
+Protocol per workload: W untimed warm-up sorts, then K timed sorts, each
+preceded by a device copy that restores the unsorted input (outside the
+events); the time of a sort is the HIP-event time around the call on the
+sort stream; median, min and max are reported.  Statistics (levels, keys
+partitioned, per-launch event times of the partition pass) come from extra
+instrumented sorts after the timed ones.  Every output is checked against
+numpy (outside the timed region), and the outputs of all timed sorts of a
+workload must be identical.  The CPU oracle (one pinned host core) and GNU
+std::sort are timed on a bounded sample of the headline input.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--extra]
+Printed: ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--extra] [--small]
 """
 from __future__ import annotations
 
@@ -19,6 +29,7 @@ import argparse
 import json
 import os
 import platform
+import statistics
 import sys
 import time
 
@@ -29,20 +40,25 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 CONFIGS = {
-    # name: (kind, n, distributions or None, seed, description)
+    # name: (kind, n, distributions or segment bounds, seed, description)
+    "i32_2e28": ("i32", 1 << 28, None, 1, "sort_i32, 2^28 int32 keys uniform over the full range"),
+    "f64_2e28": ("f64", 1 << 28, ["uniform"], 2, "sort_f64, 2^28 float64 keys uniform on [0,1) (totalOrder)"),
+    "kv_2e28": ("kv", 1 << 28, None, 4,
+                "sort_kv_i32, 2^28 int32 pairs, 2^16 distinct keys, values = original index"),
     "f64_2e27": ("f64", 1 << 27, ["uniform", "normal", "sorted", "reverse"], 2,
                  "sort_f64, 2^27 float64 keys x 4 distributions (uniform [0,1), N(0,1), sorted, reverse)"),
     "i32_2e20": ("i32", 1 << 20, None, 1, "sort_i32, 2^20 int32 keys uniform over the full range"),
-    "i32_2e28": ("i32", 1 << 28, None, 1, "sort_i32, 2^28 int32 keys uniform over the full range"),
-    "kv_2e28": ("kv", 1 << 28, None, 4,
-                "sort_kv_i32, 2^28 int32 pairs, 2^16 distinct keys, values = original index"),
     "kvf64_2e27": ("kvf64", 1 << 27, None, 6,
                    "sort_kv_f64, 2^27 (float64 key, int32 value) pairs, 2^16 distinct N(0,1) keys, "
                    "values = original index"),
     "seg_A": ("seg", 200000, (16, 1 << 13), 5,
-              "sort_segmented_i32, 200,000 int32 arrays, sizes log-uniform in [16, 2^13]"),
+              "sort_segmented_i32, 200,000 int32 arrays, sizes log-uniform in [16, 2^13], one autotuned graph replay"),
     "seg_B": ("seg", 2840, (16, 1 << 20), 5,
-              "sort_segmented_i32, 2,840 int32 arrays, sizes log-uniform in [16, 2^20]"),
+              "sort_segmented_i32, 2,840 int32 arrays, sizes log-uniform in [16, 2^20], one autotuned graph replay"),
+    "learned_2e28_lognormal": ("f64", 1 << 28, ["lognormal"], 6,
+                               "sort_f64 with learned splitters (training included), 2^28 lognormal(0,2) float64 keys"),
+    "plain_2e28_lognormal": ("f64", 1 << 28, ["lognormal"], 6,
+                             "sort_f64 (plain method) on the input of learned_2e28_lognormal"),
     "learned_2e28": ("f64", 1 << 28, ["lognormal", "zipf", "mixture"], 6,
                      "sort_f64 with learned splitters (training included), 2^28 float64 keys x 3 distributions "
                      "(lognormal(0,2), Zipf s=1.1 over 2^24, 8-Gaussian mixture)"),
@@ -58,11 +74,19 @@ CONFIGS = {
                          "sort_i32 with the partition levels in place, 2^28 int32 keys uniform over the full range"),
 }
 
+HEADLINE = "i32_2e28"
+# measured beside the headline in a default run
+BESIDE = ["f64_2e28", "kv_2e28", "plain_2e28_lognormal", "learned_2e28_lognormal", "seg_A", "i32_2e20", "f64_2e27"]
+# measured too with --extra
+EXTRA = ["kvf64_2e27", "seg_B", "learned_2e28", "sampled_2e28_learned_inputs", "plain_2e28_learned_inputs",
+         "f64_2e27_inplace", "i32_2e28_inplace"]
+
 # configurations sorted with the partition levels in place
 INPLACE = {"f64_2e27_inplace", "i32_2e28_inplace"}
-
 # configurations sorted with the learned-splitter method: name -> learn_flags
-LEARNED = {"learned_2e28": 0, "sampled_2e28_learned_inputs": 2}
+LEARNED = {"learned_2e28": 0, "learned_2e28_lognormal": 0, "sampled_2e28_learned_inputs": 2}
+
+DTYPE = {"f64": "u64", "i32": "u32", "kv": "u64", "kvf64": "u128", "seg": "u32"}
 
 
 def log(msg):
@@ -75,31 +99,76 @@ def make_inputs(name):
     import workloads
     kind, n, extra, seed, _ = CONFIGS[name]
     if kind == "f64":
-        return [("f64", workloads.f64(n, d, seed=seed)) for d in extra]
+        return [("f64", d, workloads.f64(n, d, seed=seed)) for d in extra]
     if kind == "i32":
-        return [("i32", workloads.uniform_i32(n, seed=seed))]
+        return [("i32", None, workloads.uniform_i32(n, seed=seed))]
     if kind == "kv":
-        k, v = workloads.kv_dup_i32(n, seed=seed)
-        return [("kv", (k, v))]
+        return [("kv", None, workloads.kv_dup_i32(n, seed=seed))]
     if kind == "kvf64":
-        k, v = workloads.kv_dup_f64(n, seed=seed)
-        return [("kvf64", (k, v))]
+        return [("kvf64", None, workloads.kv_dup_f64(n, seed=seed))]
     if kind == "seg":
         lo, hi = extra
         off = workloads.segment_offsets(n, lo, hi, seed=seed)
-        return [("seg", (workloads.uniform_i32(int(off[-1]), seed=seed + 1), off.astype(np.int64)))]
+        return [("seg", None, (workloads.uniform_i32(int(off[-1]), seed=seed + 1), off.astype(np.int64)))]
     raise ValueError(kind)
 
 
-class Case:
-    """One array of the step: pristine device copy + work buffers."""
+# ---------------------------------------------------------------- output checks (numpy, outside the timing)
 
-    def __init__(self, kind, data, torch):
-        self.kind = kind
+def _f64_sorted_bits(x):
+    """float64 values sorted by IEEE totalOrder, as uint64 bits."""
+    import numpy as np
+    u = x.view(np.uint64)
+    k = np.where(u >> np.uint64(63), ~u, u | np.uint64(1 << 63))
+    k.sort()
+    return np.where(k >> np.uint64(63), k & np.uint64((1 << 63) - 1), ~k)
+
+
+def check_output(kind, host_in, out):
+    """Raise if `out` (numpy) is not the sorted form of `host_in`."""
+    import numpy as np
+    if kind == "i32":
+        if not np.array_equal(out, np.sort(host_in)):
+            raise AssertionError("int32 output differs from numpy's sort")
+    elif kind == "f64":
+        if not np.array_equal(out.view(np.uint64), _f64_sorted_bits(host_in)):
+            raise AssertionError("float64 output differs from the totalOrder sort")
+    elif kind in ("kv", "kvf64"):
+        k_in, _ = host_in
+        k_out, v_out = out
+        ref = np.sort(k_in) if kind == "kv" else _f64_sorted_bits(k_in).view(np.float64)
+        if not np.array_equal(k_out.view(np.uint8), ref.view(np.uint8)):
+            raise AssertionError("key/value keys differ from numpy's sort")
+        idx = v_out.astype(np.int64)
+        if idx.min() < 0 or idx.max() >= k_in.size or np.bincount(idx, minlength=k_in.size).max() != 1:
+            raise AssertionError("values are not a permutation of the input positions")
+        if not np.array_equal(k_in[idx].view(np.uint8), k_out.view(np.uint8)):
+            raise AssertionError("a key lost its value")
+    elif kind == "seg":
+        k_in, off = host_in
+        sid = np.repeat(np.arange(off.size - 1, dtype=np.int64), np.diff(off))
+        comb = (sid << 32) | (k_in.astype(np.int64) + (1 << 31))
+        comb.sort()
+        ref = ((comb & 0xFFFFFFFF) - (1 << 31)).astype(np.int32)
+        if not np.array_equal(out, ref):
+            raise AssertionError("segmented output differs from per-segment sorts")
+    else:
+        raise ValueError(kind)
+
+
+# ---------------------------------------------------------------- one workload
+
+class Case:
+    """One array of a workload: pristine device copy and work buffers."""
+
+    def __init__(self, kind, dist, data, torch):
+        self.kind, self.dist, self.host = kind, dist, data
         dev = "cuda"
+        self.off = None
         if kind in ("f64", "i32"):
             self.src = torch.from_numpy(data).to(dev)
             self.work = torch.empty_like(self.src)
+            self.vsrc = None
             self.n = data.size
             self.s = data.itemsize
         elif kind in ("kv", "kvf64"):
@@ -113,39 +182,54 @@ class Case:
         else:
             k, off = data
             self.src = torch.from_numpy(k).to(dev)
+            self.vsrc = None
             self.work = torch.empty_like(self.src)
             self.off = torch.from_numpy(off).to(dev)
             self.n = k.size
             self.s = 4
+        self.plan = None
+        self.first = None  # output of the first timed sort (device copy)
 
     def restore(self):
         self.work.copy_(self.src)
-        if self.kind in ("kv", "kvf64"):
+        if self.vsrc is not None:
             self.vwork.copy_(self.vsrc)
 
-    def sort(self, hs, opts=None):
-        if getattr(self, "plan", None) is not None:
-            return self.plan.run()
+    def sort(self, hs, opts, stats):
+        if self.plan is not None:
+            self.plan.run()
+            return None
         if self.kind in ("f64", "i32"):
-            return hs.sort_(self.work, opts=opts, stats=True)
+            return hs.sort_(self.work, opts=opts, stats=stats)
         if self.kind in ("kv", "kvf64"):
-            return hs.sort_kv_(self.work, self.vwork, opts=opts, stats=True)
-        return hs.sort_segmented_(self.work, self.off, opts=opts, stats=True)
+            return hs.sort_kv_(self.work, self.vwork, opts=opts, stats=stats)
+        return hs.sort_segmented_(self.work, self.off, opts=opts, stats=stats)
+
+    def output(self):
+        if self.vsrc is not None:
+            return (self.work.cpu().numpy(), self.vwork.cpu().numpy())
+        return self.work.cpu().numpy()
+
+    def keep_first(self):
+        self.first = [self.work.clone()] + ([self.vwork.clone()] if self.vsrc is not None else [])
+
+    def same_as_first(self, torch):
+        cur = [self.work] + ([self.vwork] if self.vsrc is not None else [])
+        return all(torch.equal(a, b) for a, b in zip(self.first, cur))
 
 
-def run_gpu(name, steps, warmup, driver=0):
+def run_workload(name, steps, warmup, driver=0, stat_runs=3):
+    """Time one workload; returns a dict of its measurements."""
     import torch
 
     import paper_1704_08579_amd as hs
     hs.lib()
-    inputs = make_inputs(name)
-    dists = CONFIGS[name][2] if CONFIGS[name][0] == "f64" else [None] * len(inputs)
-    cases = [Case(k, d, torch) for k, d in inputs]
-    del inputs
+    t_in = time.perf_counter()
+    cases = [Case(k, d, data, torch) for k, d, data in make_inputs(name)]
+    log(f"[bench] {name}: inputs ready ({time.perf_counter() - t_in:.1f} s)")
     opts = hs.learned_opts(seed=100, flags=LEARNED[name]) if name in LEARNED else hs.Opts()
     opts.driver = driver
     opts.inplace = 1 if name in INPLACE else 0
-    learn = {d: [] for d in dists} if name in LEARNED else None
     graph = None
     if CONFIGS[name][0] == "seg":
         # batched segmented sort: autotuned knobs, one graph replay per sort
@@ -156,73 +240,114 @@ def run_gpu(name, steps, warmup, driver=0):
         t0 = time.perf_counter()
         tuned, report = hs.autotune(c.work, offsets=c.off, opts=base)
         tune_s = time.perf_counter() - t0
-        # stats of one eager sort with the tuned knobs (the graph cannot read them back)
-        c.restore()
-        seg_stats = c.sort(hs, tuned)
         c.plan = hs.Plan(c.work, offsets=c.off, opts=tuned)
         graph = dict(tune_report=report, tune_s=round(tune_s, 2),
                      knobs=dict(local_T=tuned.local_T, leaf=tuned.leaf, pivot_rule=tuned.pivot_rule))
-    torch.cuda.synchronize()
+        stat_opts = tuned
+    else:
+        stat_opts = opts
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    sort_ms = []
-    acc = dict(bytes_alg=0, keys_part=0, part_ms=0.0, part_launches=0, local_ms=0.0, local_keys=0)
+    step_ms = []
+    torch.cuda.synchronize()
     for step in range(warmup + steps):
         timed = step >= warmup
-        if step == warmup:
-            torch.cuda.synchronize()
-            t_wall = time.perf_counter()
         ms_step = 0.0
-        for c, dist in zip(cases, dists):
+        for c in cases:
             c.restore()
             ev0.record()
-            st = c.sort(hs, opts)
+            c.sort(hs, opts, False)
             ev1.record()
             ev1.synchronize()
             ms_step += ev0.elapsed_time(ev1)
-            if graph is not None:
+            if c.plan is not None:
                 c.plan.check()
-                st = seg_stats
-            if timed and learn is not None:
-                learn[dist].append(dict(ms=ev0.elapsed_time(ev1), learn_ms=st["learn_ms"],
-                                        multiway_ms=st["multiway_ms"], fallback_used=st["fallback_used"],
-                                        splitters=st["splitters"], model_imbalance=st["model_imbalance"],
-                                        sample_imbalance=st["sample_imbalance"], final_loss=st["final_loss"],
-                                        bytes_per_key=st["bytes_alg"] / c.n))
-            if timed:
-                acc["bytes_alg"] += st["bytes_alg"]
-                acc["keys_part"] += st["keys_partitioned"]
-                acc["part_ms"] += st["partition_ms"]
-                acc["part_launches"] += st["partition_launches"]
-                acc["local_ms"] += st["local_ms"]
-                acc["local_keys"] += c.n
+            if step == warmup:
+                c.keep_first()
         if timed:
-            sort_ms.append(ms_step)
+            step_ms.append(ms_step)
         log(f"[bench] {name} step {step} ({'timed' if timed else 'warmup'}): {ms_step:.3f} ms")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
+    # every timed sort gave the same output; the last one is checked against numpy
+    t_chk = time.perf_counter()
+    for c in cases:
+        if not c.same_as_first(torch):
+            raise AssertionError(f"{name}: timed sorts gave different outputs")
+        check_output(c.kind, c.host, c.output())
+        c.first = None
+    log(f"[bench] {name}: outputs checked against numpy ({time.perf_counter() - t_chk:.1f} s)")
+    # instrumented sorts (per-level events inside the library), outside the timing
+    acc = dict(bytes_alg=0, keys_part=0, part_ms=0.0, part_launches=0, local_ms=0.0, local_keys=0, levels=0)
+    learn = {}
+    for _ in range(stat_runs):
+        for c in cases:
+            c.restore()
+            if c.plan is not None:
+                saved, c.plan = c.plan, None
+                st = c.sort(hs, stat_opts, True)
+                c.plan = saved
+            else:
+                st = c.sort(hs, opts, True)
+            acc["bytes_alg"] += st["bytes_alg"]
+            acc["keys_part"] += st["keys_partitioned"]
+            acc["part_ms"] += st["partition_ms"]
+            acc["part_launches"] += st["partition_launches"]
+            acc["local_ms"] += st["local_ms"]
+            acc["local_keys"] += c.n
+            acc["levels"] += st["passes"]
+            if name in LEARNED:
+                learn.setdefault(c.dist, []).append(dict(
+                    learn_ms=st["learn_ms"], multiway_ms=st["multiway_ms"], fallback_used=st["fallback_used"],
+                    splitters=st["splitters"], model_imbalance=st["model_imbalance"],
+                    sample_imbalance=st["sample_imbalance"], final_loss=st["final_loss"],
+                    bytes_per_key=st["bytes_alg"] / c.n))
     keys_step = sum(c.n for c in cases)
     s = cases[0].s
-    ms = sum(sort_ms) / len(sort_ms)
+    med = statistics.median(step_ms)
+    nst = stat_runs
     part_bytes = 2 * s * acc["keys_part"]
     part_gbs = part_bytes / (acc["part_ms"] * 1e-3) / 1e9 if acc["part_ms"] > 0 else 0.0
-    local_gbs = 2 * s * acc["local_keys"] / (acc["local_ms"] * 1e-3) / 1e9 if acc["local_ms"] > 0 else 0.0
-    total_s = sum(sort_ms) * 1e-3
-    return dict(
-        name=name, keys_per_step=keys_step, ms_per_step=ms, wall_ms_per_step=wall * 1e3 / steps,
-        gkeys=keys_step / (ms * 1e-3) / 1e9,
-        bytes_per_key=acc["bytes_alg"] / (keys_step * steps),
-        whole_sort_roofline=acc["bytes_alg"] / total_s / 1e9 / HBM_PEAK_GBS,
-        partition=dict(gbs=part_gbs, ms_per_step=acc["part_ms"] / steps,
-                       launches_per_step=acc["part_launches"] / steps,
+    bytes_per_step = acc["bytes_alg"] / nst
+    out = dict(
+        name=name, kind=cases[0].kind, keys_per_step=keys_step, elem_bytes=s,
+        median_ms=med, min_ms=min(step_ms), max_ms=max(step_ms), runs=len(step_ms),
+        gkeys=keys_step / (med * 1e-3) / 1e9,
+        bytes_per_key=bytes_per_step / keys_step,
+        whole_sort_roofline=bytes_per_step / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        levels_per_sort=acc["levels"] / (nst * len(cases)),
+        partition=dict(gbs=part_gbs, ms_per_step=acc["part_ms"] / nst,
+                       launches_per_step=acc["part_launches"] / nst,
                        bytes_per_launch=part_bytes / max(1, acc["part_launches"]),
                        avg_launch_ms=acc["part_ms"] / max(1, acc["part_launches"])),
-        local=dict(gbs=local_gbs, ms_per_step=acc["local_ms"] / steps),
-        elem_bytes=s,
-        learned=None if learn is None else {
-            d: {k: round(sum(r[k] for r in v) / len(v), 4) for k in v[0]} for d, v in learn.items()},
+        local=dict(ms_per_step=acc["local_ms"] / nst,
+                   gbs=2 * s * acc["local_keys"] / (acc["local_ms"] * 1e-3) / 1e9 if acc["local_ms"] > 0 else 0.0),
         graph=graph,
+        learned={d: {k: round(sum(r[k] for r in v) / len(v), 4) for k in v[0]} for d, v in learn.items()} or None,
     )
+    for c in cases:
+        if c.plan is not None:
+            c.plan.close()
+    del cases
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def summary(r):
+    """The fields of one workload printed beside the headline."""
+    d = {"workload": CONFIGS[r["name"]][4], "gkeys_per_s": round(r["gkeys"], 3),
+         "ms_per_step": {"median": round(r["median_ms"], 4), "min": round(r["min_ms"], 4),
+                         "max": round(r["max_ms"], 4), "runs": r["runs"]},
+         "keys_per_step": r["keys_per_step"], "bytes_per_key": round(r["bytes_per_key"], 1),
+         "whole_sort_roofline_frac": round(r["whole_sort_roofline"], 4),
+         "partition_gbs": round(r["partition"]["gbs"], 1),
+         "partition_ms_per_step": round(r["partition"]["ms_per_step"], 3),
+         "local_sort_ms_per_step": round(r["local"]["ms_per_step"], 3),
+         "levels_per_sort": round(r["levels_per_sort"], 2), "output_checked": True}
+    if r["learned"]:
+        d["per_distribution"] = r["learned"]
+    if r["graph"]:
+        d["graph"] = r["graph"]
+    return d
 
 
 def measured_traffic(name, kernel):
@@ -245,49 +370,56 @@ def measured_traffic(name, kernel):
     return int(val.group(1))
 
 
-def cpu_baseline(name):
-    """The oracle (single thread, as written) on a bounded sample of the
-    workload: the first 2^27 keys of the first array of the step (about
-    15 s for float64 on one host core)."""
+def cpu_baseline(name, log2_sample=26):
+    """The oracle (single thread, as written) on the first 2^26 keys of the
+    workload's first array, on one pinned host core (about 15 s for int32),
+    and GNU std::sort once on the same sample for context."""
     import numpy as np
 
     import oracle
     kind, n, extra, seed, _ = CONFIGS[name]
-    inputs = make_inputs(name)
-    kind0, data = inputs[0]
-    m = min(n, 1 << 27)
-    t0 = time.perf_counter()
-    if kind0 == "f64":
-        oracle.sort_f64(data[:m])
-        what = f"first 2^{m.bit_length() - 1} keys of the {extra[0]} float64 array"
-    elif kind0 == "i32":
-        oracle.sort_i32(data[:m])
-        what = f"first 2^{m.bit_length() - 1} keys of the int32 array"
-    elif kind0 == "kv":
-        oracle.sort_kv_i32(data[0][:m], data[1][:m])
-        what = f"first 2^{m.bit_length() - 1} pairs"
-    elif kind0 == "kvf64":
-        oracle.sort_kv_f64(data[0][:m], data[1][:m])
-        what = f"first 2^{m.bit_length() - 1} float64 key/value pairs"
-    else:
-        k, off = data
-        nseg = int(np.searchsorted(off, m, side="right")) - 1
-        sub = off[: nseg + 1]
-        oracle.sort_segmented_i32(k[: int(sub[-1])], sub)
-        m = int(sub[-1])
-        what = f"first {nseg} segments ({m} keys)"
-    dt = time.perf_counter() - t0
+    _, dist, data = make_inputs(name)[0]
+    m = min(n, 1 << log2_sample)
+    prev = os.sched_getaffinity(0)
+    core = min(prev)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        if kind == "f64":
+            sample = data[:m]
+            out = oracle.sort_f64(sample)
+            what = f"first 2^{m.bit_length() - 1} keys of the {dist} float64 array"
+        elif kind == "i32":
+            sample = data[:m]
+            out = oracle.sort_i32(sample)
+            what = f"first 2^{m.bit_length() - 1} keys of the int32 array"
+        elif kind == "kv":
+            sample = data[0][:m]
+            out, _ = oracle.sort_kv_i32(sample, data[1][:m])
+            what = f"first 2^{m.bit_length() - 1} pairs"
+        else:
+            raise ValueError(f"no CPU baseline for {name}")
+        dt = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        ref = oracle.std_sort_context(sample)
+        dt_std = time.perf_counter() - t1
+    finally:
+        os.sched_setaffinity(0, prev)
+    if not np.array_equal(out.view(np.uint8), ref.view(np.uint8)) and kind != "f64":
+        raise AssertionError("the oracle and std::sort disagree on the CPU sample")
+    host = f"{platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"
     return {"value": m / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": what + f", {dt:.1f} s on one host core ({platform.processor() or platform.machine()}, "
-                             f"os.cpu_count()={os.cpu_count()})"}
+            "sample": what + f", {dt:.1f} s on one pinned host core ({host})",
+            "std_sort_context": {"value": m / dt_std / 1e9, "unit": "Gkeys/s", "cores": 1,
+                                 "seconds": round(dt_std, 2),
+                                 "note": "GNU std::sort on the same sample and core (the paper's comparison "
+                                         "library; context only)"}}
 
 
 def run_small(reps=40):
     """Small arrays: latency of one sort per size (GPU time between events on
     the sort stream, and host time from the call to the sort's completion),
     and batched sorts of many equal-size arrays in one segmented call."""
-    import statistics
-
     import torch
 
     import paper_1704_08579_amd as hs
@@ -351,77 +483,77 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="f64_2e27", choices=sorted(CONFIGS))
-    ap.add_argument("--extra", action="store_true", help="also run the int32, key/value and batched configs")
+    ap.add_argument("--config", default=HEADLINE, choices=sorted(CONFIGS),
+                    help="the workload of `value` (default: int32 2^28)")
+    ap.add_argument("--only", action="store_true", help="measure --config alone, nothing beside it")
+    ap.add_argument("--extra", action="store_true", help="also measure the remaining workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true",
                     help="also measure small arrays: per-size latency and batched throughput")
-    ap.add_argument("--driver", choices=["persistent", "host"], default="host",
+    ap.add_argument("--driver", choices=["auto", "persistent", "host"], default="auto",
                     help="partition levels in one persistent launch, or one launch per level")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
+        print("bench.py: this build runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1:
+        print("bench.py: --steps must be at least 1", file=sys.stderr)
         sys.exit(2)
 
-    driver = 2 if args.driver == "persistent" else 1
-    r = run_gpu(args.config, args.steps, args.warmup, driver)
-    extra = {}
-    if args.extra:
-        for nm in ["i32_2e28", "kv_2e28", "kvf64_2e27", "seg_A", "seg_B", "i32_2e20", "learned_2e28",
-                   "sampled_2e28_learned_inputs", "plain_2e28_learned_inputs", "f64_2e27_inplace",
-                   "i32_2e28_inplace"]:
-            if nm == args.config:
-                continue
-            e = run_gpu(nm, max(3, args.steps // 2), 1, driver)
-            extra[nm] = {"gkeys_per_s": round(e["gkeys"], 3), "ms_per_step": round(e["ms_per_step"], 3),
-                         "bytes_per_key": round(e["bytes_per_key"], 1),
-                         "partition_gbs": round(e["partition"]["gbs"], 1),
-                         "whole_sort_roofline_frac": round(e["whole_sort_roofline"], 4),
-                         "workload": CONFIGS[nm][4]}
-            if e["learned"]:
-                extra[nm]["per_distribution"] = e["learned"]
-            if e["graph"]:
-                extra[nm]["graph"] = e["graph"]
+    driver = {"auto": 0, "host": 1, "persistent": 2}[args.driver]
+    r = run_workload(args.config, args.steps, args.warmup, driver)
+    beside = {}
+    names = [] if args.only else [nm for nm in BESIDE + (EXTRA if args.extra else []) if nm != args.config]
+    for nm in names:
+        beside[nm] = summary(run_workload(nm, args.steps, min(args.warmup, 2), driver))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.config)
 
-    kind, n, _, _, desc = CONFIGS[args.config]
     p = r["partition"]
+    persistent = driver == 2
+    kernel = "k_levels" if persistent else "k_partition"
     out = {
-        "metric": "sorted Gkeys/s + HBM roofline %",
+        "metric": "sorted Gkeys/s at 2^28 + HBM roofline %",
         "value": round(r["gkeys"], 4),
         "unit": "Gkeys/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(r["ms_per_step"], 4),
+        "ms_per_step": round(r["median_ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "u64", "i32": "u32", "kv": "u64", "kvf64": "u128", "seg": "u32"}[kind],
+        "dtype": DTYPE[r["kind"]],
         "data": "synthetic",
-        "config": {"workload": desc, "keys_per_step": r["keys_per_step"],
+        "config": {"workload": CONFIGS[args.config][4], "keys_per_step": r["keys_per_step"],
+                   "timing": {"statistic": "median", "min_ms": round(r["min_ms"], 4),
+                              "max_ms": round(r["max_ms"], 4), "runs": r["runs"]},
                    "bytes_per_key": round(r["bytes_per_key"], 1),
                    "whole_sort_roofline_frac": round(r["whole_sort_roofline"], 4),
-                   "wall_ms_per_step_incl_restore": round(r["wall_ms_per_step"], 3),
+                   "levels_per_sort": round(r["levels_per_sort"], 2),
                    "local_sort_gbs": round(r["local"]["gbs"], 1),
                    "local_sort_ms_per_step": round(r["local"]["ms_per_step"], 3),
                    "partition_ms_per_step": round(p["ms_per_step"], 3),
-                   "partition_launches_per_step": p["launches_per_step"]},
+                   "partition_launches_per_step": p["launches_per_step"],
+                   "output_checked": True},
         "roofline": {"bound": "hbm",
-                     "kernel": ("k_levels (every partition level of a sort in one persistent launch)" if driver == 2
+                     "kernel": ("k_levels (every partition level of a sort in one persistent launch)" if persistent
                                 else "k_partition (one partition level per launch)"),
                      "achieved": round(p["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(p["gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.config, "k_levels" if driver == 2 else "k_partition"),
+                     "frac": round(p["gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.config, kernel),
                      "bytes_per_launch": round(p["bytes_per_launch"]),
-                     "avg_launch_ms": round(p["avg_launch_ms"], 4)},
+                     "avg_launch_ms": round(p["avg_launch_ms"], 4),
+                     "whole_sort_frac": round(r["whole_sort_roofline"], 4)},
         "cpu_baseline": cpu,
     }
     if r["learned"]:
         out["config"]["learned_per_distribution"] = r["learned"]
-    if extra:
-        out["extra"] = extra
+    if r["graph"]:
+        out["config"]["graph"] = r["graph"]
+    if beside:
+        out["beside"] = beside
     if args.small:
         out["small_arrays"] = run_small()
     print(json.dumps(out), flush=True)

@@ -19,6 +19,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "hsort_oracle.c"), os.path.join(_HERE, "learned_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
+_CTX_SRC = os.path.join(_HERE, "std_sort_context.cpp")
+_CTX_LIB = os.path.join(_HERE, "libstdsort_context.so")
 
 _I64 = ctypes.c_int64
 _P = ctypes.c_void_p
@@ -31,6 +33,10 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC",
                                "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_CTX_LIB) or os.path.getmtime(_CTX_LIB) < os.path.getmtime(_CTX_SRC):
+        tmp = _CTX_LIB + ".tmp"
+        subprocess.check_call(["g++", "-O3", "-std=c++17", "-shared", "-fPIC", "-o", tmp, _CTX_SRC])
+        os.replace(tmp, _CTX_LIB)
     return _LIB
 
 
@@ -316,4 +322,26 @@ def f64_order_keys(x) -> np.ndarray:
     bits = np.ascontiguousarray(x, dtype=np.float64).view(np.uint64)
     out = np.empty(bits.size, dtype=np.uint64)
     lib().oracle_keys_f64(_ptr(bits), bits.size, _ptr(out))
+    return out
+
+
+_ctx = None
+
+
+def std_sort_context(a: np.ndarray) -> np.ndarray:
+    """GNU std::sort of an int32 or float64 array on the calling thread (the
+    paper's comparison library, timed by the benchmark for context only)."""
+    global _ctx
+    if _ctx is None:
+        if not os.path.exists(_CTX_LIB):
+            build(force=False)
+        _ctx = ctypes.CDLL(_CTX_LIB)
+        for nm in ("context_std_sort_i32", "context_std_sort_f64"):
+            getattr(_ctx, nm).argtypes = [_P, _I64]
+            getattr(_ctx, nm).restype = None
+    out = np.ascontiguousarray(a).copy()
+    fn = _ctx.context_std_sort_i32 if out.dtype == np.int32 else _ctx.context_std_sort_f64
+    if out.dtype not in (np.int32, np.float64):
+        raise TypeError(out.dtype)
+    fn(_ptr(out), out.size)
     return out
