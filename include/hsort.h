@@ -212,7 +212,12 @@ HS_API int hs_sort_kv_f64(double *keys, int32_t *vals, int64_t n, const hs_opts 
  * partitioned back (one read and one write of each key after the copy);
  * with opts->inplace set they never leave the array (classify, count the
  * misplaced keys, exchange them pairwise), and the workspace holds one bit
- * per key and 4 bytes per 64 keys instead of a copy. */
+ * per key and 4 bytes per 64 keys instead of a copy.  The call returns once
+ * its work is enqueued, so errors found by its kernels cannot be returned:
+ * if one flags an inconsistency (the misplaced-key counts of the in-place
+ * exchange do not match), *d_count_le is set to -1 and the keys are left
+ * partly partitioned.  n = 0 writes 0 without touching keys.  Every clear
+ * is a kernel (no memset), so the call can be captured into a graph. */
 HS_API int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_le,
                      const hs_opts *opts, void *stream);
 
@@ -277,22 +282,79 @@ HS_API int hs_mlp_train_f32(const float *d_z, const float *d_y, int64_t m, int32
 HS_API int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_splitters, int32_t k,
                                      uint32_t *d_start, void *stream);
 
-/* ---- Plans: one call captured into a HIP graph ------------------------
+/* The learned front end of a float64 sort on its own, for inspection (keys
+ * are read, not changed): the training sample of 2^sample_log2 keys
+ * (splitmix64(seed), with replacement) sorted by the plain method, the
+ * held-out sample of 2^14 keys (splitmix64(seed + 1)), the model trained on
+ * the sample's empirical CDF, its 255 splitters (for j = 1..255 the smallest
+ * totalOrder key K with F(K) >= j/256, found by a 64-ary search in fp32,
+ * before the running maximum), the sample's order statistics (the key of
+ * rank floor(j * m / 256) of the sorted sample, j = 1..255), and the judge:
+ * running maximum and de-duplication of the model's splitters,
+ * de-duplication of the order statistics, the bucket counts of both sets on
+ * the held-out sample, their imbalance (largest non-equality bucket over
+ * h/256) and the choice (the model unless its imbalance exceeds 1.25 times
+ * the order statistics').  Same options and results as the learned sort's
+ * front end (hs_opts.method is taken as HS_METHOD_LEARNED).
+ * Outputs (device memory, caller-owned; totalOrder keys as uint64 words):
+ *   d_params       1153 floats, the trained parameters;
+ *   d_model_split  255 words, the model's splitters;
+ *   d_sample_split 255 words, the order statistics;
+ *   d_chosen       255 words, the first report->k are the chosen distinct
+ *                  splitters;
+ *   d_holdout      2^14 words, the held-out sample in draw order;
+ *   d_train_sorted 2^sample_log2 doubles, the sorted training sample;
+ *   d_counts       2 * 511 words: the held-out bucket counts of the model's
+ *                  distinct splitters (bucket 2r: keys strictly between
+ *                  splitters r-1 and r, 2r+1: keys equal to splitter r),
+ *                  then those of the order statistics; unused entries 0;
+ *   report         (host) feature normalisation mu and sd, the sample's
+ *                  extreme keys, sizes, the judge's imbalances and choice,
+ *                  and the loss after the last training step.
+ * With HS_LEARN_FORCE_SAMPLE the model is not trained: d_params and
+ * d_model_split are copied from uninitialised workspace and carry no
+ * meaning, and the model imbalance is -1.  Returns once the work is done
+ * (it reads the report back).  HS_EINVAL for n < 1 or a NULL pointer. */
+typedef struct hs_learn_report {
+    double mu, sd;           /* the model's input is (asinh(x) - mu) / sd */
+    uint64_t smin, smax;     /* totalOrder keys of the sample's smallest and largest key */
+    int32_t m, h;            /* training and held-out sample sizes */
+    int32_t k;               /* distinct splitters chosen */
+    int32_t use_model;       /* 1: the model's splitters, 0: the order statistics */
+    float model_imbalance, sample_imbalance, final_loss;
+    int32_t reserved;
+} hs_learn_report;
+HS_API int hs_learn_debug_f64(const double *keys, int64_t n, const hs_opts *opts, float *d_params,
+                              uint64_t *d_model_split, uint64_t *d_sample_split, uint64_t *d_chosen,
+                              uint64_t *d_holdout, double *d_train_sorted, uint32_t *d_counts,
+                              hs_learn_report *report, void *stream);
+
+/* ---- Plans: one sort captured into a HIP graph -------------------------
  *
- * hs_plan_create records one sort of the given buffers (op HS_OP_SORT_I32,
- * _U32, _I64, _F64, _KV_I32, _KV_F64, _SORT_SEGMENTED_I32 or _SORT_SEGMENTED_F64; vals only for key/value, d_offsets
- * and nseg only for segmented) into a graph: the partition levels run in the
- * persistent driver, every clear is a kernel, and the plan owns its
- * workspace, so replaying it needs no host work beyond hipGraphLaunch.
- * Each hs_plan_exec sorts whatever the buffers hold at that moment.  Replays
- * of one plan must not overlap (they share its workspace).  With
- * opts->autotune set, the knobs are tuned first (hs_autotune, persistent
- * driver).  The call synchronizes the device while creating the plan. */
+ * hs_plan_create prepares a sort of a fixed shape (op HS_OP_SORT_I32, _U32,
+ * _I64, _F64, _KV_I32, _KV_F64, _SORT_SEGMENTED_I32 or _SORT_SEGMENTED_F64;
+ * n keys; nseg segments for the segmented ops, ignored otherwise) and
+ * allocates the plan's own workspace; it takes no buffers.  hs_plan_exec
+ * sorts the caller's buffers (keys; vals only for key/value, d_offsets only
+ * for segmented; each of the plan's shape) with the plan: the partition
+ * levels run in the persistent driver and every clear is a kernel, so the
+ * whole sort is one HIP graph launched on `stream`.  The graph is recorded
+ * by the first hs_plan_exec and recorded again, and updated in place, when
+ * a later call passes other buffers than the call before it; a replay on
+ * the same buffers is only hipGraphLaunch.  The first call also tunes the
+ * knobs when opts->autotune is set (hs_autotune on those buffers, persistent
+ * driver) and, for segmented sorts, reads the offsets once to size the
+ * recorded levels; it synchronizes `stream` for that.  Any later offsets
+ * are correct too (the persistent driver finishes whatever levels remain).
+ * Replays of one plan must not overlap (they share its workspace), and calls
+ * on one plan must not run concurrently from several threads.
+ * Errors: HS_EINVAL for a bad op, size or pointer, for in-place levels, the
+ * host-driven level loop or a caller workspace in opts, and for a stream of
+ * another device than the plan's; HS_ENOMEM if the workspace cannot be
+ * allocated; HS_EHIP if recording or launching the graph fails. */
 typedef struct hs_plan hs_plan;
-HS_API int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_offsets, int64_t nseg,
-                          const hs_opts *opts, hs_plan **plan);
-/* `stream` must belong to the device the plan was created on. */
-HS_API int hs_plan_exec(hs_plan *plan, void *stream);
+HS_API int hs_plan_create(int op, int64_t n, int64_t nseg, const hs_opts *opts, hs_plan **plan);
+HS_API int hs_plan_exec(hs_plan *plan, void *keys, int32_t *vals, const int64_t *d_offsets, void *stream);
 /* Waits for the plan's last replay on `stream` and reports the error word
  * its kernels left (HS_EINTERNAL if set). */
 HS_API int hs_plan_check(hs_plan *plan, void *stream);

@@ -77,6 +77,8 @@ def lib() -> ctypes.CDLL:
             ("oracle_adam_step", [_P, _P, _P, _P, _I64, ctypes.c_double], None),
             ("oracle_feature_stats", [_P, _I64, _P, _P], None),
             ("oracle_mlp_train", [ctypes.c_uint64, _P, _P, _I64, _I64, ctypes.c_double, _P, _P], None),
+            ("oracle_invert_one_f64", [_P, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                       ctypes.c_double], ctypes.c_uint64),
             ("oracle_invert_f64", [_P, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                    ctypes.c_int, _P], None),
             ("oracle_dedupe", [_P, _I64, _P], _I64),
@@ -300,6 +302,12 @@ def invert_f64(p, mu: float, sd: float, kmin: int, kmax: int, nb: int = 256) -> 
     out = np.empty(nb - 1, dtype=np.uint64)
     lib().oracle_invert_f64(_ptr(p), mu, sd, kmin, kmax, nb, _ptr(out))
     return out
+
+
+def invert_one_f64(p, mu: float, sd: float, kmin: int, kmax: int, q: float) -> int:
+    """One splitter before the running maximum: the bisection's crossing of q."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    return int(lib().oracle_invert_one_f64(_ptr(p), mu, sd, kmin, kmax, q))
 
 
 def dedupe(s) -> np.ndarray:

@@ -212,23 +212,28 @@ static double model_at(const double *p, double mu, double sd, uint64_t key)
     return forward1(p, (asinh(value_of_f64_key(key)) - mu) / sd, NULL, NULL);
 }
 
+/* The smallest order word K in [kmin, kmax] with F(K) >= q, by bisection
+ * (kmax when there is none); for a model that is not monotone, one word
+ * where F crosses q. */
+uint64_t oracle_invert_one_f64(const double *p, double mu, double sd, uint64_t kmin, uint64_t kmax, double q)
+{
+    uint64_t lo = kmin, hi = kmax;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (model_at(p, mu, sd, mid) >= q)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
 /* Splitters of a float64 key space (order words) for nb buckets: nb - 1
  * bisections, then running maximum; returns them in split[0 .. nb-2]. */
 void oracle_invert_f64(const double *p, double mu, double sd, uint64_t kmin, uint64_t kmax, int nb,
                        uint64_t *split)
 {
-    for (int j = 1; j < nb; ++j) {
-        const double q = (double)j / (double)nb;
-        uint64_t lo = kmin, hi = kmax;
-        while (lo < hi) {
-            const uint64_t mid = lo + (hi - lo) / 2;
-            if (model_at(p, mu, sd, mid) >= q)
-                hi = mid;
-            else
-                lo = mid + 1;
-        }
-        split[j - 1] = lo;
-    }
+    for (int j = 1; j < nb; ++j) split[j - 1] = oracle_invert_one_f64(p, mu, sd, kmin, kmax, (double)j / (double)nb);
     for (int j = 1; j < nb - 1; ++j)
         if (split[j] < split[j - 1]) split[j] = split[j - 1];
 }

@@ -19,8 +19,8 @@ import ctypes
 import os
 
 __all__ = ["sort_", "sort_kv_", "argsort", "partition_", "sort_segmented_", "workspace_size", "Stats", "Opts",
-           "learned_opts", "mlp_forward", "mlp_grad", "mlp_train", "multiway_partition_", "Plan", "autotune",
-           "TuneReport", "lib", "LIB_PATH", "HSortError"]
+           "learned_opts", "mlp_forward", "mlp_grad", "mlp_train", "multiway_partition_", "learn_debug", "Plan",
+           "autotune", "TuneReport", "lib", "LIB_PATH", "HSortError"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhsort.so")
 
@@ -92,8 +92,9 @@ _SIGS = {
     "hs_mlp_train_f32": ([_P, _P, _I64, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64, _P, _P, _P],
                          ctypes.c_int),
     "hs_multiway_partition_f64": ([_P, _I64, _P, ctypes.c_int32, _P, _P], ctypes.c_int),
-    "hs_plan_create": ([ctypes.c_int, _P, _P, _I64, _P, _I64, _P, _P], ctypes.c_int),
-    "hs_plan_exec": ([_P, _P], ctypes.c_int),
+    "hs_learn_debug_f64": ([_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "hs_plan_create": ([ctypes.c_int, _I64, _I64, _P, _P], ctypes.c_int),
+    "hs_plan_exec": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "hs_plan_check": ([_P, _P], ctypes.c_int),
     "hs_plan_destroy": ([_P], None),
     "hs_autotune": ([ctypes.c_int, _P, _P, _I64, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
@@ -316,6 +317,48 @@ def multiway_partition_(keys, splitters):
     return starts
 
 
+class LearnReport(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("sd", ctypes.c_double), ("smin", ctypes.c_uint64),
+                ("smax", ctypes.c_uint64), ("m", ctypes.c_int32), ("h", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("use_model", ctypes.c_int32), ("model_imbalance", ctypes.c_float),
+                ("sample_imbalance", ctypes.c_float), ("final_loss", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+NB_MAX = 511  # buckets of 255 distinct splitters, equality buckets included
+
+
+def learn_debug(keys, opts: Opts | None = None):
+    """The learned front end of a float64 sort on its own (hs_learn_debug_f64;
+    `keys` is not changed).  Returns a dict: the report's fields, and CUDA
+    tensors params (1153 float32), model_split, sample_split, chosen (255
+    totalOrder words as int64; the first k of chosen are used), holdout (2^14
+    words), train_sorted (the sorted training sample, float64) and counts
+    (2 x 511 int32: held-out bucket counts, model then order statistics)."""
+    torch = _torch()
+    _require(keys, (torch.float64,), "keys")
+    dev = keys.device
+    m = 1 << (opts.sample_log2 if opts is not None and opts.sample_log2 > 0 else 16)
+    out = {"params": torch.empty(MLP_NPARAM, dtype=torch.float32, device=dev),
+           "model_split": torch.empty(255, dtype=torch.int64, device=dev),
+           "sample_split": torch.empty(255, dtype=torch.int64, device=dev),
+           "chosen": torch.empty(255, dtype=torch.int64, device=dev),
+           "holdout": torch.empty(1 << 14, dtype=torch.int64, device=dev),
+           "train_sorted": torch.empty(m, dtype=torch.float64, device=dev),
+           "counts": torch.zeros(2 * NB_MAX, dtype=torch.int32, device=dev)}
+    rep = LearnReport()
+    with torch.cuda.device(dev):
+        _check(lib().hs_learn_debug_f64(keys.data_ptr(), keys.numel(), _opts_ptr(opts), out["params"].data_ptr(),
+                                        out["model_split"].data_ptr(), out["sample_split"].data_ptr(),
+                                        out["chosen"].data_ptr(), out["holdout"].data_ptr(),
+                                        out["train_sorted"].data_ptr(), out["counts"].data_ptr(),
+                                        ctypes.addressof(rep), _stream_handle(keys)))
+    out.update(rep.as_dict())
+    return out
+
+
 # ---------------------------------------------------------------- plans and the autotuner
 
 class TuneReport(ctypes.Structure):
@@ -350,24 +393,36 @@ def _sort_args(keys, vals=None, offsets=None):
 
 
 class Plan:
-    """One sort of fixed tensors captured into a HIP graph (hs_plan_*).
+    """A sort of a fixed shape captured into a HIP graph (hs_plan_*).
 
-    ``run()`` replays it on the current stream: it sorts whatever the tensors
-    hold at that moment.  The tensors are kept alive by the plan."""
+    Built from example tensors (their dtype and sizes fix the shape; they are
+    also the default buffers of ``run``).  ``run()`` sorts the default
+    tensors, ``run(keys, vals=..., offsets=...)`` other tensors of the same
+    shape, on the current stream."""
 
     def __init__(self, keys, vals=None, offsets=None, opts: Opts | None = None):
         torch = _torch()
-        self._tensors = (keys, vals, offsets)
-        op, kp, vp, n, op_off, nseg = _sort_args(keys, vals, offsets)
+        op, _, _, n, _, nseg = _sort_args(keys, vals, offsets)
+        self._op, self._n, self._nseg = op, n, nseg
+        self._default = (keys, vals, offsets)
+        self._bound = None
         self._plan = ctypes.c_void_p()
         self.device = keys.device
         with torch.cuda.device(keys.device):
-            _check(lib().hs_plan_create(op, kp, vp, n, op_off, nseg, _opts_ptr(opts), ctypes.byref(self._plan)))
+            _check(lib().hs_plan_create(op, n, nseg, _opts_ptr(opts), ctypes.byref(self._plan)))
 
-    def run(self):
+    def run(self, keys=None, vals=None, offsets=None):
         torch = _torch()
+        if keys is None:
+            keys, vals, offsets = self._default
+        op, kp, vp, n, op_off, nseg = _sort_args(keys, vals, offsets)
+        if (op, n, nseg) != (self._op, self._n, self._nseg):
+            raise ValueError("tensors of another shape than the plan's")
+        if keys.device != self.device:
+            raise ValueError("tensors on another device than the plan's")
+        self._bound = (keys, vals, offsets)  # kept alive while a replay may use them
         with torch.cuda.device(self.device):
-            _check(lib().hs_plan_exec(self._plan, torch.cuda.current_stream(self.device).cuda_stream))
+            _check(lib().hs_plan_exec(self._plan, kp, vp, op_off, torch.cuda.current_stream(self.device).cuda_stream))
         return self
 
     def check(self):

@@ -983,10 +983,12 @@ __global__ void k_count_diff(const uint32_t *a, const uint32_t *b, uint64_t nwor
     if (lane_id() == 0 && d) atomicAdd(count, d);
 }
 
-// Count of the <= side after a single-segment pass (partition entry point).
-__global__ void k_write_count(const unsigned long long *cur, int64_t *d_count)
+// Count of the <= side after a single-segment pass (partition entry point),
+// or -1 when a kernel of the pass flagged an error (the keys are then only
+// partly partitioned).
+__global__ void k_write_count(const Ctl *ctl, const unsigned long long *cur, int64_t *d_count)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *d_count = (int64_t)(uint32_t)cur[0];  // segment 0
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d_count = ctl->err ? (int64_t)-1 : (int64_t)(uint32_t)cur[0];
 }
 
 }  // namespace hs

@@ -465,12 +465,15 @@ __global__ __launch_bounds__(256) void k_ls_invert(const float *p, const LearnCt
 // both on the held-out sample, and the choice.  Writes the chosen distinct
 // splitters to `chosen` and their count to lc->k.  mode: JUDGE_AUTO, or
 // JUDGE_MODEL / JUDGE_SAMPLE to force one set (JUDGE_SAMPLE does not read
-// the model's splitters and reports a model imbalance of -1).
+// the model's splitters and reports a model imbalance of -1).  counts_out
+// (optional, 2 * NB_MAX words) receives the held-out bucket counts of both
+// sets, the model's first (2k + 1 used entries each, the rest zero).
 constexpr int JUDGE_AUTO = 0, JUDGE_MODEL = 1, JUDGE_SAMPLE = 2;
 
 template <typename K>
 __global__ __launch_bounds__(256) void k_ls_judge(const K *model_split, const K *sample_split, const K *holdout,
-                                                  uint32_t h, K *chosen, LearnCtl *lc, int mode)
+                                                  uint32_t h, K *chosen, LearnCtl *lc, int mode,
+                                                  uint32_t *counts_out)
 {
     __shared__ K dm[NSPLIT], ds[NSPLIT];
     __shared__ uint32_t cm[NB_MAX], cs[NB_MAX];
@@ -525,6 +528,11 @@ __global__ __launch_bounds__(256) void k_ls_judge(const K *model_split, const K 
     const bool um = um_s != 0;
     const uint32_t k = um ? km : ks;
     for (uint32_t i = tid; i < k; i += blockDim.x) chosen[i] = um ? dm[i] : ds[i];
+    if (counts_out)
+        for (int i = tid; i < NB_MAX; i += blockDim.x) {
+            counts_out[i] = cm[i];
+            counts_out[NB_MAX + i] = cs[i];
+        }
 }
 
 // ---------------------------------------------------------------- multiway partition

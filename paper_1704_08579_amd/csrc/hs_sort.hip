@@ -411,12 +411,59 @@ int levels_for(uint64_t size, uint32_t T)
     return l;
 }
 
+// The learned front end up to the judge: the training and held-out samples,
+// the nested plain sort of the training sample, features, training, the
+// model's splitters and the judge, which leaves the chosen distinct
+// splitters in the workspace and its decision in the LearnCtl.  counts_out
+// (optional, 2 * NB_MAX words) receives the judge's held-out bucket counts,
+// the model's splitters first.
+template <int F>
+int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg,
+              const hs_opts *o, const LearnParams &P, hs_stats *st, hipStream_t stream, int graph_levels = 0);
+
+template <int F>
+int learn_front(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, uint32_t T, const hs_opts *o,
+                const LearnParams &P, hipStream_t stream, uint32_t *counts_out)
+{
+    using K = typename KeyOf<F>::type;
+    LearnCtl *lctl = (LearnCtl *)(ws + L.lctl);
+    Raw smp{ws + L.smp_k, has_vals<F>() ? (int32_t *)(ws + L.smp_v) : nullptr};
+    float *z = (float *)(ws + L.z), *y = (float *)(ws + L.y);
+    float *par = (float *)(ws + L.par), *mom = (float *)(ws + L.mom), *vel = (float *)(ws + L.vel);
+    float *part = (float *)(ws + L.part), *lossb = (float *)(ws + L.lossb);
+    K *msplit = (K *)(ws + L.msplit), *ssplit = (K *)(ws + L.ssplit), *chosen = (K *)(ws + L.chosen);
+    K *hold = (K *)(ws + L.hold);
+    HS_LAUNCH(k_zero_words, 1, 256, stream, (uint32_t *)lctl, (uint32_t)(sizeof(LearnCtl) / 4));
+    // sample draws: the training sample from splitmix64(seed), the
+    // held-out sample from splitmix64(seed + 1), the weights from
+    // splitmix64(seed + 2)
+    HS_LAUNCH(k_ls_sample<F>, (P.m + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed, P.m, smp);
+    HS_LAUNCH(k_ls_holdout<F>, (P.h + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed + 1, P.h, hold);
+    const Layout S = make_layout<K>(op_of<F>(), P.m, 1, T);
+    int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
+    if (rc) return rc;
+    HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl);
+    const uint32_t gblk = (P.m + 255) / 256;
+    if (P.mode != JUDGE_SAMPLE) {
+        HS_LAUNCH(k_mlp_init, (MLP_NP + 255) / 256, 256, stream, par, mom, vel, P.seed + 2);
+        for (int t = 1; t <= P.steps; ++t) {
+            const bool last = t == P.steps;
+            HS_LAUNCH(k_mlp_grad, gblk, 256, stream, par, z, y, P.m, part, lossb);
+            HS_LAUNCH(k_mlp_update, MLP_UPDATE_GRID, 256, stream, par, mom, vel, part, gblk, t, P.lr,
+                      (float *)nullptr, lossb, last ? lossb + gblk : (float *)nullptr, P.m);
+        }
+        HS_LAUNCH(k_ls_invert<F>, (NSPLIT * WAVE + 255) / 256, 256, stream, par, lctl, msplit);
+    }
+    HS_LAUNCH(k_ls_judge<K>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode, counts_out);
+    return HS_OK;
+}
+
 // graph_levels > 0 (graph plans): record that many per-level launches (a
 // level with an empty list costs three empty launches) before the
 // persistent driver, which finishes whatever levels remain.
 template <int F>
 int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const int64_t *d_off, int64_t nseg,
-              const hs_opts *o, const LearnParams &P, hs_stats *st, hipStream_t stream, int graph_levels = 0)
+              const hs_opts *o, const LearnParams &P, hs_stats *st, hipStream_t stream, int graph_levels)
 {
     using K = typename KeyOf<F>::type;
     const uint32_t T = local_limit<K>(o);
@@ -491,37 +538,12 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     if (learned) {
         // ---- learned splitters and the multiway pass
         lctl = (LearnCtl *)(ws + L.lctl);
-        Raw smp{ws + L.smp_k, has_vals<F>() ? (int32_t *)(ws + L.smp_v) : nullptr};
-        float *z = (float *)(ws + L.z), *y = (float *)(ws + L.y);
-        float *par = (float *)(ws + L.par), *mom = (float *)(ws + L.mom), *vel = (float *)(ws + L.vel);
-        float *part = (float *)(ws + L.part), *lossb = (float *)(ws + L.lossb);
-        K *msplit = (K *)(ws + L.msplit), *ssplit = (K *)(ws + L.ssplit), *chosen = (K *)(ws + L.chosen);
-        K *hold = (K *)(ws + L.hold);
+        K *chosen = (K *)(ws + L.chosen);
         uint32_t *hist = (uint32_t *)(ws + L.hist), *btot = (uint32_t *)(ws + L.btot);
         uint32_t *bstart = (uint32_t *)(ws + L.bstart);
         if (st) HS_HIP(hipEventRecord(lev[2], stream));
-        HS_LAUNCH(k_zero_words, 1, 256, stream, (uint32_t *)lctl, (uint32_t)(sizeof(LearnCtl) / 4));
-        // sample draws: the training sample from splitmix64(seed), the
-        // held-out sample from splitmix64(seed + 1), the weights from
-        // splitmix64(seed + 2)
-        HS_LAUNCH(k_ls_sample<F>, (P.m + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed, P.m, smp);
-        HS_LAUNCH(k_ls_holdout<F>, (P.h + 255) / 256, 256, stream, raw, (uint32_t)n, P.seed + 1, P.h, hold);
-        const Layout S = make_layout<K>(op_of<F>(), P.m, 1, T);
-        int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
+        int rc = learn_front<F>(d, ws, L, raw, n, T, o, P, stream, nullptr);
         if (rc) return rc;
-        HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl);
-        const uint32_t gblk = (P.m + 255) / 256;
-        if (P.mode != JUDGE_SAMPLE) {
-            HS_LAUNCH(k_mlp_init, (MLP_NP + 255) / 256, 256, stream, par, mom, vel, P.seed + 2);
-            for (int t = 1; t <= P.steps; ++t) {
-                const bool last = t == P.steps;
-                HS_LAUNCH(k_mlp_grad, gblk, 256, stream, par, z, y, P.m, part, lossb);
-                HS_LAUNCH(k_mlp_update, MLP_UPDATE_GRID, 256, stream, par, mom, vel, part, gblk, t, P.lr,
-                          (float *)nullptr, lossb, last ? lossb + gblk : (float *)nullptr, P.m);
-            }
-            HS_LAUNCH(k_ls_invert<F>, (NSPLIT * WAVE + 255) / 256, 256, stream, par, lctl, msplit);
-        }
-        HS_LAUNCH(k_ls_judge<K>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode);
         if (st) HS_HIP(hipEventRecord(lev[3], stream));
         uint32_t chunk = (uint32_t)(((uint64_t)n + MW_GMAX - 1) / MW_GMAX);
         const uint32_t cmin = (uint32_t)(((uint64_t)n + (uint64_t)d->ncu * 8 - 1) / ((uint64_t)d->ncu * 8));
@@ -999,8 +1021,15 @@ template <typename Fn> int with_format(int op, Fn &&fn)
 
 struct hs_plan {
     int device = 0;
+    int op = 0;
+    int64_t n = 0, nseg = 0;
+    hs_opts opts{};             // the knobs (tuned at the first replay when opts.autotune is set)
+    bool tuned = false;
+    int graph_levels = -1;      // per-level launches recorded before the persistent driver (-1: not yet known)
     void *ws = nullptr;
+    size_t ws_bytes = 0;
     size_t ctl_off = 0;
+    const void *bound_keys = nullptr, *bound_vals = nullptr, *bound_off = nullptr;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1207,7 +1236,7 @@ int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_l
     if ((rc = get_device(&d))) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) {
-        HS_HIP(hipMemsetAsync(d_count_le, 0, sizeof(int64_t), s));
+        HS_LAUNCH(k_zero_words, 1, 64, s, (uint32_t *)d_count_le, 2u);  // a kernel, not a memset node
         return HS_OK;
     }
     Layout L;
@@ -1248,7 +1277,7 @@ int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_l
         HS_LAUNCH((k_partition<FMT_I32, true, true>), g, PartCfg<uint32_t>::NT, s, ctl, 0, 0, segs, cur,
                   (const uint32_t *)nullptr, Raw{copy, nullptr}, (uint32_t *)nullptr, Raw{keys, nullptr}, L.cand_cap);
     }
-    HS_LAUNCH(k_write_count, 1, 64, s, cur, d_count_le);
+    HS_LAUNCH(k_write_count, 1, 64, s, ctl, cur, d_count_le);
     if (shared_ws) HS_HIP(hipEventRecord(d->last, s));
     return HS_OK;
 }
@@ -1412,9 +1441,64 @@ int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_splitte
                                                                d_start, nullptr, Raw{keys, nullptr});
         HS_LAUNCHED();
     } else {
-        HS_HIP(hipMemsetAsync(d_start, 0, (size_t)(2 * k + 2) * 4, s));  // no bucket has keys
+        HS_LAUNCH(k_zero_words, 1, 256, s, d_start, (uint32_t)(2 * k + 2));  // no bucket has keys
     }
     HS_HIP(hipEventRecord(d->last, s));
+    return HS_OK;
+}
+
+int hs_learn_debug_f64(const double *keys, int64_t n, const hs_opts *opts, float *d_params, uint64_t *d_model_split,
+                       uint64_t *d_sample_split, uint64_t *d_chosen, uint64_t *d_holdout, double *d_train_sorted,
+                       uint32_t *d_counts, hs_learn_report *report, void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n < 1 || !keys) return fail(HS_EINVAL, "the learned front end needs n >= 1 keys");
+    if (!d_params || !d_model_split || !d_sample_split || !d_chosen || !d_holdout || !d_train_sorted || !d_counts ||
+        !report)
+        return fail(HS_EINVAL, "NULL output pointer");
+    hs_opts o = opts ? *opts : hs_opts{};
+    o.method = HS_METHOD_LEARNED;
+    if ((rc = check_learn(&o))) return rc;
+    if (o.inplace) return fail(HS_EINVAL, "inplace is not offered with the learned method");
+    DevState *d;
+    if ((rc = get_device(&d))) return rc;
+    const LearnParams P = learn_params(&o, n, HS_OP_SORT_F64);
+    const uint32_t T = local_limit<uint64_t>(&o);
+    const Layout L = make_layout<uint64_t>(HS_OP_SORT_F64, n, 1, T, P);
+    std::lock_guard<std::mutex> lk(d->mu);
+    char *ws = nullptr;
+    if ((rc = bind_workspace(d, &o, L, &ws))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool shared_ws = !o.workspace;
+    if (shared_ws) HS_HIP(hipStreamWaitEvent(s, d->last, 0));
+    rc = learn_front<FMT_F64>(d, ws, L, Raw{(void *)keys, nullptr}, n, T, &o, P, s, d_counts);
+    if (rc) return rc;
+    HS_HIP(hipMemcpyAsync(d_params, ws + L.par, MLP_NP * 4, hipMemcpyDeviceToDevice, s));
+    HS_HIP(hipMemcpyAsync(d_model_split, ws + L.msplit, NSPLIT * 8, hipMemcpyDeviceToDevice, s));
+    HS_HIP(hipMemcpyAsync(d_sample_split, ws + L.ssplit, NSPLIT * 8, hipMemcpyDeviceToDevice, s));
+    HS_HIP(hipMemcpyAsync(d_chosen, ws + L.chosen, NSPLIT * 8, hipMemcpyDeviceToDevice, s));
+    HS_HIP(hipMemcpyAsync(d_holdout, ws + L.hold, (size_t)P.h * 8, hipMemcpyDeviceToDevice, s));
+    HS_HIP(hipMemcpyAsync(d_train_sorted, ws + L.smp_k, (size_t)P.m * 8, hipMemcpyDeviceToDevice, s));
+    HS_HIP(hipMemcpyAsync(d->h_lctl, ws + L.lctl, sizeof(LearnCtl), hipMemcpyDeviceToHost, s));
+    float loss = 0.f;
+    if (P.mode != JUDGE_SAMPLE && P.steps > 0)
+        HS_HIP(hipMemcpyAsync(&loss, (float *)(ws + L.lossb) + (P.m + 255) / 256, 4, hipMemcpyDeviceToHost, s));
+    HS_HIP(hipStreamSynchronize(s));
+    if (shared_ws) HS_HIP(hipEventRecord(d->last, s));
+    const LearnCtl &lc = *d->h_lctl;
+    *report = hs_learn_report{};
+    report->mu = lc.mu;
+    report->sd = lc.sd;
+    report->smin = lc.smin;
+    report->smax = lc.smax;
+    report->m = (int32_t)P.m;
+    report->h = (int32_t)P.h;
+    report->k = (int32_t)lc.k;
+    report->use_model = (int32_t)lc.use_model;
+    report->model_imbalance = lc.model_imb;
+    report->sample_imbalance = lc.sample_imb;
+    report->final_loss = loss;
     return HS_OK;
 }
 
@@ -1443,13 +1527,15 @@ int hs_autotune(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_o
     });
 }
 
-int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *d_offsets, int64_t nseg,
-                   const hs_opts *opts, hs_plan **plan)
+int hs_plan_create(int op, int64_t n, int64_t nseg, const hs_opts *opts, hs_plan **plan)
 {
     if (!plan) return fail(HS_EINVAL, "plan is NULL");
     *plan = nullptr;
-    int rc = check_sort_args(op, keys, vals, n, d_offsets, nseg);
+    // the buffers are bound per replay; check the sizes with placeholders
+    static const char probe[1] = {0};
+    int rc = check_sort_args(op, probe, (const int32_t *)(probe + 0), 0, (const int64_t *)probe, nseg);
     if (rc) return rc;
+    if ((rc = check_n(n))) return rc;
     if ((rc = check_learn(opts))) return rc;
     if (opts && opts->inplace) return fail(HS_EINVAL, "in-place levels cannot be captured into a graph");
     if (opts && opts->driver == HS_DRIVER_HOST)
@@ -1459,29 +1545,21 @@ int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *
     if ((rc = get_device(&d))) return rc;
     hs_plan *p = new hs_plan();
     HS_HIP(hipGetDevice(&p->device));
+    p->op = op;
+    p->n = n;
+    p->nseg = is_seg(op) ? nseg : 0;
+    p->opts = opts ? *opts : hs_opts{};
+    p->opts.driver = HS_DRIVER_PERSISTENT;
     if (n < 2 || (is_seg(op) && nseg == 0)) {  // nothing to sort: an empty plan
         *plan = p;
         return HS_OK;
     }
-    const int64_t *off = is_seg(op) ? d_offsets : nullptr;
-    hs_opts o = opts ? *opts : hs_opts{};
-    o.driver = HS_DRIVER_PERSISTENT;
-    if (o.autotune) {
-        hs_opts tuned;
-        rc = with_format(op, [&](auto fmt) {
-            return autotune_impl<decltype(fmt)::value>(d, op, Raw{keys, vals}, n, off, nseg, &o, &tuned, nullptr,
-                                                       nullptr);
-        });
-        if (rc) {
-            plan_release(p);
-            return rc;
-        }
-        o = tuned;
-        o.autotune = 0;
-        o.driver = HS_DRIVER_PERSISTENT;
-    }
+    // The workspace is sized for every on-chip limit the tuner may pick
+    // (a smaller limit means more segments per level).
+    hs_opts lo = p->opts;
+    if (lo.autotune) lo.local_T = 2048;
     Layout L;
-    if ((rc = layout_for(op, n, nseg, &o, &L))) {
+    if ((rc = layout_for(op, n, p->nseg, &lo, &L))) {
         plan_release(p);
         return rc;
     }
@@ -1491,62 +1569,130 @@ int hs_plan_create(int op, void *keys, int32_t *vals, int64_t n, const int64_t *
         plan_release(p);
         return fail(HS_ENOMEM, "hipMalloc of %zu plan workspace bytes failed", L.total);
     }
-    o.workspace = p->ws;
-    o.workspace_bytes = L.total;
-    p->ctl_off = L.ctl;
+    p->ws_bytes = L.total;
     if (hipHostMalloc((void **)&p->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
         plan_release(p);
         return fail(HS_EHIP, "plan set-up failed");
     }
-    HS_HIP(hipDeviceSynchronize());  // the autotuner's work and the workspace are ready
-    // Per-level launches recorded before the persistent driver: the levels
-    // the largest segment needs with balanced splits, plus two (a level with
-    // an empty list costs three empty launches; the persistent driver takes
-    // whatever remains).
-    int graph_levels = 0;
-    {
-        const bool w32 = op == HS_OP_SORT_I32 || op == HS_OP_SORT_U32 || op == HS_OP_SORT_SEGMENTED_I32;
-        const uint32_t T = w32 ? local_limit<uint32_t>(&o)
-                         : op == HS_OP_SORT_KV_F64 ? local_limit<u128>(&o) : local_limit<uint64_t>(&o);
-        uint64_t biggest = (uint64_t)n;
-        if (is_seg(op)) {
-            std::vector<int64_t> h_off((size_t)nseg + 1);
-            HS_HIP(hipMemcpy(h_off.data(), d_offsets, h_off.size() * 8, hipMemcpyDeviceToHost));
-            biggest = 0;
-            for (int64_t i = 0; i < nseg; ++i)
-                if (h_off[i + 1] - h_off[i] > (int64_t)biggest) biggest = (uint64_t)(h_off[i + 1] - h_off[i]);
-        } else if (o.method == HS_METHOD_LEARNED) {
-            biggest = (uint64_t)n / 64;  // buckets of the multiway pass hold about n/256 keys
-        }
-        graph_levels = biggest > T ? levels_for(biggest, T) + 1 : 0;
-    }
-    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        plan_release(p);
-        return fail(HS_EHIP, "hipStreamBeginCapture failed");
-    }
-    rc = with_format(op, [&](auto fmt) {
-        return run_sort_tuned<decltype(fmt)::value>(d, Raw{keys, vals}, n, off, nseg, &o, nullptr, p->cap,
-                                                    graph_levels);
-    });
-    const hipError_t ec = hipStreamEndCapture(p->cap, &p->graph);
-    if (rc == HS_OK && ec != hipSuccess) rc = fail(HS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
-    if (rc == HS_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
-        rc = fail(HS_EHIP, "hipGraphInstantiate failed");
-    if (rc) {
-        (void)hipGetLastError();
-        plan_release(p);
-        return rc;
-    }
     *plan = p;
     return HS_OK;
 }
 
-int hs_plan_exec(hs_plan *plan, void *stream)
+namespace {
+
+// Record the plan's sort of the given buffers into a graph and make it the
+// plan's executable graph: the first time by instantiating it, later by
+// updating the executable graph in place (same launches, new arguments).
+// The first recording also tunes the knobs (opts.autotune) and counts the
+// per-level launches to record from the largest segment; both read the
+// buffers, so the caller's stream is synchronized first.
+int plan_record(DevState *d, hs_plan *p, void *keys, int32_t *vals, const int64_t *d_off, hipStream_t stream)
+{
+    const int64_t *off = is_seg(p->op) ? d_off : nullptr;
+    if (p->graph_levels < 0) {
+        HS_HIP(hipStreamSynchronize(stream));
+        if (p->opts.autotune && !p->tuned) {
+            hs_opts tuned;
+            int rc = with_format(p->op, [&](auto fmt) {
+                return autotune_impl<decltype(fmt)::value>(d, p->op, Raw{keys, vals}, p->n, off, p->nseg, &p->opts,
+                                                           &tuned, nullptr, nullptr);
+            });
+            if (rc) return rc;
+            tuned.autotune = 0;
+            tuned.driver = HS_DRIVER_PERSISTENT;
+            tuned.workspace = nullptr;
+            tuned.workspace_bytes = 0;
+            p->opts = tuned;
+            p->tuned = true;
+        }
+        // Per-level launches recorded before the persistent driver: the
+        // levels the largest segment needs with balanced splits, plus two (a
+        // level with an empty list costs three empty launches; the
+        // persistent driver takes whatever remains).
+        const int op = p->op;
+        const bool w32 = op == HS_OP_SORT_I32 || op == HS_OP_SORT_U32 || op == HS_OP_SORT_SEGMENTED_I32;
+        const uint32_t T = w32 ? local_limit<uint32_t>(&p->opts)
+                         : op == HS_OP_SORT_KV_F64 ? local_limit<u128>(&p->opts) : local_limit<uint64_t>(&p->opts);
+        uint64_t biggest = (uint64_t)p->n;
+        if (is_seg(op)) {
+            std::vector<int64_t> h_off((size_t)p->nseg + 1);
+            HS_HIP(hipMemcpy(h_off.data(), d_off, h_off.size() * 8, hipMemcpyDeviceToHost));
+            biggest = 0;
+            for (int64_t i = 0; i < p->nseg; ++i)
+                if (h_off[i + 1] - h_off[i] > (int64_t)biggest) biggest = (uint64_t)(h_off[i + 1] - h_off[i]);
+        } else if (p->opts.method == HS_METHOD_LEARNED) {
+            biggest = (uint64_t)p->n / 64;  // buckets of the multiway pass hold about n/256 keys
+        }
+        p->graph_levels = biggest > T ? levels_for(biggest, T) + 1 : 0;
+    }
+    hs_opts o = p->opts;
+    o.workspace = p->ws;
+    o.workspace_bytes = p->ws_bytes;
+    Layout L;
+    int rc = layout_for(p->op, p->n, p->nseg, &o, &L);
+    if (rc) return rc;
+    p->ctl_off = L.ctl;
+    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(HS_EHIP, "hipStreamBeginCapture failed");
+    rc = with_format(p->op, [&](auto fmt) {
+        return run_sort_tuned<decltype(fmt)::value>(d, Raw{keys, vals}, p->n, off, p->nseg, &o, nullptr, p->cap,
+                                                    p->graph_levels);
+    });
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->cap, &g);
+    if (rc == HS_OK && ec != hipSuccess) rc = fail(HS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    if (rc) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    bool updated = false;
+    if (p->exec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        updated = hipGraphExecUpdate(p->exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(p->exec);
+            p->exec = nullptr;
+        }
+    }
+    if (!updated && hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        p->exec = nullptr;
+        (void)hipGraphDestroy(g);
+        return fail(HS_EHIP, "hipGraphInstantiate failed");
+    }
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph = g;
+    p->bound_keys = keys;
+    p->bound_vals = vals;
+    p->bound_off = off;
+    return HS_OK;
+}
+
+}  // namespace
+
+int hs_plan_exec(hs_plan *plan, void *keys, int32_t *vals, const int64_t *d_offsets, void *stream)
 {
     if (!plan) return fail(HS_EINVAL, "plan is NULL");
-    if (!plan->exec) return HS_OK;
-    HS_HIP(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    int rc = check_sort_args(plan->op, keys, vals, plan->n, d_offsets, plan->nseg);
+    if (rc) return rc;
+    if (plan->n < 2 || (is_seg(plan->op) && plan->nseg == 0)) return HS_OK;
+    int dev = 0;
+    HS_HIP(hipGetDevice(&dev));
+    if (dev != plan->device) return fail(HS_EINVAL, "the plan belongs to device %d, the current device is %d",
+                                         plan->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t *off = is_seg(plan->op) ? d_offsets : nullptr;
+    const int32_t *v = (plan->op == HS_OP_SORT_KV_I32 || plan->op == HS_OP_SORT_KV_F64) ? vals : nullptr;
+    if (!plan->exec || plan->bound_keys != keys || plan->bound_vals != v || plan->bound_off != off) {
+        DevState *d;
+        if ((rc = get_device(&d))) return rc;
+        if ((rc = plan_record(d, plan, keys, (int32_t *)v, off, s))) return rc;
+    }
+    HS_HIP(hipGraphLaunch(plan->exec, s));
     return HS_OK;
 }
 

@@ -161,19 +161,26 @@ def test_plan_argument_errors_before_launch(hs):
     L = hs.lib()
     p = ctypes.c_void_p(0x1000)
     out = ctypes.c_void_p()
-    assert L.hs_plan_create(hs.OP_SORT_I32, p, None, 10, None, 0, None, None) == -1
-    assert L.hs_plan_create(hs.OP_PARTITION_I32, p, None, 10, None, 0, None, ctypes.byref(out)) == -1
-    assert L.hs_plan_create(hs.OP_SORT_KV_I32, p, None, 10, None, 0, None, ctypes.byref(out)) == -1
-    assert L.hs_plan_create(hs.OP_SORT_SEGMENTED_I32, p, None, 10, None, 3, None, ctypes.byref(out)) == -1
+    assert L.hs_plan_create(hs.OP_SORT_I32, 10, 0, None, None) == -1
+    assert L.hs_plan_create(hs.OP_PARTITION_I32, 10, 0, None, ctypes.byref(out)) == -1
+    assert L.hs_plan_create(99, 10, 0, None, ctypes.byref(out)) == -1
+    assert L.hs_plan_create(hs.OP_SORT_I32, -1, 0, None, ctypes.byref(out)) == -1
+    assert L.hs_plan_create(hs.OP_SORT_I32, 1 << 31, 0, None, ctypes.byref(out)) == -1
+    assert L.hs_plan_create(hs.OP_SORT_SEGMENTED_I32, 10, -1, None, ctypes.byref(out)) == -1
     o = hs.Opts()
     o.driver = hs.DRIVER_HOST
-    assert L.hs_plan_create(hs.OP_SORT_I32, p, None, 10, None, 0, ctypes.byref(o), ctypes.byref(out)) == -1
+    assert L.hs_plan_create(hs.OP_SORT_I32, 10, 0, ctypes.byref(o), ctypes.byref(out)) == -1
     o = hs.Opts()
     o.leaf = 100
-    assert L.hs_plan_create(hs.OP_SORT_I32, p, None, 10, None, 0, ctypes.byref(o), ctypes.byref(out)) == -1
+    assert L.hs_plan_create(hs.OP_SORT_I32, 10, 0, ctypes.byref(o), ctypes.byref(out)) == -1
     o.leaf = 2048
-    assert L.hs_plan_create(hs.OP_SORT_I32, p, None, 10, None, 0, ctypes.byref(o), ctypes.byref(out)) == -1
-    assert L.hs_plan_exec(None, None) == -1
+    assert L.hs_plan_create(hs.OP_SORT_I32, 10, 0, ctypes.byref(o), ctypes.byref(out)) == -1
+    o = hs.Opts()
+    o.workspace = 0x1000
+    o.workspace_bytes = 1 << 20
+    assert L.hs_plan_create(hs.OP_SORT_I32, 10, 0, ctypes.byref(o), ctypes.byref(out)) == -1
+    assert "workspace" in _last(hs)
+    assert L.hs_plan_exec(None, p, None, None, None) == -1
     assert L.hs_plan_check(None, None) == -1
     L.hs_plan_destroy(None)
     assert L.hs_autotune(hs.OP_SORT_I32, p, None, 10, None, 0, None, None, None, None) == -1

@@ -1,7 +1,8 @@
 """Graph plans (hs_plan_*) and the autotuner, through the C ABI.
 
-A plan records one sort of fixed tensors into a HIP graph; every test
-replays it several times with fresh data, with eager work of the program's
+A plan records a sort of a fixed shape into a HIP graph (on the buffers of
+its first replay, recorded again when a replay names other buffers); every
+test replays it several times with fresh data, with eager work of the program's
 own (copies and an unrelated sort) and synchronizations between the
 replays, and checks every replay against the oracle.  The autotuner must
 leave its input unchanged, find every candidate's output identical, and
@@ -98,6 +99,52 @@ def test_plan_learned(hs, oracle_mod):
         plan.run()
         plan.check()
         assert np.array_equal(t.cpu().numpy().view(np.uint64), oracle_mod.sort_f64(x).view(np.uint64)), r
+
+
+@pytest.mark.parametrize("kind", ["i32", "f64", "kv", "seg"])
+def test_plan_on_other_buffers(hs, oracle_mod, kind):
+    """One plan sorts several tensor sets of its shape: A, B, A again (each
+    change of buffers records the graph again and updates it in place),
+    every replay bit-exact against the oracle."""
+    n = 300007
+    off = workloads.segment_offsets(400, 16, 1 << 12, seed=95).astype(np.int64) if kind == "seg" else None
+    if off is not None:
+        n = int(off[-1])
+    sets = []
+    for r in range(2):
+        if kind == "f64":
+            sets.append((torch.empty(n, dtype=torch.float64, device="cuda"), None))
+        else:
+            sets.append((torch.empty(n, dtype=torch.int32, device="cuda"),
+                         torch.empty(n, dtype=torch.int32, device="cuda") if kind == "kv" else None))
+    o = _gpu(off) if off is not None else None
+    o2 = o.clone() if o is not None else None
+    plan = hs.Plan(sets[0][0], vals=sets[0][1], offsets=o)
+    for r, which in enumerate([0, 1, 1, 0]):
+        k, v = sets[which]
+        if kind == "f64":
+            x = workloads.f64(n, "normal", seed=96 + r)
+        elif kind == "kv":
+            x, vals = workloads.kv_dup_i32(n, seed=96 + r, ndistinct=3000)
+            v.copy_(_gpu(vals))
+        else:
+            x = workloads.uniform_i32(n, seed=96 + r)
+        k.copy_(_gpu(x))
+        plan.run(k, vals=v, offsets=(o if which == 0 else o2))
+        plan.check()
+        got = k.cpu().numpy()
+        if kind == "f64":
+            assert np.array_equal(got.view(np.uint64), oracle_mod.sort_f64(x).view(np.uint64)), r
+        elif kind == "kv":
+            assert np.array_equal(got, oracle_mod.sort_kv_i32(x, vals)[0]), r
+            kv_index_check(x, got, v.cpu().numpy())
+        elif kind == "seg":
+            assert np.array_equal(got, oracle_mod.sort_segmented_i32(x, off)), r
+        else:
+            assert np.array_equal(got, oracle_mod.sort_i32(x)), r
+    with pytest.raises(ValueError):
+        plan.run(torch.empty(n + 1, dtype=sets[0][0].dtype, device="cuda"))
+    plan.close()
 
 
 def test_plan_rejects_host_driver(hs):

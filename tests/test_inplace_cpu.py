@@ -53,8 +53,7 @@ def test_inplace_refusals(hs):
         with pytest.raises(hs.HSortError, match=what):
             hs.workspace_size(hs.OP_SORT_F64, 1 << 20, opts=o)
     plan = p()
-    assert L.hs_plan_create(hs.OP_SORT_I32, p(0x1000), None, 1 << 20, None, 0, ctypes.byref(_ip(hs)),
-                            ctypes.byref(plan)) == -1
+    assert L.hs_plan_create(hs.OP_SORT_I32, 1 << 20, 0, ctypes.byref(_ip(hs)), ctypes.byref(plan)) == -1
     assert "graph" in L.hs_last_error().decode()
     best, rep = hs.Opts(), hs.TuneReport()
     assert L.hs_autotune(hs.OP_SORT_I32, p(0x1000), None, 1 << 20, None, 0, ctypes.byref(_ip(hs)),
