@@ -221,6 +221,24 @@ HS_API int hs_sort_kv_f64(double *keys, int32_t *vals, int64_t n, const hs_opts 
 HS_API int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_le,
                      const hs_opts *opts, void *stream);
 
+/* hs_sort_i32 for callers that cannot allocate memory: code being captured
+ * into a HIP graph, tight serving loops, harnesses that forbid hipMalloc.
+ * Same result as hs_sort_i32 with default options (it runs the same
+ * kernels), but its scratch memory is a static device array of the library
+ * (20 MiB per GPU, reserved when the library's code is loaded on the device
+ * and held until the process ends) instead of the cached workspace; the
+ * call makes no hipMalloc, hipFree or other allocating call (the first call
+ * on a device looks up the array's address there).  Limits and errors:
+ * n <= 2^22 keys (HS_EINVAL above), NULL keys with n > 0 (HS_EINVAL), not a
+ * gfx950 device (HS_EUNSUPPORTED), a kernel-reported error (HS_EINTERNAL).
+ * Every call on one GPU shares that GPU's array and starts by clearing what
+ * must start at zero; calls whose work overlaps on one GPU (other streams,
+ * other threads, or a graph replayed while a call runs) race on it and must
+ * be ordered by the caller.  While `stream` is being captured the sort runs
+ * its persistent level driver and nothing is read back (kernel-reported
+ * errors cannot be returned then). */
+HS_API int hs_sort_i32_noalloc(int32_t *keys, int64_t n, void *stream);
+
 /* Sort nseg independent int32 segments in place: segment i is
  * keys[off[i], off[i+1]) with the DEVICE array off[nseg+1], off[0] = 0,
  * non-decreasing, off[nseg] = n_total (the caller states n_total so that no

@@ -84,6 +84,7 @@ _SIGS = {
     "hs_argsort_i32": ([_P, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_argsort_f64": ([_P, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_partition_i32": ([_P, _I64, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+    "hs_sort_i32_noalloc": ([_P, _I64, _P], ctypes.c_int),
     "hs_sort_segmented_i32": ([_P, _I64, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_segmented_f64": ([_P, _I64, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_workspace_size": ([ctypes.c_int, _I64, _I64, _P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),

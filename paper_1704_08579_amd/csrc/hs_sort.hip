@@ -1019,6 +1019,64 @@ template <typename Fn> int with_format(int op, Fn &&fn)
 
 }  // namespace
 
+// ---------------------------------------------------------------- allocation-free sort
+
+// Scratch memory of hs_sort_i32_noalloc: a static device array, one copy per
+// GPU, held until the process ends.  It holds the workspace of an int32 sort
+// of up to NOALLOC_MAX_N keys (ping-pong buffer, level lists, tasks, control
+// block: about 4.3 bytes per key).  Host code must never pass `scratch`
+// itself to a kernel or a copy (in host code the name is a host-side
+// stand-in, not a device address): it uses the device address that
+// hipGetSymbolAddress returned on that device.
+namespace {
+constexpr int64_t NOALLOC_MAX_N = (int64_t)1 << 22;
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)20 << 20;
+}  // namespace
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+struct NoAllocDev {
+    bool ready = false;
+    void *ptr = nullptr;  // device address of `scratch` on this device
+    DevState st;          // device facts for the level driver (no pinned memory, no events)
+    Ctl h_ctl;            // host copy of the control block (static storage: nothing is allocated)
+    std::mutex mu;        // one call at a time per device (host side)
+};
+NoAllocDev g_noalloc[MAXDEV];
+std::mutex g_noalloc_probe_mu;
+
+// Per device, once, with that device current: check the architecture and
+// look up the address of the device's copy of `scratch`.
+int noalloc_device(NoAllocDev **out)
+{
+    int dev = 0;
+    HS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAXDEV) return fail(HS_EUNSUPPORTED, "device index %d out of range", dev);
+    NoAllocDev &nd = g_noalloc[dev];
+    std::lock_guard<std::mutex> lk(g_noalloc_probe_mu);
+    if (!nd.ready) {
+        hipDeviceProp_t prop;
+        HS_HIP(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(HS_EUNSUPPORTED, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HS_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        nd.ptr = p;
+        nd.st.probed = true;
+        nd.st.supported = true;
+        nd.st.ncu = prop.multiProcessorCount;
+        nd.st.h_ctl = &nd.h_ctl;
+        nd.ready = true;
+    }
+    *out = &nd;
+    return HS_OK;
+}
+
+}  // namespace
+
 struct hs_plan {
     int device = 0;
     int op = 0;
@@ -1280,6 +1338,26 @@ int hs_partition_i32(int32_t *keys, int64_t n, int32_t pivot, int64_t *d_count_l
     HS_LAUNCH(k_write_count, 1, 64, s, ctl, cur, d_count_le);
     if (shared_ws) HS_HIP(hipEventRecord(d->last, s));
     return HS_OK;
+}
+
+int hs_sort_i32_noalloc(int32_t *keys, int64_t n, void *stream)
+{
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (n > NOALLOC_MAX_N)
+        return fail(HS_EINVAL, "n = %lld exceeds the %lld keys the static scratch of hs_sort_i32_noalloc holds",
+                    (long long)n, (long long)NOALLOC_MAX_N);
+    if (n > 0 && !keys) return fail(HS_EINVAL, "keys is NULL");
+    if (n < 2) return HS_OK;
+    NoAllocDev *nd;
+    if ((rc = noalloc_device(&nd))) return rc;
+    const Layout L = make_layout<uint32_t>(HS_OP_SORT_I32, n, 1, (uint32_t)LocalCfg<uint32_t>::T);
+    if (L.total > NOALLOC_SCRATCH_BYTES)
+        return fail(HS_EINTERNAL, "a sort of %lld keys needs %zu scratch bytes, %zu are reserved", (long long)n,
+                    L.total, NOALLOC_SCRATCH_BYTES);
+    std::lock_guard<std::mutex> lk(nd->mu);
+    return sort_body<FMT_I32>(&nd->st, (char *)nd->ptr, L, Raw{keys, nullptr}, n, nullptr, 0, nullptr,
+                              LearnParams(), nullptr, (hipStream_t)stream);
 }
 
 // ---- the learned method's kernels on their own

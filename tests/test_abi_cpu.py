@@ -186,3 +186,13 @@ def test_plan_argument_errors_before_launch(hs):
     assert L.hs_autotune(hs.OP_SORT_I32, p, None, 10, None, 0, None, None, None, None) == -1
     best = hs.Opts()
     assert L.hs_autotune(99, p, None, 10, None, 0, None, ctypes.byref(best), None, None) == -1
+
+
+def test_noalloc_rejects_sizes_beyond_its_scratch(hs):
+    """hs_sort_i32_noalloc checks n against its static scratch before it
+    touches a device."""
+    L = hs.lib()
+    assert L.hs_sort_i32_noalloc(ctypes.c_void_p(0x1000), (1 << 22) + 1, None) == -1
+    assert "static scratch" in _last(hs)
+    assert L.hs_sort_i32_noalloc(None, 5, None) == -1
+    assert L.hs_sort_i32_noalloc(ctypes.c_void_p(0x1000), -1, None) == -1
