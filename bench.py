@@ -350,22 +350,32 @@ def summary(r):
     return d
 
 
+def partition_source_sha():
+    """sha256 of the source the partition pass is built from: the device
+    primitives, and the shared types, tile geometry and partition-pass
+    sections of the kernel header."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1704_08579_amd", "csrc")
+    dev = open(os.path.join(csrc, "hs_device.hpp")).read()
+    k = open(os.path.join(csrc, "hs_kernels.hpp")).read()
+    mark = "// ---------------------------------------------------------------- "
+    head = k[:k.index(mark + "grid barrier")]
+    part = k[k.index(mark + "partition pass"):k.index(mark + "finalize")]
+    return hashlib.sha256((dev + head + part).encode()).hexdigest()
+
+
 def measured_traffic(name, kernel):
     """HBM traffic per launch of the dominant kernel from the committed
     rocprofv3 --pmc summary for this workload, or None when there is none or
-    the kernel source has changed since the counters were taken."""
-    import hashlib
+    the kernel's source has changed since the counters were taken."""
     import re
     path = os.path.join(ROOT, "profiles", f"{kernel}_{name}.md")
-    src = os.path.join(ROOT, "paper_1704_08579_amd", "csrc", "hs_kernels.hpp")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    sha = re.search(r"^source_sha256: ([0-9a-f]+)", txt, re.M)
+    sha = re.search(r"^partition_source_sha256: ([0-9a-f]+)", txt, re.M)
     val = re.search(r"^traffic_bytes_per_launch: ([0-9]+)", txt, re.M)
-    if not sha or not val:
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != sha.group(1):
+    if not sha or not val or sha.group(1) != partition_source_sha():
         return None
     return int(val.group(1))
 
