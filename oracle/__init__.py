@@ -61,8 +61,6 @@ def lib() -> ctypes.CDLL:
             ("oracle_sort_segmented_i32", [_P, _P, _I64, _I64], _I64),
             ("oracle_sort_segmented_f64", [_P, _P, _I64, _I64], _I64),
             ("oracle_partition_le_i32", [_P, _I64, ctypes.c_int32], _I64),
-            ("oracle_simd_partition_i32", [_P, _I64, ctypes.c_int32, ctypes.c_int], _I64),
-            ("oracle_qs_appendix_i32", [_P, _I64, _P], None),
             ("oracle_bitonic_apply", [_P, _P, ctypes.c_int], None),
             ("oracle_bitonic_exhaustive_failures", [ctypes.c_int], _I64),
             ("oracle_bitonic_merger_failures", [ctypes.c_int], _I64),
@@ -194,19 +192,6 @@ def partition_le_i32(keys: np.ndarray, pivot: int):
     a = np.ascontiguousarray(keys, dtype=np.int32).copy()
     k = lib().oracle_partition_le_i32(_ptr(a), a.size, int(pivot))
     return a, int(k)
-
-
-def simd_partition_i32(keys: np.ndarray, pivot: int, vec_size: int = 16):
-    a = np.ascontiguousarray(keys, dtype=np.int32).copy()
-    k = lib().oracle_simd_partition_i32(_ptr(a), a.size, int(pivot), int(vec_size))
-    return a, int(k)
-
-
-def qs_appendix_i32(keys: np.ndarray):
-    a = np.ascontiguousarray(keys, dtype=np.int32).copy()
-    first = ctypes.c_int32(0)
-    lib().oracle_qs_appendix_i32(_ptr(a), a.size, ctypes.addressof(first))
-    return a, int(first.value)
 
 
 def bitonic_apply(keys: np.ndarray, vals: np.ndarray | None = None):

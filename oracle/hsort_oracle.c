@@ -17,10 +17,7 @@
  *   - padding of a partial network with the greatest key (Sec. III-A,
  *     "Sorting Small Arrays");
  *   - partition with "<= pivot" on the left and the boundary as the result
- *     (Sec. III-B, Algorithm 3), plus a scalar re-enactment of Algorithm 3's
- *     two-ended, free-space-balanced, compress-store scheme;
- *   - the appendix's scalar quicksort with the middle element as pivot and a
- *     strict "<" Lomuto partition (Appendix A);
+ *     (Sec. III-B, Algorithm 3's contract);
  *   - key/value pairs moved together with their keys (Sec. III-D).
  *
  * Readings taken where the paper is silent or ambiguous (all listed in the
@@ -379,100 +376,6 @@ int64_t oracle_partition_le_i32(int32_t *keys, int64_t n, int32_t pivot)
         }
     }
     return w;
-}
-
-/* Scalar re-enactment of Algorithm 3 with vectors of `vs` lanes.  One vector
- * is saved from each end before the steady state; each step loads a vector
- * from the side with less free room (so no store can reach unread data),
- * compares it with the pivot and "store-some"s the <= lanes at left_w and the
- * > lanes just below right_w.  Fewer than vs leftover elements are handled
- * with a cut mask, and the two saved vectors go last, when exactly 2*vs free
- * slots remain.  Arrays of at most 2*vs elements take the scalar path, as in
- * the paper.  Returns left_w. */
-static void part_vec(int32_t *arr, const int32_t *v, int cnt, int32_t pivot,
-                     int64_t *left_w, int64_t *right_w)
-{
-    int nlow = 0, nhigh = 0;
-    for (int l = 0; l < cnt; ++l) (v[l] <= pivot) ? ++nlow : ++nhigh;
-    int64_t lw = *left_w, rw = *right_w - nhigh;
-    int il = 0, ih = 0;
-    for (int l = 0; l < cnt; ++l) {
-        if (v[l] <= pivot)
-            arr[lw + il++] = v[l];
-        else
-            arr[rw + ih++] = v[l];
-    }
-    *left_w = lw + nlow;
-    *right_w = rw;
-}
-
-int64_t oracle_simd_partition_i32(int32_t *arr, int64_t length, int32_t pivot, int vs)
-{
-    if (vs < 1 || vs > 64) return -1;
-    if (length <= 2 * (int64_t)vs) return oracle_partition_le_i32(arr, length, pivot);
-    int32_t left_vec[64], right_vec[64], val[64];
-    int64_t left = 0, left_w = 0;
-    memcpy(left_vec, arr + left, (size_t)vs * sizeof(int32_t));
-    left += vs;
-    int64_t right = length - vs, right_w = length;
-    memcpy(right_vec, arr + right, (size_t)vs * sizeof(int32_t));
-    while (left + vs <= right) {
-        if (left - left_w <= right_w - right) {
-            memcpy(val, arr + left, (size_t)vs * sizeof(int32_t));
-            left += vs;
-        } else {
-            right -= vs;
-            memcpy(val, arr + right, (size_t)vs * sizeof(int32_t));
-        }
-        part_vec(arr, val, vs, pivot, &left_w, &right_w);
-    }
-    int remaining = (int)(right - left);
-    memcpy(val, arr + left, (size_t)remaining * sizeof(int32_t));
-    part_vec(arr, val, remaining, pivot, &left_w, &right_w);
-    part_vec(arr, left_vec, vs, pivot, &left_w, &right_w);
-    part_vec(arr, right_vec, vs, pivot, &left_w, &right_w);
-    return left_w;
-}
-
-/* Appendix A: scalar quicksort, middle element as pivot, strict "<" Lomuto
- * partition.  *first_pivot receives the first pivot value (if n >= 2). */
-static int64_t qs_partition(int32_t *a, int64_t left, int64_t right, int32_t pv)
-{
-    for (int64_t r = left; r <= right; ++r) {
-        if (a[r] < pv) {
-            int32_t t = a[r];
-            a[r] = a[left];
-            a[left] = t;
-            ++left;
-        }
-    }
-    return left;
-}
-
-static void qs_core(int32_t *a, int64_t left, int64_t right, int32_t *first, int *have)
-{
-    if (left < right) {
-        int64_t pidx = (right - left) / 2 + left;
-        int32_t t = a[pidx];
-        a[pidx] = a[right];
-        a[right] = t;
-        if (!*have) {
-            *first = a[right];
-            *have = 1;
-        }
-        int64_t b = qs_partition(a, left, right, a[right]);
-        t = a[b];
-        a[b] = a[right];
-        a[right] = t;
-        qs_core(a, left, b - 1, first, have);
-        qs_core(a, b + 1, right, first, have);
-    }
-}
-
-void oracle_qs_appendix_i32(int32_t *a, int64_t n, int32_t *first_pivot)
-{
-    int have = 0;
-    qs_core(a, 0, n - 1, first_pivot, &have);
 }
 
 /* ---- network checks (0-1 principle) ------------------------------------- */

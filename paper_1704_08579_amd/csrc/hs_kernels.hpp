@@ -342,6 +342,32 @@ __device__ K wave_pick_pivot(const Rd &rd, uint32_t b, uint32_t e, int rule, int
     return lane_bcast(x[0], WAVE / 2 - 1);
 }
 
+// Pivots of two ranges at once (the children of one segment): the sample
+// loads of both are issued before either network runs, so the two load
+// latencies overlap.  has0 / has1: whether the range needs a pivot.
+template <typename K, typename Rd>
+__device__ void wave_pick_pivot2(const Rd &rd, uint32_t b0, uint32_t e0, bool has0, uint32_t b1, uint32_t e1,
+                                 bool has1, int rule, int lane, K &p0, K &p1)
+{
+    const uint32_t m0 = e0 - b0, m1 = e1 - b1;
+    const bool s0 = has0 && rule == PIVOT_SAMPLE && m0 >= 256, s1 = has1 && rule == PIVOT_SAMPLE && m1 >= 256;
+    K x0[1], x1[1];
+    if (s0) x0[0] = rd(b0 + (uint32_t)(((uint64_t)(m0 - 1) * (uint32_t)lane) / (WAVE - 1)));
+    if (s1) x1[0] = rd(b1 + (uint32_t)(((uint64_t)(m1 - 1) * (uint32_t)lane) / (WAVE - 1)));
+    if (s0) {
+        bitonic_wave<1>(x0, lane);
+        p0 = lane_bcast(x0[0], WAVE / 2 - 1);
+    } else if (has0) {
+        p0 = pick_pivot<K>(rd, b0, e0, rule);
+    }
+    if (s1) {
+        bitonic_wave<1>(x1, lane);
+        p1 = lane_bcast(x1[0], WAVE / 2 - 1);
+    } else if (has1) {
+        p1 = pick_pivot<K>(rd, b1, e1, rule);
+    }
+}
+
 // ---------------------------------------------------------------- init
 
 // One array: the whole range becomes a level-0 segment, or a single local
@@ -806,6 +832,14 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
     unsigned long long lkeys = 0, fkeys = 0, ekeys = 0;
     uint32_t emax = 0;
 
+    // the record and cursor of the wave's next segment are loaded while the
+    // current one is processed
+    Seg<K> nx_sg{};
+    unsigned long long nx_c = 0;
+    if (w < nseg) {
+        nx_sg = segs[w];
+        nx_c = cur[(size_t)w * CUR_STRIDE];
+    }
     for (uint32_t step0 = 0; w + (uint64_t)step0 * nwaves < nseg; step0 += WAVE) {
         // parked items of this batch (lane k: batch step k)
         Seg<K> c0, c1;
@@ -817,9 +851,13 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
         for (uint32_t k = 0; k < (uint32_t)WAVE; ++k) {
             const uint64_t i64 = w + (uint64_t)(step0 + k) * nwaves;
             if (i64 >= nseg) break;
-            const uint32_t i = (uint32_t)i64;
-            const Seg<K> sg = segs[i];
-            const unsigned long long c = cur[(size_t)i * CUR_STRIDE];
+            const Seg<K> sg = nx_sg;
+            const unsigned long long c = nx_c;
+            const uint64_t n64 = i64 + nwaves;
+            if (n64 < nseg) {
+                nx_sg = segs[(uint32_t)n64];
+                nx_c = cur[(size_t)n64 * CUR_STRIDE];
+            }
             const uint32_t nle = (uint32_t)c, ngt = (uint32_t)(c >> 32);
             if (nle + ngt != sg.e - sg.b) {
                 if (lane == 0) atomicOr(&ctl->err, ERR_CURSOR);
@@ -831,6 +869,14 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
             const uint32_t cb[2] = {sg.b, mid}, ce[2] = {mid, sg.e};
             const uint32_t cfl[2] = {strict ? 0u : SEG_UB, sg.flags & SEG_UB};
             const K cub[2] = {sg.piv, sg.ub};
+            // children that become segments of the next level need a pivot
+            bool need[2];
+#pragma unroll
+            for (int side = 0; side < 2; ++side)
+                need[side] = ce[side] - cb[side] > T && !(side == 1 && strict);
+            K piv[2] = {K(0), K(0)};
+            if (need[0] || need[1])
+                wave_pick_pivot2<K>(rd, cb[0], ce[0], need[0], cb[1], ce[1], need[1], rule, lane, piv[0], piv[1]);
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
                 const uint32_t b = cb[side], e = ce[side], m = e - b;
@@ -873,7 +919,7 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
                 ch.e = e;
                 ch.tile0 = 0;
                 ch.ub = cub[side];
-                ch.piv = wave_pick_pivot<K>(rd, b, e, rule, lane);
+                ch.piv = piv[side];
                 ch.flags = cfl[side];
                 if ((ch.flags & SEG_UB) && ch.piv == ch.ub) ch.flags |= SEG_STRICT;
                 if (lane == (int)k) {

@@ -26,6 +26,10 @@ namespace {
 using namespace hs;
 
 constexpr int LMAX = 96;  // cap on global partition levels per call
+// k_finalize workgroups (256 threads) per compute unit: at the deepest levels
+// a level has tens of thousands of segments, one wave each, and every wave
+// waits on its samples' loads, so many waves pay.
+constexpr int FIN_BLOCKS_PER_CU = 8;
 
 thread_local std::string g_err;
 
@@ -579,7 +583,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_p, k_partition<F, false, false>, PartCfg<K>::NT, 0));
     if (occ_p < 1) occ_p = 1;
     const int part_grid = d->ncu * occ_p;
-    const int fin_grid = d->ncu * 2;
+    const int fin_grid = d->ncu * FIN_BLOCKS_PER_CU;
     uint64_t *ipmask = (uint64_t *)(ws + L.ipmask);
     uint32_t *iprow = (uint32_t *)(ws + L.iprow), *iptot = (uint32_t *)(ws + L.iptot), *ipgp = (uint32_t *)(ws + L.ipgp);
     auto launch_level = [&](int level) -> int {

@@ -29,15 +29,6 @@ def _golden(name):
 
 # ---------------------------------------------------------------- worked example
 
-def test_fig1_example_appendix_quicksort(oracle_mod):
-    rows = dict(r.split(":", 1) for r in _golden("fig1_quicksort_example.txt"))
-    inp = np.array(rows["input"].split(), dtype=np.int32)
-    out = np.array(rows["output"].split(), dtype=np.int32)
-    got, first = oracle_mod.qs_appendix_i32(inp)
-    assert np.array_equal(got, out)
-    assert first == int(rows["first_pivot"])
-
-
 def test_fig1_example_hybrid(oracle_mod):
     rows = dict(r.split(":", 1) for r in _golden("fig1_quicksort_example.txt"))
     inp = np.array(rows["input"].split(), dtype=np.int32)
@@ -66,15 +57,6 @@ def test_bruteforce_random_small(oracle_mod):
             g.integers(-(2 ** 31), 2 ** 31, n, dtype=np.int32)
         leaf = int(g.choice([1, 2, 4, 16, 256]))
         assert oracle_mod.sort_i32(a, leaf=leaf).tolist() == insertion_sort(a.tolist())
-
-
-def test_appendix_quicksort_bruteforce(oracle_mod):
-    g = workloads.rng(12)
-    for _ in range(200):
-        n = int(g.integers(1, 40))
-        a = g.integers(-20, 20, n).astype(np.int32)
-        got, _ = oracle_mod.qs_appendix_i32(a)
-        assert got.tolist() == insertion_sort(a.tolist())
 
 
 # ---------------------------------------------------------------- library special cases
@@ -160,24 +142,20 @@ def test_kv_bruteforce_ties(oracle_mod):
 
 # ---------------------------------------------------------------- partition
 
-@pytest.mark.parametrize("vec", [1, 8, 16, 64])
-def test_partition_contract(oracle_mod, vec):
+def test_partition_contract(oracle_mod):
     """Algorithm 3's contract: keys <= pivot land left, the result is their
-    count (closed form).  Both the one-pass oracle and the re-enactment of
-    Algorithm 3's two-ended compress-store scheme must satisfy it."""
-    g = workloads.rng(21 + vec)
-    for trial in range(300):
+    count (closed form), and the keys are permuted."""
+    g = workloads.rng(21)
+    for trial in range(1200):
         n = int(g.integers(0, 3000))
         a = g.integers(-50, 50, n).astype(np.int32) if trial % 3 else \
             g.integers(-(2 ** 31), 2 ** 31, n, dtype=np.int32)
         pivot = int(a[g.integers(0, n)]) if n and trial % 4 else int(g.integers(-60, 60))
         expect_k = int(np.count_nonzero(a <= pivot))
-        for fn in (lambda x: oracle_mod.partition_le_i32(x, pivot),
-                   lambda x: oracle_mod.simd_partition_i32(x, pivot, vec)):
-            out, k = fn(a)
-            assert k == expect_k
-            assert np.all(out[:k] <= pivot) and np.all(out[k:] > pivot)
-            assert np.array_equal(np.sort(out), np.sort(a))
+        out, k = oracle_mod.partition_le_i32(a, pivot)
+        assert k == expect_k
+        assert np.all(out[:k] <= pivot) and np.all(out[k:] > pivot)
+        assert np.array_equal(np.sort(out), np.sort(a))
 
 
 # ---------------------------------------------------------------- networks
