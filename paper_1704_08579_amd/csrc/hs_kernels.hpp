@@ -586,11 +586,19 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
     if (t >= tend) return;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
 
-    // segment of the first tile
+    // segment of the first tile: the last one with tile0 <= t, by a 64-way
+    // search (lane l probes lo + span*l/64; tile0 grows with the index, so the
+    // probes at or below t are a prefix of the lanes): three rounds of parallel
+    // loads at 2^15 segments instead of fifteen dependent ones
     uint32_t lo = 0, hi = nseg;
     while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (segs[mid].tile0 <= t) lo = mid; else hi = mid;
+        const uint32_t span = hi - lo;
+        const uint32_t probe = lo + (uint32_t)(((uint64_t)span * (uint32_t)lane) / WAVE);
+        const uint64_t m = __ballot(segs[probe].tile0 <= t);  // lane 0 probes lo: always set
+        const int last = 63 - __builtin_clzll(m);
+        const uint32_t nlo = lane_bcast(probe, last);
+        hi = last == WAVE - 1 ? hi : lane_bcast(probe, last + 1);
+        lo = nlo;
     }
     // the current segment and a look-ahead copy of the one after it (plain
     // conditional loads: a select between whole records would go through
@@ -797,6 +805,124 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partit
                                                raw_dst, blockIdx.x, gridDim.x, stage, wsum, sbase);
 }
 
+// ---------------------------------------------------------------- block-wide appends
+
+// What the waves of a workgroup park in one batch (lane k: up to two
+// segments for the next level and up to two tasks) is appended with one
+// atomic per list for the whole workgroup: the waves publish their counts in
+// LDS, one thread reserves the workgroup's slots, and every wave writes its
+// items at its share.  Every thread of the workgroup must call it.
+struct BlockFlushLds {
+    uint32_t cnt[32][4];   // per wave: segments, their tiles, on-chip tasks, small tasks
+    uint32_t base[32][4];  // per wave: first slot / tile of each
+};
+
+template <typename K>
+__device__ __forceinline__ void block_flush(const Seg<K> &a, bool ha, const Seg<K> &b, bool hb, const Task<K> &ta,
+                                            bool hta, bool sta, const Task<K> &tb, bool htb, bool stb,
+                                            Seg<K> *list, unsigned long long *curs, LevelCounts *lc, uint32_t cand_cap,
+                                            Task<K> *tasks, uint32_t task_cap, Ctl *ctl, unsigned long long &keys,
+                                            uint32_t &mx, BlockFlushLds &L)
+{
+    const int lane = lane_id(), wv = (int)(threadIdx.x / WAVE), nw = (int)(blockDim.x / WAVE);
+    const uint32_t nta = ha ? seg_tiles<K>(a.b, a.e) : 0u, ntb = hb ? seg_tiles<K>(b.b, b.e) : 0u;
+    const uint32_t c_s = (ha ? 1u : 0u) + (hb ? 1u : 0u), c_t = nta + ntb;
+    const uint32_t c_l = (hta && !sta ? 1u : 0u) + (htb && !stb ? 1u : 0u);
+    const uint32_t c_m = (hta && sta ? 1u : 0u) + (htb && stb ? 1u : 0u);
+    const uint32_t i_s = wave_incl_scan(c_s), i_t = wave_incl_scan(c_t);
+    const uint32_t i_l = wave_incl_scan(c_l), i_m = wave_incl_scan(c_m);
+    __syncthreads();  // the previous batch has read its bases
+    if (lane == WAVE - 1) {
+        L.cnt[wv][0] = i_s;
+        L.cnt[wv][1] = i_t;
+        L.cnt[wv][2] = i_l;
+        L.cnt[wv][3] = i_m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot[4] = {0, 0, 0, 0};
+        for (int w = 0; w < nw; ++w)
+            for (int j = 0; j < 4; ++j) {
+                L.base[w][j] = tot[j];
+                tot[j] += L.cnt[w][j];
+            }
+        uint32_t g[4] = {0, 0, 0, 0};
+        if (tot[0]) {
+            const unsigned long long r =
+                atomicAdd(&lc->segs_tiles, ((unsigned long long)tot[1] << 32) | (unsigned long long)tot[0]);
+            g[0] = (uint32_t)r;
+            g[1] = (uint32_t)(r >> 32);
+        }
+        if (tot[2]) g[2] = atomicAdd(&ctl->ntask, tot[2]);
+        if (tot[3]) g[3] = atomicAdd(&ctl->nsmall, tot[3]);
+        for (int w = 0; w < nw; ++w)
+            for (int j = 0; j < 4; ++j) L.base[w][j] += g[j];
+    }
+    __syncthreads();
+    uint32_t ks = L.base[wv][0] + i_s - c_s, kt = L.base[wv][1] + i_t - c_t;
+    uint32_t kl = L.base[wv][2] + i_l - c_l, km = L.base[wv][3] + i_m - c_m;
+    auto put_seg = [&](Seg<K> item, uint32_t ntiles) {
+        if (ks < cand_cap) {
+            item.tile0 = kt;
+            list[ks] = item;
+            curs[(size_t)ks * CUR_STRIDE] = 0ull;
+        } else {
+            atomicOr(&ctl->err, ERR_CAND_CAP);
+        }
+        ++ks;
+        kt += ntiles;
+        keys += item.e - item.b;
+        mx = max(mx, item.e - item.b);
+    };
+    if (ha) put_seg(a, nta);
+    if (hb) put_seg(b, ntb);
+    auto put_task = [&](const Task<K> &t, bool small) {
+        uint32_t &k = small ? km : kl;
+        if (k < task_cap) tasks[small ? task_cap - 1 - k : k] = t;
+        else atomicOr(&ctl->err, ERR_TASK_CAP);
+        ++k;
+    };
+    if (hta) put_task(ta, sta);
+    if (htb) put_task(tb, stb);
+}
+
+// The workgroup's sums of its waves' counters, added to the device with one
+// atomic each: ekeys and emax are per lane (the segments each lane emitted),
+// lkeys and fkeys are the same in every lane of a wave.  Every thread of the
+// workgroup must call it.
+__device__ __forceinline__ void block_totals(LevelCounts *lc, Ctl *ctl, unsigned long long ekeys, uint32_t emax,
+                                             unsigned long long lkeys, unsigned long long fkeys, BlockFlushLds &L)
+{
+    const int lane = lane_id(), wv = (int)(threadIdx.x / WAVE), nw = (int)(blockDim.x / WAVE);
+    __shared__ unsigned long long s_sum[32][3];
+    ekeys = wave_sum64(ekeys);
+    for (int d = 1; d < WAVE; d <<= 1) emax = max(emax, (uint32_t)__shfl_xor((int)emax, d));
+    __syncthreads();
+    if (lane == 0) {
+        s_sum[wv][0] = ekeys;
+        s_sum[wv][1] = lkeys;
+        s_sum[wv][2] = fkeys;
+        L.cnt[wv][0] = emax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long e = 0, l = 0, f = 0;
+        uint32_t m = 0;
+        for (int w = 0; w < nw; ++w) {
+            e += s_sum[w][0];
+            l += s_sum[w][1];
+            f += s_sum[w][2];
+            m = max(m, L.cnt[w][0]);
+        }
+        if (e) {
+            atomicAdd(&lc->keys, e);
+            atomicMax(&lc->max_seg, m);
+        }
+        if (l) atomicAdd(&ctl->local_keys, l);
+        if (f) atomicAdd(&ctl->fill_keys, f);
+    }
+}
+
 // ---------------------------------------------------------------- finalize
 
 // Split every segment of the level at its front cursor (the count of the <=
@@ -804,8 +930,10 @@ __global__ __launch_bounds__(PartCfg<typename KeyOf<F>::type>::NT) void k_partit
 // T becomes a segment of the next level with its own pivot; a smaller child
 // becomes a local task; the ">=" child of a strict split holds only keys
 // equal to the pivot and becomes a fill task.  Waves take segments in a
-// grid-stride loop, 64 at a time, and append what they emit with one atomic
-// per list and batch.
+// grid-stride loop, 64 at a time, and a workgroup appends what its waves
+// emit with one atomic per list and batch (at the deepest levels tens of
+// thousands of waves append to the same few counters, and atomics on one
+// address serialize).  Every thread of the workgroup must call it.
 //
 // Equal keys: a left child inherits its parent's pivot as an upper bound.
 // When a segment's pivot equals that bound, the segment is split with "<"
@@ -840,7 +968,11 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
         nx_sg = segs[w];
         nx_c = cur[(size_t)w * CUR_STRIDE];
     }
-    for (uint32_t step0 = 0; w + (uint64_t)step0 * nwaves < nseg; step0 += WAVE) {
+    __shared__ BlockFlushLds fl;
+    // the batch loop runs as long as the workgroup's first wave has work, so
+    // every wave of the workgroup takes part in every block-wide append
+    const uint32_t w_first = w - (uint32_t)(threadIdx.x / WAVE);
+    for (uint32_t step0 = 0; w_first + (uint64_t)step0 * nwaves < nseg; step0 += WAVE) {
         // parked items of this batch (lane k: batch step k)
         Seg<K> c0, c1;
         Task<K> t0, t1;
@@ -927,19 +1059,15 @@ __device__ __forceinline__ void finalize_level(Ctl *ctl, uint32_t nseg, const Se
                 }
             }
         }
-        wave_emit_segs2(c0, h_c0, c1, h_c1, cand, ncur, nlev, cand_cap, ctl, ekeys, emax);
-        wave_flush_task2(t0, h_t0, t0.kind == TASK_FILL || t0.e - t0.b <= leaf, t1, h_t1,
-                         t1.kind == TASK_FILL || t1.e - t1.b <= leaf, tasks, task_cap, ctl);
+        block_flush(c0, h_c0, c1, h_c1, t0, h_t0, t0.kind == TASK_FILL || t0.e - t0.b <= leaf, t1, h_t1,
+                    t1.kind == TASK_FILL || t1.e - t1.b <= leaf, cand, ncur, nlev, cand_cap, tasks, task_cap, ctl,
+                    ekeys, emax, fl);
     }
-    wave_emit_totals(nlev, ekeys, emax);
-    if (lane == 0) {
-        if (lkeys) atomicAdd(&ctl->local_keys, lkeys);
-        if (fkeys) atomicAdd(&ctl->fill_keys, fkeys);
-    }
+    block_totals(nlev, ctl, ekeys, emax, lkeys, fkeys, fl);
 }
 
 template <int F>
-__global__ __launch_bounds__(256) void k_finalize(Ctl *ctl, int par, const Seg<typename KeyOf<F>::type> *segs,
+__global__ __launch_bounds__(1024) void k_finalize(Ctl *ctl, int par, const Seg<typename KeyOf<F>::type> *segs,
                                                   const unsigned long long *cur,
                                                   Seg<typename KeyOf<F>::type> *cand, unsigned long long *ncur,
                                                   Task<typename KeyOf<F>::type> *tasks,
