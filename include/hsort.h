@@ -258,9 +258,14 @@ HS_API int hs_sort_segmented_f64(double *keys, int64_t n_total, const int64_t *d
  * Not in the paper, which partitions around one pivot at a time (Sec. III-B,
  * Algorithm 3).  A sample of 2^sample_log2 keys (drawn with splitmix64) is
  * sorted; an fp32 MLP 1-32-32-1 (tanh, tanh, sigmoid) is trained on the GPU
- * by these kernels to the sample's empirical CDF (input (asinh(x) - mu)/sd,
- * target (rank + 0.5)/m, mean squared error, full-batch Adam); 255 splitters
- * are read off the model by search, and a judge compares the model's bucket
+ * by these kernels to the sample's empirical CDF (input
+ * (asinh(x / s) - mu) / sd, with s the sample's 1% order statistic when the
+ * sample is positive there and spans more than three decades, likewise for
+ * negative samples, else its standard deviation; targets (rank + 0.5)/m at
+ * 4096 evenly spaced order statistics of the sorted sample; mean squared
+ * error; full-batch Adam, 100 steps at lr 3e-2 by default, all in one
+ * launch); 255 splitters are read off the model (for j = 1..255 the smallest
+ * sample key with F >= j/256), and a judge compares the model's bucket
  * imbalance on a held-out sample with that of the sample's order statistics
  * (the sampled-pivot fallback), keeping the model unless it is more than
  * 1.25 times worse.  One multiway pass then splits the keys into 2k+1
@@ -305,10 +310,11 @@ HS_API int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_
  * (splitmix64(seed), with replacement) sorted by the plain method, the
  * held-out sample of 2^14 keys (splitmix64(seed + 1)), the model trained on
  * the sample's empirical CDF, its 255 splitters (for j = 1..255 the smallest
- * totalOrder key K with F(K) >= j/256, found by a 64-ary search in fp32,
- * before the running maximum), the sample's order statistics (the key of
- * rank floor(j * m / 256) of the sorted sample, j = 1..255), and the judge:
- * running maximum and de-duplication of the model's splitters,
+ * key of the sorted sample with F >= j/256, found by a 64-ary search over
+ * the sample's ranks in fp32, before the running maximum), the sample's
+ * order statistics (the key of rank floor(j * m / 256) of the sorted sample,
+ * j = 1..255), and the judge: running maximum and de-duplication of the
+ * model's splitters,
  * de-duplication of the order statistics, the bucket counts of both sets on
  * the held-out sample, their imbalance (largest non-equality bucket over
  * h/256) and the choice (the model unless its imbalance exceeds 1.25 times
@@ -334,7 +340,8 @@ HS_API int hs_multiway_partition_f64(double *keys, int64_t n, const uint64_t *d_
  * meaning, and the model imbalance is -1.  Returns once the work is done
  * (it reads the report back).  HS_EINVAL for n < 1 or a NULL pointer. */
 typedef struct hs_learn_report {
-    double mu, sd;           /* the model's input is (asinh(x) - mu) / sd */
+    double scale;            /* the feature's scale s */
+    double mu, sd;           /* the model's input is (asinh(x / s) - mu) / sd */
     uint64_t smin, smax;     /* totalOrder keys of the sample's smallest and largest key */
     int32_t m, h;            /* training and held-out sample sizes */
     int32_t k;               /* distinct splitters chosen */

@@ -73,12 +73,14 @@ def lib() -> ctypes.CDLL:
             ("oracle_mlp_forward", [_P, _P, _I64, _P], None),
             ("oracle_mlp_loss_grad", [_P, _P, _P, _I64, _P], ctypes.c_double),
             ("oracle_adam_step", [_P, _P, _P, _P, _I64, ctypes.c_double], None),
-            ("oracle_feature_stats", [_P, _I64, _P, _P], None),
+            ("oracle_feature_scale", [_P, _I64], ctypes.c_double),
+            ("oracle_feature_stats", [_P, _I64, ctypes.c_double, _P, _P], None),
+            ("oracle_training_points", [_I64, _P], _I64),
             ("oracle_mlp_train", [ctypes.c_uint64, _P, _P, _I64, _I64, ctypes.c_double, _P, _P], None),
-            ("oracle_invert_one_f64", [_P, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
-                                       ctypes.c_double], ctypes.c_uint64),
-            ("oracle_invert_f64", [_P, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
-                                   ctypes.c_int, _P], None),
+            ("oracle_invert_one_f64", [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _I64,
+                                       ctypes.c_double], _I64),
+            ("oracle_invert_f64", [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _I64, ctypes.c_int,
+                                   _P], None),
             ("oracle_dedupe", [_P, _I64, _P], _I64),
             ("oracle_bucket_hist", [_P, _I64, _P, _I64, _P], None),
             ("oracle_keys_f64", [_P, _I64, _P], None),
@@ -265,12 +267,26 @@ def adam_step(p, mom, vel, grad, t: int, lr: float):
     lib().oracle_adam_step(_ptr(p), _ptr(mom), _ptr(vel), _ptr(g), int(t), float(lr))
 
 
-def feature_stats(x):
+def feature_scale(sorted_x) -> float:
+    """Scale s of the model's feature asinh(x / s), from the sorted sample."""
+    x = np.ascontiguousarray(sorted_x, dtype=np.float64)
+    return float(lib().oracle_feature_scale(_ptr(x), x.size))
+
+
+def feature_stats(x, s: float = 1.0):
+    """Mean and population standard deviation of asinh(x / s)."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     mu = ctypes.c_double()
     sd = ctypes.c_double()
-    lib().oracle_feature_stats(_ptr(x), x.size, ctypes.addressof(mu), ctypes.addressof(sd))
+    lib().oracle_feature_stats(_ptr(x), x.size, float(s), ctypes.addressof(mu), ctypes.addressof(sd))
     return mu.value, sd.value
+
+
+def training_points(m: int) -> np.ndarray:
+    """Ranks of the training set in a sorted sample of m keys."""
+    r = np.empty(min(m, 4096), dtype=np.int64)
+    nt = lib().oracle_training_points(m, _ptr(r))
+    return r[:nt]
 
 
 def mlp_train(seed: int, z, y, steps: int, lr: float):
@@ -282,17 +298,22 @@ def mlp_train(seed: int, z, y, steps: int, lr: float):
     return p, losses
 
 
-def invert_f64(p, mu: float, sd: float, kmin: int, kmax: int, nb: int = 256) -> np.ndarray:
+def invert_f64(p, s: float, mu: float, sd: float, sorted_keys, nb: int = 256) -> np.ndarray:
+    """Splitters: for j = 1..nb-1 the smallest key of the sorted sample (order
+    words) with F >= j/nb, then the running maximum."""
     p = np.ascontiguousarray(p, dtype=np.float64)
+    sk = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
     out = np.empty(nb - 1, dtype=np.uint64)
-    lib().oracle_invert_f64(_ptr(p), mu, sd, kmin, kmax, nb, _ptr(out))
+    lib().oracle_invert_f64(_ptr(p), s, mu, sd, _ptr(sk), sk.size, nb, _ptr(out))
     return out
 
 
-def invert_one_f64(p, mu: float, sd: float, kmin: int, kmax: int, q: float) -> int:
-    """One splitter before the running maximum: the bisection's crossing of q."""
+def invert_one_f64(p, s: float, mu: float, sd: float, sorted_keys, q: float) -> int:
+    """Rank of one splitter before the running maximum (the bisection's
+    crossing of q over the sorted sample)."""
     p = np.ascontiguousarray(p, dtype=np.float64)
-    return int(lib().oracle_invert_one_f64(_ptr(p), mu, sd, kmin, kmax, q))
+    sk = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
+    return int(lib().oracle_invert_one_f64(_ptr(p), s, mu, sd, _ptr(sk), sk.size, q))
 
 
 def dedupe(s) -> np.ndarray:

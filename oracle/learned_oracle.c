@@ -9,9 +9,19 @@
  * readings are listed in the repository's design notes:
  *   - sample: m indices i_k = floor(r_k * n / 2^64) where r_k is the k-th
  *     output of splitmix64 seeded with `seed` (Steele, Lea, Flood 2014);
- *   - feature z = (asinh(x) - mu) / sd with mu, sd the mean and (population)
- *     standard deviation of asinh(x) over the sample; target of the sample
- *     key of rank j (0-based, ascending) is (j + 0.5) / m;
+ *   - feature z = (asinh(x / s) - mu) / sd with mu, sd the mean and
+ *     (population) standard deviation of asinh(x / s) over the sample; the
+ *     scale s comes from the sorted sample: with a = its order statistic of
+ *     rank floor(0.01 m) and b that of rank floor(0.99 m), s = a when the
+ *     sample is positive there and spans more than three decades (a > 0 and
+ *     b / a > 1000), s = -b when it is negative there and spans more than
+ *     three decades (b < 0 and a / b > 1000), else the sample's population
+ *     standard deviation (1 if that is not a positive finite number); a
+ *     quotient x / s beyond the largest double is clamped to it;
+ *   - training set: the ntrain = min(4096, m) sample keys of rank
+ *     floor(k m / ntrain) + floor(m / (2 ntrain)), k = 0 .. ntrain - 1 (evenly
+ *     spaced order statistics); target of the sample key of rank j (0-based,
+ *     ascending) is (j + 0.5) / m;
  *   - model: h1 = tanh(W1 z + b1), h2 = tanh(W2 h1 + b2),
  *     F(z) = sigmoid(w3 . h2 + b3); 1153 parameters laid out as
  *     [W1(32) b1(32) W2(32x32, row = output unit) b2(32) w3(32) b3(1)];
@@ -19,9 +29,11 @@
  *     beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and bias correction (Kingma & Ba);
  *   - init: Xavier-uniform weights U(-a, a), a = sqrt(6 / (fan_in + fan_out)),
  *     from splitmix64 (53-bit uniforms), biases zero;
- *   - splitter j (1 <= j < nb): the smallest order key K in [kmin, kmax] with
- *     F(value(K)) >= j / nb, by bisection over the integers; then a running
- *     maximum and de-duplication give distinct splitters d_0 < ... < d_{k-1};
+ *   - splitter j (1 <= j < nb): the smallest key t of the sorted sample with
+ *     F(value(t)) >= j / nb (the largest sample key when there is none), by
+ *     bisection over the sample's ranks; then a running maximum and
+ *     de-duplication give distinct splitters d_0 < ... < d_{k-1} (a run of
+ *     equal sample keys yields one splitter, and so an equality bucket);
  *   - buckets: a key x with r = #{d_i < x} falls in bucket 2r + 1 if
  *     d_r == x (an equality bucket: every key in it is equal) and in bucket
  *     2r otherwise; 2k + 1 buckets.
@@ -156,19 +168,51 @@ void oracle_adam_step(double *p, double *mom, double *vel, const double *grad, i
     }
 }
 
-/* Mean and population standard deviation of asinh(x) over the sample. */
-void oracle_feature_stats(const double *x, int64_t m, double *mu, double *sd)
+/* asinh(x / s), the quotient clamped to the finite doubles. */
+static double feat(double x, double s)
 {
+    double t = x / s;
+    if (t > 1.7976931348623157e308) t = 1.7976931348623157e308;
+    if (t < -1.7976931348623157e308) t = -1.7976931348623157e308;
+    return asinh(t);
+}
+
+/* Scale s of the feature from the sorted sample xs[0..m) (see above). */
+double oracle_feature_scale(const double *xs, int64_t m)
+{
+    const double a = xs[(int64_t)(0.01 * (double)m)], b = xs[(int64_t)(0.99 * (double)m)];
+    if (a > 0.0 && b / a > 1000.0) return a;
+    if (b < 0.0 && a / b > 1000.0) return -b;
     double s = 0.0;
-    for (int64_t k = 0; k < m; ++k) s += asinh(x[k]);
+    for (int64_t k = 0; k < m; ++k) s += xs[k];
     const double mean = s / (double)m;
     double v = 0.0;
+    for (int64_t k = 0; k < m; ++k) v += (xs[k] - mean) * (xs[k] - mean);
+    const double sd = sqrt(v / (double)m);
+    return (sd > 0.0 && sd <= 1.7976931348623157e308) ? sd : 1.0;
+}
+
+/* Mean and population standard deviation of asinh(x / s) over the sample. */
+void oracle_feature_stats(const double *x, int64_t m, double s, double *mu, double *sd)
+{
+    double sum = 0.0;
+    for (int64_t k = 0; k < m; ++k) sum += feat(x[k], s);
+    const double mean = sum / (double)m;
+    double v = 0.0;
     for (int64_t k = 0; k < m; ++k) {
-        const double d = asinh(x[k]) - mean;
+        const double d = feat(x[k], s) - mean;
         v += d * d;
     }
     *mu = mean;
     *sd = sqrt(v / (double)m);
+}
+
+/* Ranks of the training set in a sorted sample of m keys (see above). */
+int64_t oracle_training_points(int64_t m, int64_t *rank)
+{
+    const int64_t nt = m < 4096 ? m : 4096;
+    for (int64_t k = 0; k < nt; ++k) rank[k] = (k * m) / nt + m / (2 * nt);
+    return nt;
 }
 
 /* Full-batch training from `seed`-initialised weights: `steps` Adam steps on
@@ -207,20 +251,21 @@ static double value_of_f64_key(uint64_t key)
     return x;
 }
 
-static double model_at(const double *p, double mu, double sd, uint64_t key)
+static double model_at(const double *p, double sc, double mu, double sd, uint64_t key)
 {
-    return forward1(p, (asinh(value_of_f64_key(key)) - mu) / sd, NULL, NULL);
+    return forward1(p, (feat(value_of_f64_key(key), sc) - mu) / sd, NULL, NULL);
 }
 
-/* The smallest order word K in [kmin, kmax] with F(K) >= q, by bisection
- * (kmax when there is none); for a model that is not monotone, one word
- * where F crosses q. */
-uint64_t oracle_invert_one_f64(const double *p, double mu, double sd, uint64_t kmin, uint64_t kmax, double q)
+/* The rank of the smallest key of the sorted sample (order words) with
+ * F >= q, by bisection over the ranks (the last rank when there is none); for
+ * a model that is not monotone, one rank where F crosses q. */
+int64_t oracle_invert_one_f64(const double *p, double sc, double mu, double sd, const uint64_t *sorted, int64_t m,
+                              double q)
 {
-    uint64_t lo = kmin, hi = kmax;
+    int64_t lo = 0, hi = m - 1;
     while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (model_at(p, mu, sd, mid) >= q)
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (model_at(p, sc, mu, sd, sorted[mid]) >= q)
             hi = mid;
         else
             lo = mid + 1;
@@ -228,12 +273,13 @@ uint64_t oracle_invert_one_f64(const double *p, double mu, double sd, uint64_t k
     return lo;
 }
 
-/* Splitters of a float64 key space (order words) for nb buckets: nb - 1
- * bisections, then running maximum; returns them in split[0 .. nb-2]. */
-void oracle_invert_f64(const double *p, double mu, double sd, uint64_t kmin, uint64_t kmax, int nb,
+/* Splitters for nb buckets: nb - 1 bisections over the sorted sample (m
+ * order words), then the running maximum; returns them in split[0 .. nb-2]. */
+void oracle_invert_f64(const double *p, double sc, double mu, double sd, const uint64_t *sorted, int64_t m, int nb,
                        uint64_t *split)
 {
-    for (int j = 1; j < nb; ++j) split[j - 1] = oracle_invert_one_f64(p, mu, sd, kmin, kmax, (double)j / (double)nb);
+    for (int j = 1; j < nb; ++j)
+        split[j - 1] = sorted[oracle_invert_one_f64(p, sc, mu, sd, sorted, m, (double)j / (double)nb)];
     for (int j = 1; j < nb - 1; ++j)
         if (split[j] < split[j - 1]) split[j] = split[j - 1];
 }

@@ -319,7 +319,8 @@ def multiway_partition_(keys, splitters):
 
 
 class LearnReport(ctypes.Structure):
-    _fields_ = [("mu", ctypes.c_double), ("sd", ctypes.c_double), ("smin", ctypes.c_uint64),
+    _fields_ = [("scale", ctypes.c_double), ("mu", ctypes.c_double), ("sd", ctypes.c_double),
+                ("smin", ctypes.c_uint64),
                 ("smax", ctypes.c_uint64), ("m", ctypes.c_int32), ("h", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("use_model", ctypes.c_int32), ("model_imbalance", ctypes.c_float),
                 ("sample_imbalance", ctypes.c_float), ("final_loss", ctypes.c_float), ("reserved", ctypes.c_int32)]

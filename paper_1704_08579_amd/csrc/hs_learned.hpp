@@ -11,12 +11,18 @@
 //               scaled to [0, n) by a 64x64 high multiply), sorted by the
 //               library's own sort;
 //   model       an fp32 MLP 1-32-32-1 (tanh, tanh, sigmoid) fitted to the
-//               sample's empirical CDF: input z = (asinh(x) - mu) / sd over the
-//               sample, target (rank + 0.5) / m, mean squared error, Adam;
-//               forward, backward and update are this file's kernels;
-//   splitters   for j = 1..255 the smallest key K with F(K) >= j/256, by a
-//               64-ary search over the key's order word (one wave per
-//               splitter), then running maximum and de-duplication;
+//               sample's empirical CDF: input z = (asinh(x / s) - mu) / sd over
+//               the sample (s: the sample's 1% order statistic when it is
+//               positive there and spans more than three decades, likewise
+//               for negative samples, else its standard deviation), targets
+//               (rank + 0.5) / m at 4096 evenly spaced order statistics of the
+//               sorted sample, mean squared error, Adam; forward, backward
+//               and update are this file's kernels (one launch per step);
+//   splitters   for j = 1..255 the smallest key of the sorted sample with
+//               F >= j/256, by a 64-ary search over the sample's ranks (one
+//               wave per splitter; a run of equal sample keys then becomes a
+//               single splitter, which gives it an equality bucket), then
+//               running maximum and de-duplication;
 //   judge       the model's bucket imbalance (largest non-equality bucket over
 //               the ideal n/256) on a held-out sample is compared with that of
 //               the sample's order statistics (the sampled-pivot fallback);
@@ -106,14 +112,27 @@ template <> struct LearnKey<FMT_KV_F64> {
     static __device__ __forceinline__ double value(S s) { return LearnKey<FMT_F64>::value(s); }
 };
 
+constexpr uint32_t LEARN_NTRAIN = 4096;  // training points: evenly spaced order statistics of the sample
+
 // Scalars of the learned front end, in device memory.
+// Barrier of the persistent training kernel: arrivals, generation, and an
+// error word set when a wait runs out (the workgroups were not all
+// resident); each on a line of its own.
+struct LearnBar {
+    alignas(256) uint32_t arrive;
+    alignas(256) uint32_t gen;
+    alignas(256) uint32_t err;
+};
+
 struct LearnCtl {
+    double scale;                 // the feature is asinh(x / scale)
     double mu, sd;                // feature normalisation
     unsigned long long smin, smax;  // searched words of the sample's extremes
     uint32_t k;                   // distinct splitters in use
     uint32_t use_model;           // 1: the model's splitters, 0: the sample's order statistics
     float model_imb, sample_imb;  // imbalance of both splitter sets on the held-out sample
     uint32_t reserved[2];
+    LearnBar bar;                 // training barrier (zeroed with the rest)
 };
 
 // ---------------------------------------------------------------- sampling
@@ -153,33 +172,81 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return s;
 }
 
-// One workgroup over the sorted sample: feature statistics, inputs z and
-// targets y, the order-statistic splitters (the fallback) and the extremes.
+// asinh(x / s), the quotient clamped to the finite doubles.
+__device__ __forceinline__ double feat(double x, double s)
+{
+    double t = x / s;
+    t = t > 1.7976931348623157e308 ? 1.7976931348623157e308 : t;
+    t = t < -1.7976931348623157e308 ? -1.7976931348623157e308 : t;
+    return asinh(t);
+}
+
+// Training points: ntrain = min(LEARN_NTRAIN, m) evenly spaced ranks of the
+// sorted sample.
+__device__ __host__ __forceinline__ uint32_t ntrain_of(uint32_t m) { return m < LEARN_NTRAIN ? m : LEARN_NTRAIN; }
+__device__ __forceinline__ uint32_t train_rank(uint32_t k, uint32_t m)
+{
+    const uint32_t nt = ntrain_of(m);
+    return (uint32_t)(((uint64_t)k * m) / nt) + m / (2 * nt);
+}
+
+// One workgroup over the sorted sample: the feature's scale and statistics,
+// inputs z and targets y of the training points, the order-statistic
+// splitters (the fallback) and the extremes.
 template <int F>
 __global__ __launch_bounds__(1024) void k_ls_prep(Raw sorted, uint32_t m, float *z, float *y,
-                                                   typename KeyOf<F>::type *fallback, LearnCtl *lc)
+                                                   typename KeyOf<F>::type *fallback, LearnCtl *lc, double *fbuf)
 {
     using LK = LearnKey<F>;
     __shared__ double red[16];
     const uint32_t tid = threadIdx.x;
+    auto val = [&](uint32_t k) { return LK::value(LK::search(raw_load<F>(sorted, k))); };
+    // scale: the 1% order statistic of a positive sample spanning more than
+    // three decades (or minus the 99% one of such a negative sample), else
+    // the sample's standard deviation
+    const double a = val((uint32_t)(0.01 * (double)m)), b = val((uint32_t)(0.99 * (double)m));
+    double sc;
+    if (a > 0.0 && b / a > 1000.0) {
+        sc = a;
+    } else if (b < 0.0 && a / b > 1000.0) {
+        sc = -b;
+    } else {
+        double s0 = 0.0;
+        for (uint32_t k = tid; k < m; k += blockDim.x) s0 += val(k);
+        const double mean = block_sum(s0, red) / (double)m;
+        double v0 = 0.0;
+        for (uint32_t k = tid; k < m; k += blockDim.x) {
+            const double d = val(k) - mean;
+            v0 += d * d;
+        }
+        sc = sqrt(block_sum(v0, red) / (double)m);
+        if (!(sc > 0.0 && sc <= 1.7976931348623157e308)) sc = 1.0;
+    }
+    // each sample's feature once (kept in fbuf by the thread that reads it back)
     double s = 0.0;
-    for (uint32_t k = tid; k < m; k += blockDim.x) s += asinh(LK::value(LK::search(raw_load<F>(sorted, k))));
+    for (uint32_t k = tid; k < m; k += blockDim.x) {
+        const double f = feat(val(k), sc);
+        fbuf[k] = f;
+        s += f;
+    }
     const double mu = block_sum(s, red) / (double)m;
     double v = 0.0;
     for (uint32_t k = tid; k < m; k += blockDim.x) {
-        const double d = asinh(LK::value(LK::search(raw_load<F>(sorted, k)))) - mu;
+        const double d = fbuf[k] - mu;
         v += d * d;
     }
     double sd = sqrt(block_sum(v, red) / (double)m);
     if (!(sd > 0.0)) sd = 1.0;
-    for (uint32_t k = tid; k < m; k += blockDim.x) {
-        const double x = LK::value(LK::search(raw_load<F>(sorted, k)));
-        z[k] = (float)((asinh(x) - mu) / sd);
-        y[k] = (float)(((double)k + 0.5) / (double)m);
+    __syncthreads();  // fbuf of every sample written (the training points are other threads')
+    for (uint32_t k = tid; k < ntrain_of(m); k += blockDim.x) {
+        const uint32_t r = train_rank(k, m);
+        z[k] = (float)((fbuf[r] - mu) / sd);
+        y[k] = (float)(((double)r + 0.5) / (double)m);
     }
     for (uint32_t j = tid; j < (uint32_t)NSPLIT; j += blockDim.x)
         fallback[j] = raw_load<F>(sorted, (uint32_t)(((uint64_t)(j + 1) * m) / NBUCKET));
     if (tid == 0) {
+        lc->scale = sc;
         lc->mu = mu;
         lc->sd = sd;
         lc->smin = LK::search(raw_load<F>(sorted, 0));
@@ -191,9 +258,10 @@ __global__ __launch_bounds__(1024) void k_ls_prep(Raw sorted, uint32_t m, float 
 
 // Xavier-uniform initialisation from splitmix64 (53-bit uniforms): W1 takes
 // draws 0..31, W2 draws 32..1055, w3 draws 1056..1087; biases are zero.
-__global__ void k_mlp_init(float *p, float *mom, float *vel, uint64_t seed)
+__global__ void k_mlp_init(float *p, float *mom, float *vel, uint64_t seed, uint32_t *done)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && done) *done = 0u;  // the step counter of k_mlp_step
     if (i >= MLP_NP) return;
     mom[i] = 0.f;
     vel[i] = 0.f;
@@ -254,110 +322,387 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *p, const float
     out[k] = mlp_forward1(sp, z[k], h1, h2);
 }
 
-// Gradient of the mean squared error over samples [0, m) of (z, y), first
-// half: workgroup g writes the gradient sum of its 256 samples to
-// part[g * MLP_PS ...] and their squared error to loss_blk[g].  Every sum
-// over samples runs in a fixed order, so the result is deterministic.
-//   forward      each thread runs its sample through the net (weights in LDS);
-//   W2, b2       dW2 = D2^T H1 over the 256 samples: the rows of H1 and D2
-//                go through LDS; thread t owns row t/8, columns 4(t%8)..+3;
-//   W1, b1, w3, b3 and the loss: 98 sums, each split over two threads
-//                (samples 0..127 and 128..255) and combined in LDS.
+// Gradient of the mean squared error over samples [0, m) of (z, y) for the
+// 256 samples of workgroup g: their gradient sum goes to part[g * MLP_PS ...]
+// and their squared error to loss_blk[g].  Each wave takes 64 samples and
+// runs the three products of a step on the matrix cores (fp32 MFMA 16x16x4:
+// lane l holds A[l%16][l/16] and B[l/16][l%16], and register r of the
+// result holds D[4(l/16)+r][l%16]):
+//   forward      A2 = H1 W2^T (64x32x32), H1 = tanh(z W1 + b1) computed in
+//                the operand layout, H2 = tanh(A2 + b2), F = sigmoid(H2 w3 + b3)
+//                (the sum over the 32 outputs of a sample runs over the 16
+//                lanes of a row and the two output blocks);
+//   weights      dW2 = D2^T H1 (32x32 over the wave's 64 samples) with
+//                D2 = ds3 w3 (1 - H2^2), ds3 = 2 (F - y) / m F (1 - F);
+//                D2 is already in the operand layout this product needs;
+//   layer 1      dH1 = D2 W2 (64x32x32; D2 goes through LDS to change
+//                layout), ds1 = dH1 (1 - H1^2);
+// and the vector terms (b2, W1, b1, w3, b3, the loss) are sums over lanes.
+// The four waves' partials are added in a fixed order, so the result is
+// deterministic.
+typedef float mlp_v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mlp_v4f mfma4(float a, float b, mlp_v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Sum over the 16 lanes of a row (lanes with equal lane / 16), in every one.
+__device__ __forceinline__ float row16_sum(float v)
+{
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    return v;
+}
+
+// Sum over lanes l, l ^ 16, l ^ 32, l ^ 48 (the four rows), in every one.
+__device__ __forceinline__ float rows4_sum(float v)
+{
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+__device__ __forceinline__ void mlp_grad_block(const float *sp, const float *z, const float *y, uint32_t m,
+                                               float *part, float *loss_blk)
+{
+    constexpr int NT = 256, NW = NT / WAVE, DS = 33;  // DS: row stride of the D2 rows in LDS
+    __shared__ float sz[NT], sy[NT], sv[NT];
+    __shared__ float sd2[NW][WAVE * DS];
+    __shared__ float sw2[NW][MLP_H * MLP_H];
+    __shared__ float svec[NW][4][MLP_H];
+    __shared__ float sscal[NW][2];
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    const int g = lane >> 4, c = lane & 15;
+    const uint32_t k = blockIdx.x * NT + tid;
+    const bool valid = k < m;
+    sz[tid] = valid ? z[k] : 0.f;
+    sy[tid] = valid ? y[k] : 0.f;
+    sv[tid] = valid ? 1.f : 0.f;
+    __syncthreads();
+    const float *wz = sz + wv * WAVE, *wy = sy + wv * WAVE, *wvl = sv + wv * WAVE;
+
+    // ---- forward: A2 = H1 W2^T; B operand W2^T[4ku + g][16ob + c]
+    float bw[2][8];
+#pragma unroll
+    for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+        for (int ku = 0; ku < 8; ++ku) bw[ob][ku] = sp[MLP_W2 + (16 * ob + c) * MLP_H + 4 * ku + g];
+    mlp_v4f acc[4][2];
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+        acc[sb][0] = mlp_v4f{0.f, 0.f, 0.f, 0.f};
+        acc[sb][1] = mlp_v4f{0.f, 0.f, 0.f, 0.f};
+        const float zs = wz[sb * 16 + c];  // A operand: sample sb*16 + c, unit 4ku + g
+#pragma unroll
+        for (int ku = 0; ku < 8; ++ku) {
+            const int u = 4 * ku + g;
+            const float a = tanh_fast(fmaf(sp[MLP_W1 + u], zs, sp[MLP_B1 + u]));
+            acc[sb][0] = mfma4(a, bw[0][ku], acc[sb][0]);
+            acc[sb][1] = mfma4(a, bw[1][ku], acc[sb][1]);
+        }
+    }
+    // result: acc[sb][ob][r] = A2[sb*16 + 4g + r][16ob + c]
+    float d2v[4][2][4];
+    float dw3p[2] = {0.f, 0.f}, db3p = 0.f, lossp = 0.f;
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int s = sb * 16 + 4 * g + r;
+            float h2[2], a3p = 0.f;
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob) {
+                h2[ob] = tanh_fast(acc[sb][ob][r] + sp[MLP_B2 + 16 * ob + c]);
+                a3p = fmaf(h2[ob], sp[MLP_W3 + 16 * ob + c], a3p);
+            }
+            const float f = 1.f / (1.f + __expf(-(row16_sum(a3p) + sp[MLP_B3])));
+            const float e = wvl[s] * (f - wy[s]);
+            const float ds3 = 2.f * e / (float)m * f * (1.f - f);
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob) {
+                d2v[sb][ob][r] = ds3 * sp[MLP_W3 + 16 * ob + c] * (1.f - h2[ob] * h2[ob]);
+                dw3p[ob] = fmaf(ds3, h2[ob], dw3p[ob]);
+            }
+            if (c == 0) {  // one lane per sample
+                db3p += ds3;
+                lossp = fmaf(e, e, lossp);
+            }
+        }
+
+    // ---- dW2 = D2^T H1: A operand D2[s][16ob + c], B operand H1[s][16ub + c],
+    // s = sb*16 + 4g + r over the 16 steps (sb, r)
+    float h1d[4][4][2];
+    mlp_v4f acc2[2][2];
+#pragma unroll
+    for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+        for (int ub = 0; ub < 2; ++ub) acc2[ob][ub] = mlp_v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float zs = wz[sb * 16 + 4 * g + r];
+#pragma unroll
+            for (int ub = 0; ub < 2; ++ub)
+                h1d[sb][r][ub] = tanh_fast(fmaf(sp[MLP_W1 + 16 * ub + c], zs, sp[MLP_B1 + 16 * ub + c]));
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+                for (int ub = 0; ub < 2; ++ub) acc2[ob][ub] = mfma4(d2v[sb][ob][r], h1d[sb][r][ub], acc2[ob][ub]);
+        }
+
+    // ---- dH1 = D2 W2: A operand D2[sb*16 + c][4ko + g] (through LDS), B operand W2[4ko + g][16ub + c]
+    float *wd2 = sd2[wv];
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wd2[(sb * 16 + 4 * g + r) * DS + 16 * ob + c] = d2v[sb][ob][r];
+    __syncthreads();
+    float bw2[2][8];
+#pragma unroll
+    for (int ub = 0; ub < 2; ++ub)
+#pragma unroll
+        for (int ko = 0; ko < 8; ++ko) bw2[ub][ko] = sp[MLP_W2 + (4 * ko + g) * MLP_H + 16 * ub + c];
+    float dw1p[2] = {0.f, 0.f}, db1p[2] = {0.f, 0.f};
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+        mlp_v4f acc3[2] = {mlp_v4f{0.f, 0.f, 0.f, 0.f}, mlp_v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int ko = 0; ko < 8; ++ko) {
+            const float a = wd2[(sb * 16 + c) * DS + 4 * ko + g];
+            acc3[0] = mfma4(a, bw2[0][ko], acc3[0]);
+            acc3[1] = mfma4(a, bw2[1][ko], acc3[1]);
+        }
+        // acc3[ub][r] = dH1[sb*16 + 4g + r][16ub + c], the layout of h1d
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float zs = wz[sb * 16 + 4 * g + r];
+#pragma unroll
+            for (int ub = 0; ub < 2; ++ub) {
+                const float h = h1d[sb][r][ub];
+                const float ds1 = acc3[ub][r] * (1.f - h * h);
+                dw1p[ub] = fmaf(ds1, zs, dw1p[ub]);
+                db1p[ub] += ds1;
+            }
+        }
+    }
+
+    // ---- the wave's partials to LDS, then the sum over the waves
+    float *w2 = sw2[wv];
+#pragma unroll
+    for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+        for (int ub = 0; ub < 2; ++ub)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w2[(16 * ob + 4 * g + r) * MLP_H + 16 * ub + c] = acc2[ob][ub][r];
+    float db2p[2] = {0.f, 0.f};
+#pragma unroll
+    for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) db2p[ob] += d2v[sb][ob][r];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const float b2s = rows4_sum(db2p[h]), w1s = rows4_sum(dw1p[h]), b1s = rows4_sum(db1p[h]);
+        const float w3s = rows4_sum(dw3p[h]);
+        if (g == 0) {
+            svec[wv][0][16 * h + c] = b2s;
+            svec[wv][1][16 * h + c] = w1s;
+            svec[wv][2][16 * h + c] = b1s;
+            svec[wv][3][16 * h + c] = w3s;
+        }
+    }
+    const float b3s = rows4_sum(db3p), ls = rows4_sum(lossp);
+    if (lane == 0) {
+        sscal[wv][0] = b3s;
+        sscal[wv][1] = ls;
+    }
+    __syncthreads();
+    float *gout = part + (size_t)blockIdx.x * MLP_PS;
+    for (int i = tid; i < MLP_H * MLP_H; i += NT)
+        gout[MLP_W2 + i] = ((sw2[0][i] + sw2[1][i]) + sw2[2][i]) + sw2[3][i];
+    if (tid < 4 * MLP_H) {
+        const int v = tid / MLP_H, j = tid % MLP_H;
+        const float t = ((svec[0][v][j] + svec[1][v][j]) + svec[2][v][j]) + svec[3][v][j];
+        const int off = v == 0 ? MLP_B2 : v == 1 ? MLP_W1 : v == 2 ? MLP_B1 : MLP_W3;
+        gout[off + j] = t;
+    }
+    if (tid == 0) gout[MLP_B3] = ((sscal[0][0] + sscal[1][0]) + sscal[2][0]) + sscal[3][0];
+    if (tid == 1 && loss_blk) loss_blk[blockIdx.x] = ((sscal[0][1] + sscal[1][1]) + sscal[2][1]) + sscal[3][1];
+    __syncthreads();  // the caller may overwrite the parameters in LDS next
+}
+
 __global__ __launch_bounds__(256) void k_mlp_grad(const float *p, const float *z, const float *y, uint32_t m,
                                                   float *part, float *loss_blk)
 {
-    constexpr int NT = 256, HS = 36;  // row stride of the per-sample rows: 16-byte aligned
     __shared__ float sp[MLP_NP];
-    __shared__ __align__(16) float sa[NT * HS];
-    __shared__ __align__(16) float sb[NT * HS];
-    __shared__ float sz[NT], s3[NT], sl[NT];
-    __shared__ float red[2][128];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < MLP_NP; i += NT) sp[i] = p[i];
+    for (int i = threadIdx.x; i < MLP_NP; i += blockDim.x) sp[i] = p[i];
     __syncthreads();
-    const uint32_t k = blockIdx.x * NT + tid;
-    const bool valid = k < m;
-    const float zf = valid ? z[k] : 0.f, yf = valid ? y[k] : 0.f;
-    float h1[MLP_H], h2[MLP_H], d2[MLP_H];
-    const float f = mlp_forward1(sp, zf, h1, h2);
-    const float e = valid ? f - yf : 0.f;
-    const float ds3 = 2.f * e / (float)m * f * (1.f - f);
-#pragma unroll
-    for (int o = 0; o < MLP_H; ++o) d2[o] = ds3 * sp[MLP_W3 + o] * (1.f - h2[o] * h2[o]);
-#pragma unroll
-    for (int i = 0; i < MLP_H; i += 4) {
-        *(float4 *)&sa[tid * HS + i] = make_float4(h1[i], h1[i + 1], h1[i + 2], h1[i + 3]);
-        *(float4 *)&sb[tid * HS + i] = make_float4(d2[i], d2[i + 1], d2[i + 2], d2[i + 3]);
-    }
-    sz[tid] = zf;
-    s3[tid] = ds3;
-    sl[tid] = e * e;
+    mlp_grad_block(sp, z, y, m, part, loss_blk);
+}
+
+// One Adam step of parameter i (beta1 0.9, beta2 0.999, eps 1e-8, bias
+// correction) with gradient g at step t.
+__device__ __forceinline__ void adam_update(float *p, float *mom, float *vel, uint32_t i, float g, int t, float lr)
+{
+    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1c, (float)t), c2 = 1.f - powf(b2c, (float)t);
+    const float mo = b1c * mom[i] + (1.f - b1c) * g;
+    const float ve = b2c * vel[i] + (1.f - b2c) * g * g;
+    mom[i] = mo;
+    vel[i] = ve;
+    p[i] -= lr * (mo / c1) / (sqrtf(ve / c2) + eps);
+}
+
+// One training step in one launch, for a few workgroups: each workgroup
+// writes the gradient sum of its 256 samples (as k_mlp_grad) and counts
+// itself done; the last one to finish sums the partial gradients of every
+// parameter over the workgroups in a fixed order (so a step gives the same
+// bits every time) and applies Adam.  The agent-scope fences make the
+// partials of every workgroup visible to the last one; every workgroup has
+// read the parameters before it counts itself done, so the update cannot
+// race with a reader.  `done` is zero on entry and left zero.  With `loss`
+// set the last workgroup also writes the step's mean squared error (the loss
+// before the update).
+__global__ __launch_bounds__(256) void k_mlp_step(float *p, float *mom, float *vel, const float *z, const float *y,
+                                                  uint32_t m, float *part, float *loss_blk, uint32_t *done, int t,
+                                                  float lr, float *loss)
+{
+    __shared__ uint32_t s_last;
+    __shared__ float sp[MLP_NP];
+    for (int i = threadIdx.x; i < MLP_NP; i += blockDim.x) sp[i] = p[i];
     __syncthreads();
-    float *gout = part + (size_t)blockIdx.x * MLP_PS;
-    {
-        const int o = tid >> 3, i0 = (tid & 7) * 4;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, ab = 0.f;
-#pragma unroll 8
-        for (int s = 0; s < NT; ++s) {
-            const float dv = sb[s * HS + o];
-            const float4 hv = *(const float4 *)&sa[s * HS + i0];
-            a0 = fmaf(dv, hv.x, a0);
-            a1 = fmaf(dv, hv.y, a1);
-            a2 = fmaf(dv, hv.z, a2);
-            a3 = fmaf(dv, hv.w, a3);
-            ab += dv;
+    mlp_grad_block(sp, z, y, m, part, loss_blk);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const uint32_t G = gridDim.x;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)MLP_NP; i += blockDim.x) {
+        float g = 0.f;
+        for (uint32_t b0 = 0; b0 < G; b0 += 16) {
+            float v[16];
+#pragma unroll
+            for (uint32_t u = 0; u < 16; ++u) v[u] = b0 + u < G ? part[(size_t)(b0 + u) * MLP_PS + i] : 0.f;
+#pragma unroll
+            for (uint32_t u = 0; u < 16; ++u) g += v[u];
         }
-        *(float4 *)&gout[MLP_W2 + o * MLP_H + i0] = make_float4(a0, a1, a2, a3);
-        if ((tid & 7) == 0) gout[MLP_B2 + o] = ab;
+        adam_update(p, mom, vel, i, g, t, lr);
     }
-    // back to layer 1: dh1 = W2^T d2, ds1 = dh1 (1 - h1^2)
-    float d1[MLP_H];
-#pragma unroll
-    for (int i = 0; i < MLP_H; ++i) d1[i] = 0.f;
-#pragma unroll
-    for (int o = 0; o < MLP_H; ++o) {
-#pragma unroll
-        for (int i = 0; i < MLP_H; ++i) d1[i] = fmaf(d2[o], sp[MLP_W2 + o * MLP_H + i], d1[i]);
+    if (loss && threadIdx.x < WAVE) {
+        float l = 0.f;
+        for (uint32_t b = threadIdx.x; b < G; b += WAVE) l += loss_blk[b];
+        for (int d = 1; d < WAVE; d <<= 1) l += __shfl_xor(l, d);
+        if (threadIdx.x == 0) *loss = l / (float)m;
     }
-    __syncthreads();  // everyone is done reading sa/sb
-#pragma unroll
-    for (int i = 0; i < MLP_H; i += 4) {
-        *(float4 *)&sa[tid * HS + i] = make_float4(d1[i] * (1.f - h1[i] * h1[i]), d1[i + 1] * (1.f - h1[i + 1] * h1[i + 1]),
-                                                   d1[i + 2] * (1.f - h1[i + 2] * h1[i + 2]),
-                                                   d1[i + 3] * (1.f - h1[i + 3] * h1[i + 3]));
-        *(float4 *)&sb[tid * HS + i] = make_float4(h2[i], h2[i + 1], h2[i + 2], h2[i + 3]);
-    }
+    if (threadIdx.x == 0) *done = 0u;
+}
+
+// The fused step sums all partials in one workgroup: for at most this many
+// workgroups (larger batches take k_mlp_grad + k_mlp_update).
+constexpr uint32_t MLP_STEP_MAX_G = 64;
+
+// Barrier over the G workgroups of k_mlp_train: arrival is one device-scope
+// atomic per workgroup, the last arrival resets the count and bumps the
+// generation, the others poll it with a bounded spin; the agent-scope fences
+// make the partial gradients written before the barrier visible after it.  A
+// wait that runs out sets bar->err and every workgroup leaves.
+constexpr uint32_t LEARN_SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ bool learn_barrier(LearnBar *bar, uint32_t &gen)
+{
+    __shared__ uint32_t s_ok;
     __syncthreads();
-    {
-        const int r = tid & 127, half = tid >> 7, s0 = half * (NT / 2);
-        float v = 0.f;
-        if (r < MLP_H) {  // W1[r] = sum ds1[s][r] z[s]
-#pragma unroll 8
-            for (int s = s0; s < s0 + NT / 2; ++s) v = fmaf(sa[s * HS + r], sz[s], v);
-        } else if (r < 2 * MLP_H) {  // b1
-#pragma unroll 8
-            for (int s = s0; s < s0 + NT / 2; ++s) v += sa[s * HS + r - MLP_H];
-        } else if (r < 3 * MLP_H) {  // w3 = sum ds3[s] h2[s]
-#pragma unroll 8
-            for (int s = s0; s < s0 + NT / 2; ++s) v = fmaf(s3[s], sb[s * HS + r - 2 * MLP_H], v);
-        } else if (r == 3 * MLP_H) {  // b3
-#pragma unroll 8
-            for (int s = s0; s < s0 + NT / 2; ++s) v += s3[s];
-        } else if (r == 3 * MLP_H + 1) {  // squared error
-#pragma unroll 8
-            for (int s = s0; s < s0 + NT / 2; ++s) v += sl[s];
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        __threadfence();
+        if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ok = false;
+        } else if (atomicAdd(&bar->arrive, 1u) == gridDim.x - 1) {
+            atomicExch(&bar->arrive, 0u);
+            __threadfence();
+            atomicAdd(&bar->gen, 1u);
+        } else {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    ++spins > LEARN_SPIN_LIMIT) {
+                    atomicOr(&bar->err, 1u);
+                    ok = false;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
         }
-        red[half][r] = v;
+        __threadfence();
+        ++gen;
+        s_ok = ok ? 1u : 0u;
     }
     __syncthreads();
-    if (tid < 3 * MLP_H + 2) {
-        const float v = red[0][tid] + red[1][tid];
-        if (tid < MLP_H) gout[MLP_W1 + tid] = v;
-        else if (tid < 2 * MLP_H) gout[MLP_B1 + tid - MLP_H] = v;
-        else if (tid < 3 * MLP_H) gout[MLP_W3 + tid - 2 * MLP_H] = v;
-        else if (tid == 3 * MLP_H) gout[MLP_B3] = v;
-        else if (loss_blk) loss_blk[blockIdx.x] = v;
+    return s_ok != 0;
+}
+
+// Every training step in one launch of G workgroups (all resident): each
+// keeps the parameters and Adam's moments in LDS; per step it writes the
+// gradient sum of its 256 samples to the step's half of `part` (the halves
+// alternate, so a workgroup that runs ahead never overwrites partials that
+// another one still reads), meets the others at the barrier, then sums the
+// G partials of every parameter in a fixed order and applies Adam itself.
+// Every workgroup does the same arithmetic in the same order, so all hold
+// the same parameters, and no second barrier is needed.  Workgroup 0 writes
+// the final parameters to p (which holds the initial ones on entry) and the
+// mean squared error of the last step (before its update) to *loss.  If the
+// barrier fails (bar->err set), the kernel stops; the caller then must not
+// use p.
+__global__ __launch_bounds__(256) void k_mlp_train(float *p, const float *z, const float *y, uint32_t m, int steps,
+                                                   float lr, float *part, float *loss_blk, LearnBar *bar,
+                                                   float *loss)
+{
+    __shared__ float sp[MLP_NP], smo[MLP_NP], sve[MLP_NP];
+    const uint32_t G = gridDim.x;
+    for (int i = threadIdx.x; i < MLP_NP; i += blockDim.x) {
+        sp[i] = p[i];
+        smo[i] = 0.f;
+        sve[i] = 0.f;
     }
+    __syncthreads();
+    uint32_t gen = 0;
+    for (int t = 1; t <= steps; ++t) {
+        float *pt = part + (size_t)(t & 1) * G * MLP_PS;
+        float *lt = loss_blk + (size_t)(t & 1) * G;
+        mlp_grad_block(sp, z, y, m, pt, lt);
+        if (!learn_barrier(bar, gen)) return;
+        for (uint32_t i = threadIdx.x; i < (uint32_t)MLP_NP; i += blockDim.x) {
+            // the partials of parameter i: sixteen loads in flight, summed in
+            // workgroup order
+            float g = 0.f;
+            for (uint32_t b0 = 0; b0 < G; b0 += 16) {
+                float v[16];
+#pragma unroll
+                for (uint32_t u = 0; u < 16; ++u) v[u] = b0 + u < G ? pt[(size_t)(b0 + u) * MLP_PS + i] : 0.f;
+#pragma unroll
+                for (uint32_t u = 0; u < 16; ++u) g += v[u];
+            }
+            adam_update(sp, smo, sve, i, g, t, lr);
+        }
+        if (t == steps && blockIdx.x == 0 && loss && threadIdx.x < WAVE) {
+            float l = 0.f;
+            for (uint32_t b = threadIdx.x; b < G; b += WAVE) l += lt[b];
+            for (int d = 1; d < WAVE; d <<= 1) l += __shfl_xor(l, d);
+            if (threadIdx.x == 0) *loss = l / (float)m;
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < MLP_NP; i += blockDim.x) p[i] = sp[i];
 }
 
 // Second half: sum the G partial gradients of every parameter in a fixed
@@ -401,32 +746,27 @@ __global__ __launch_bounds__(256) void k_mlp_update(float *p, float *mom, float 
         grad_out[i] = g;
         return;
     }
-    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f;
-    const float c1 = 1.f - powf(b1c, (float)t), c2 = 1.f - powf(b2c, (float)t);
-    const float mo = b1c * mom[i] + (1.f - b1c) * g;
-    const float ve = b2c * vel[i] + (1.f - b2c) * g * g;
-    mom[i] = mo;
-    vel[i] = ve;
-    p[i] -= lr * (mo / c1) / (sqrtf(ve / c2) + eps);
+    adam_update(p, mom, vel, i, g, t, lr);
 }
 
 constexpr int MLP_UPDATE_GRID = (MLP_NP + WAVE - 1) / WAVE;
 
 // ---------------------------------------------------------------- splitters
 
-// One wave per splitter j: the smallest searched word s in [smin, smax] with
-// F(value(s)) >= (j+1)/256, by a 64-ary search.  Lane l probes
+// One wave per splitter j: the smallest key t of the sorted sample with
+// F(value(t)) >= (j+1)/256 (the largest sample key when there is none), by a
+// 64-ary search over the sample's ranks: lane l probes rank
 // lo + floor(span * l / 63), so lane 0 probes lo and lane 63 probes hi; a
-// ballot finds the first probe at or above the target and the interval
-// shrinks to (previous probe, that probe].  About 11 rounds cover 64 bits.
-// (The model is not monotone in general; the search then returns one
-// crossing, and the running maximum of the judge restores the order.)
+// ballot finds the first probe at or above the target and the range shrinks
+// to (previous probe, that probe].  Three rounds cover 2^16 ranks.  The
+// splitter is the smallest word with that key.  (The model is not monotone
+// in general; the search then returns one crossing, and the running maximum
+// of the judge restores the order.)
 template <int F>
-__global__ __launch_bounds__(256) void k_ls_invert(const float *p, const LearnCtl *lc,
+__global__ __launch_bounds__(256) void k_ls_invert(const float *p, const LearnCtl *lc, Raw sorted, uint32_t m,
                                                    typename KeyOf<F>::type *split)
 {
     using LK = LearnKey<F>;
-    using S = typename LK::S;
     __shared__ float sp[MLP_NP];
     for (int i = threadIdx.x; i < MLP_NP; i += blockDim.x) sp[i] = p[i];
     __syncthreads();
@@ -434,22 +774,22 @@ __global__ __launch_bounds__(256) void k_ls_invert(const float *p, const LearnCt
     const uint32_t j = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     if (j >= (uint32_t)NSPLIT) return;
     const float q = (float)(j + 1) / (float)NBUCKET;
-    const double mu = lc->mu, sd = lc->sd;
-    S lo = (S)lc->smin, hi = (S)lc->smax;
+    const double sc = lc->scale, mu = lc->mu, sd = lc->sd;
+    uint32_t lo = 0, hi = m - 1;
     float h1[MLP_H], h2[MLP_H];
     while (lo < hi) {
-        const S span = hi - lo;
-        const S a = span / 63, r = span % 63;  // floor(span*l/63) without overflow
-        const S probe = lo + a * (S)lane + (r * (S)lane) / 63;
-        const float zf = (float)((asinh(LK::value(probe)) - mu) / sd);
+        const uint32_t span = hi - lo;
+        const uint32_t probe = lo + (uint32_t)(((uint64_t)span * (uint32_t)lane) / (WAVE - 1));
+        const double x = LK::value(LK::search(raw_load<F>(sorted, probe)));
+        const float zf = (float)((feat(x, sc) - mu) / sd);
         const bool ge = mlp_forward1(sp, zf, h1, h2) >= q;
         const uint64_t bal = __ballot(ge);
-        if (bal == 0) {  // F < q up to hi, which is then smax: answer smax
+        if (bal == 0) {  // F < q up to hi, which is then the last rank: answer it
             lo = hi;
             break;
         }
         const int first = __builtin_ctzll(bal);
-        const S at = lane_bcast(probe, first);
+        const uint32_t at = lane_bcast(probe, first);
         if (first == 0) {
             hi = lo;
             break;
@@ -457,7 +797,7 @@ __global__ __launch_bounds__(256) void k_ls_invert(const float *p, const LearnCt
         lo = lane_bcast(probe, first - 1) + 1;
         hi = at;
     }
-    if (lane == 0) split[j] = LK::word(lo);
+    if (lane == 0) split[j] = LK::word(LK::search(raw_load<F>(sorted, lo)));
 }
 
 // One workgroup: running maximum and de-duplication of the model's
@@ -465,30 +805,44 @@ __global__ __launch_bounds__(256) void k_ls_invert(const float *p, const LearnCt
 // both on the held-out sample, and the choice.  Writes the chosen distinct
 // splitters to `chosen` and their count to lc->k.  mode: JUDGE_AUTO, or
 // JUDGE_MODEL / JUDGE_SAMPLE to force one set (JUDGE_SAMPLE does not read
-// the model's splitters and reports a model imbalance of -1).  counts_out
-// (optional, 2 * NB_MAX words) receives the held-out bucket counts of both
-// sets, the model's first (2k + 1 used entries each, the rest zero).
+// the model's splitters and reports a model imbalance of -1; a training run
+// that could not finish forces it too).  counts_out (optional, 2 * NB_MAX
+// words) receives the held-out bucket counts of both sets, the model's
+// first (2k + 1 used entries each, the rest zero).
 constexpr int JUDGE_AUTO = 0, JUDGE_MODEL = 1, JUDGE_SAMPLE = 2;
 
-template <typename K>
-__global__ __launch_bounds__(256) void k_ls_judge(const K *model_split, const K *sample_split, const K *holdout,
-                                                  uint32_t h, K *chosen, LearnCtl *lc, int mode,
+template <int F>
+__global__ __launch_bounds__(256) void k_ls_judge(const typename KeyOf<F>::type *model_split,
+                                                  const typename KeyOf<F>::type *sample_split,
+                                                  const typename KeyOf<F>::type *holdout, uint32_t h,
+                                                  typename KeyOf<F>::type *chosen, LearnCtl *lc, int mode,
                                                   uint32_t *counts_out)
 {
-    __shared__ K dm[NSPLIT], ds[NSPLIT];
+    using K = typename KeyOf<F>::type;
+    __shared__ K sn[NSPLIT], so[NSPLIT], dm[NSPLIT], ds[NSPLIT];
     __shared__ uint32_t cm[NB_MAX], cs[NB_MAX];
     __shared__ uint32_t km_s, ks_s, um_s;
     const int tid = threadIdx.x;
+    // a training run that could not finish leaves no model: the sample's
+    // order statistics are used
+    if (mode != JUDGE_SAMPLE && __hip_atomic_load(&lc->bar.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        mode = JUDGE_SAMPLE;
+    // both splitter lists into LDS (the loop below runs on one thread)
+    for (int j = tid; j < NSPLIT; j += blockDim.x) {
+        if (mode != JUDGE_SAMPLE) sn[j] = model_split[j];
+        so[j] = sample_split[j];
+    }
+    __syncthreads();
     if (tid == 0) {
         uint32_t km = 0, ks = 0;
         K run = 0;
         for (int j = 0; j < NSPLIT; ++j) {
             if (mode != JUDGE_SAMPLE) {
-                const K v = j == 0 ? model_split[0] : (model_split[j] > run ? model_split[j] : run);
+                const K v = j == 0 ? sn[0] : (sn[j] > run ? sn[j] : run);
                 run = v;
                 if (km == 0 || dm[km - 1] != v) dm[km++] = v;
             }
-            const K w = sample_split[j];
+            const K w = so[j];
             if (ks == 0 || ds[ks - 1] != w) ds[ks++] = w;
         }
         km_s = km;

@@ -126,9 +126,9 @@ struct LearnParams {
     uint64_t seed = 0;
 };
 
-constexpr int LEARN_STEPS = 300;
+constexpr int LEARN_STEPS = 100;
 constexpr int LEARN_LOG2M = 16;
-constexpr float LEARN_LR = 1e-2f;
+constexpr float LEARN_LR = 3e-2f;
 constexpr uint32_t LEARN_HOLDOUT = 1u << 14;
 constexpr uint32_t MW_GMAX = 2048;  // multiway workgroups at most
 
@@ -190,7 +190,7 @@ struct Layout {
     uint32_t cand_cap = 0, task_cap = 0;
     // learned front end (LearnParams::on)
     size_t smp_k = 0, smp_v = 0, sub = 0, z = 0, y = 0, par = 0, mom = 0, vel = 0, part = 0, lossb = 0,
-           msplit = 0, ssplit = 0, chosen = 0, hold = 0, lctl = 0, hist = 0, btot = 0, bstart = 0;
+           msplit = 0, ssplit = 0, chosen = 0, hold = 0, lctl = 0, hist = 0, btot = 0, bstart = 0, feat = 0;
     size_t sub_bytes = 0;
 };
 
@@ -251,14 +251,15 @@ Layout make_layout(int op, int64_t n, int64_t nseg, uint32_t T, const LearnParam
         if (op == HS_OP_SORT_KV_I32 || op == HS_OP_SORT_KV_F64) L.smp_v = take((size_t)P.m * 4);
         L.sub = take(S.total);
         L.sub_bytes = S.total;
-        L.z = take((size_t)P.m * 4);
-        L.y = take((size_t)P.m * 4);
+        L.feat = take((size_t)P.m * 8);
+        L.z = take((size_t)ntrain_of(P.m) * 4);
+        L.y = take((size_t)ntrain_of(P.m) * 4);
         L.par = take(MLP_NP * 4);
         L.mom = take(MLP_NP * 4);
         L.vel = take(MLP_NP * 4);
-        const size_t gblk = (P.m + 255) / 256;
-        L.part = take(gblk * MLP_PS * 4);
-        L.lossb = take((gblk + 1) * 4);  // per-workgroup losses, then the mean
+        const size_t gblk = (ntrain_of(P.m) + 255) / 256;
+        L.part = take(2 * gblk * MLP_PS * 4);  // two halves: the training steps alternate
+        L.lossb = take((2 * gblk + 1) * 4);    // per-workgroup losses (two halves), then the mean
         L.msplit = take(NSPLIT * sizeof(K));
         L.ssplit = take(NSPLIT * sizeof(K));
         L.chosen = take(NSPLIT * sizeof(K));
@@ -448,19 +449,16 @@ int learn_front(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, uint
     const Layout S = make_layout<K>(op_of<F>(), P.m, 1, T);
     int rc = sort_body<F>(d, ws + L.sub, S, smp, P.m, nullptr, 0, o, LearnParams(), nullptr, stream);
     if (rc) return rc;
-    HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl);
-    const uint32_t gblk = (P.m + 255) / 256;
+    HS_LAUNCH(k_ls_prep<F>, 1, 1024, stream, smp, P.m, z, y, ssplit, lctl, (double *)(ws + L.feat));
+    const uint32_t nt = ntrain_of(P.m), gblk = (nt + 255) / 256;
     if (P.mode != JUDGE_SAMPLE) {
-        HS_LAUNCH(k_mlp_init, (MLP_NP + 255) / 256, 256, stream, par, mom, vel, P.seed + 2);
-        for (int t = 1; t <= P.steps; ++t) {
-            const bool last = t == P.steps;
-            HS_LAUNCH(k_mlp_grad, gblk, 256, stream, par, z, y, P.m, part, lossb);
-            HS_LAUNCH(k_mlp_update, MLP_UPDATE_GRID, 256, stream, par, mom, vel, part, gblk, t, P.lr,
-                      (float *)nullptr, lossb, last ? lossb + gblk : (float *)nullptr, P.m);
-        }
-        HS_LAUNCH(k_ls_invert<F>, (NSPLIT * WAVE + 255) / 256, 256, stream, par, lctl, msplit);
+        // every step in one launch of gblk resident workgroups (see k_mlp_train)
+        HS_LAUNCH(k_mlp_init, (MLP_NP + 255) / 256, 256, stream, par, mom, vel, P.seed + 2, (uint32_t *)nullptr);
+        HS_LAUNCH(k_mlp_train, gblk, 256, stream, par, z, y, nt, P.steps, P.lr, part, lossb, &lctl->bar,
+                  lossb + 2 * gblk);
+        HS_LAUNCH(k_ls_invert<F>, (NSPLIT * WAVE + 255) / 256, 256, stream, par, lctl, smp, P.m, msplit);
     }
-    HS_LAUNCH(k_ls_judge<K>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode, counts_out);
+    HS_LAUNCH(k_ls_judge<F>, 1, 256, stream, msplit, ssplit, hold, P.h, chosen, lctl, P.mode, counts_out);
     return HS_OK;
 }
 
@@ -677,8 +675,8 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     if (st) {
         if (learned) HS_HIP(hipMemcpyAsync(d->h_lctl, lctl, sizeof(LearnCtl), hipMemcpyDeviceToHost, stream));
         if (learned && P.mode != JUDGE_SAMPLE) {
-            const uint32_t gblk = (P.m + 255) / 256;
-            HS_HIP(hipMemcpyAsync(&loss, (float *)(ws + L.lossb) + gblk, sizeof(float), hipMemcpyDeviceToHost,
+            const uint32_t gblk = (ntrain_of(P.m) + 255) / 256;
+            HS_HIP(hipMemcpyAsync(&loss, (float *)(ws + L.lossb) + 2 * gblk, sizeof(float), hipMemcpyDeviceToHost,
                                   stream));
         }
     }
@@ -1390,7 +1388,7 @@ namespace {
 // Scratch of the MLP entry points: partial gradients of every workgroup,
 // per-workgroup losses and the Adam moments.
 struct MlpScratch {
-    size_t part, lossb, mom, vel, total;
+    size_t part, lossb, mom, vel, done, total;
 };
 
 MlpScratch mlp_scratch(uint32_t m)
@@ -1407,6 +1405,7 @@ MlpScratch mlp_scratch(uint32_t m)
     S.lossb = take(g * 4);
     S.mom = take(MLP_NP * 4);
     S.vel = take(MLP_NP * 4);
+    S.done = take(4);
     S.total = off;
     return S;
 }
@@ -1467,15 +1466,22 @@ int hs_mlp_train_f32(const float *d_z, const float *d_y, int64_t m, int32_t step
     HS_HIP(hipStreamWaitEvent(s, d->last, 0));
     float *mom = (float *)(ws + S.mom), *vel = (float *)(ws + S.vel);
     float *part = (float *)(ws + S.part), *lossb = (float *)(ws + S.lossb);
+    uint32_t *done = (uint32_t *)(ws + S.done);
     const uint32_t G = (uint32_t)((m + 255) / 256);
-    k_mlp_init<<<(MLP_NP + 255) / 256, 256, 0, s>>>(d_params, mom, vel, seed);
+    k_mlp_init<<<(MLP_NP + 255) / 256, 256, 0, s>>>(d_params, mom, vel, seed, done);
     HS_LAUNCHED();
     for (int t = 1; t <= steps; ++t) {
-        k_mlp_grad<<<G, 256, 0, s>>>(d_params, d_z, d_y, (uint32_t)m, part, lossb);
-        HS_LAUNCHED();
-        k_mlp_update<<<MLP_UPDATE_GRID, 256, 0, s>>>(d_params, mom, vel, part, G, t, lr, nullptr, lossb,
-                                                     d_loss ? d_loss + (t - 1) : nullptr, (uint32_t)m);
-        HS_LAUNCHED();
+        float *lt = d_loss ? d_loss + (t - 1) : nullptr;
+        if (G <= MLP_STEP_MAX_G) {  // one launch per step (as inside the sort)
+            k_mlp_step<<<G, 256, 0, s>>>(d_params, mom, vel, d_z, d_y, (uint32_t)m, part, lossb, done, t, lr, lt);
+            HS_LAUNCHED();
+        } else {
+            k_mlp_grad<<<G, 256, 0, s>>>(d_params, d_z, d_y, (uint32_t)m, part, lossb);
+            HS_LAUNCHED();
+            k_mlp_update<<<MLP_UPDATE_GRID, 256, 0, s>>>(d_params, mom, vel, part, G, t, lr, nullptr, lossb, lt,
+                                                         (uint32_t)m);
+            HS_LAUNCHED();
+        }
     }
     HS_HIP(hipEventRecord(d->last, s));
     return HS_OK;
@@ -1571,11 +1577,13 @@ int hs_learn_debug_f64(const double *keys, int64_t n, const hs_opts *opts, float
     HS_HIP(hipMemcpyAsync(d->h_lctl, ws + L.lctl, sizeof(LearnCtl), hipMemcpyDeviceToHost, s));
     float loss = 0.f;
     if (P.mode != JUDGE_SAMPLE && P.steps > 0)
-        HS_HIP(hipMemcpyAsync(&loss, (float *)(ws + L.lossb) + (P.m + 255) / 256, 4, hipMemcpyDeviceToHost, s));
+        HS_HIP(hipMemcpyAsync(&loss, (float *)(ws + L.lossb) + 2 * ((ntrain_of(P.m) + 255) / 256), 4,
+                              hipMemcpyDeviceToHost, s));
     HS_HIP(hipStreamSynchronize(s));
     if (shared_ws) HS_HIP(hipEventRecord(d->last, s));
     const LearnCtl &lc = *d->h_lctl;
     *report = hs_learn_report{};
+    report->scale = lc.scale;
     report->mu = lc.mu;
     report->sd = lc.sd;
     report->smin = lc.smin;

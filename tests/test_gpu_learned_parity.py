@@ -5,16 +5,16 @@ by the oracle from the same input:
 * the training and held-out samples are the keys at the oracle's splitmix64
   sample indices (the training sample sorted by the oracle);
 * the order statistics (the sampled-pivot fallback) are the oracle's ranks of
-  that sorted sample, the feature normalisation the oracle's statistics;
+  that sorted sample, the feature's scale and normalisation the oracle's;
 * the judge: its held-out bucket counts for both splitter sets equal the
   oracle's bucket histogram of the held-out keys over the oracle's running
   maximum and de-duplication of the same splitters; the imbalances and the
   decision follow from those counts in the judge's fp32 arithmetic;
-* the model's splitters: each meets the search's postcondition under the
-  oracle's fp64 forward pass on the GPU's fp32 weights (F(s) >= j/256 and
-  F(s - 1) < j/256, within the fp32 forward tolerance), and lies within 16
-  held-out keys (0.1% of them) of the oracle's bisection on the same model,
-  unless the model is not monotone there and both are crossings of j/256.
+* the model's splitters: each is a key of the sorted sample, of rank i with
+  F(t_i) >= j/256 and F(t_{i-1}) < j/256 under the oracle's fp64 forward
+  pass on the GPU's fp32 weights (within the fp32 forward tolerance), and
+  within 16 ranks of the oracle's bisection on the same model, unless the
+  model is not monotone there and both are crossings of j/256.
 """
 import numpy as np
 import pytest
@@ -28,7 +28,7 @@ torch = pytest.importorskip("torch")
 NB_MAX = 511
 NB = 256
 FWD_TOL = 2e-5     # fp32 forward pass against the fp64 oracle (measured error <= 1e-5)
-RANK_TOL = 16      # held-out keys between the GPU's and the oracle's splitter
+RANK_TOL = 16      # sample ranks between the GPU's and the oracle's splitter
 
 
 @pytest.fixture(scope="module")
@@ -46,8 +46,8 @@ def _key_value(k):
     return bits.view(np.float64)
 
 
-def _model_at(oracle_mod, p, mu, sd, words):
-    z = (np.arcsinh(_key_value(words)) - mu) / sd
+def _model_at(oracle_mod, p, sc, mu, sd, words):
+    z = (np.arcsinh(np.clip(_key_value(words) / sc, -1.7976931348623157e308, 1.7976931348623157e308)) - mu) / sd
     return oracle_mod.mlp_forward(p, z.astype(np.float32).astype(np.float64))
 
 
@@ -80,7 +80,9 @@ def test_front_end_matches_oracle(hs, oracle_mod, n, dist, seed, flags):
     ss = out["sample_split"].cpu().numpy().view(np.uint64)
     assert np.array_equal(ss, tk[(np.arange(1, NB, dtype=np.int64) * m) // NB])
     assert out["smin"] == int(tk[0]) and out["smax"] == int(tk[-1])
-    mu, sd = oracle_mod.feature_stats(train)
+    sc = oracle_mod.feature_scale(train)
+    assert abs(out["scale"] - sc) <= 1e-12 * sc
+    mu, sd = oracle_mod.feature_stats(train, out["scale"])
     assert abs(out["mu"] - mu) <= 1e-12 * max(1.0, abs(mu))
     assert abs(out["sd"] - sd) <= 1e-12 * max(1.0, abs(sd))
 
@@ -110,29 +112,26 @@ def test_front_end_matches_oracle(hs, oracle_mod, n, dist, seed, flags):
     want = dm if use else ds
     assert out["k"] == want.size and np.array_equal(chosen[:want.size], want)
 
-    # the model's splitters: the search's postcondition under the oracle's forward pass
+    # the model's splitters: sample keys meeting the search's postcondition
+    # under the oracle's forward pass
     p = out["params"].cpu().numpy().astype(np.float64)
-    smin, smax = np.uint64(out["smin"]), np.uint64(out["smax"])
     q = np.arange(1, NB, dtype=np.float64) / NB
-    f_at = _model_at(oracle_mod, p, out["mu"], out["sd"], ms)
-    below = np.where(ms > smin, ms - np.uint64(1), ms)
-    f_below = _model_at(oracle_mod, p, out["mu"], out["sd"], below)
-    ok_at = (ms == smax) | (f_at >= q - FWD_TOL)
-    ok_below = (ms == smin) | (f_below < q + FWD_TOL)
+    assert np.all(np.isin(ms, tk)), "a model splitter is not a sample key"
+    i_gpu = np.searchsorted(tk, ms, side="left")
+    Fs = _model_at(oracle_mod, p, out["scale"], out["mu"], out["sd"], tk)
+    ok_at = (i_gpu == m - 1) | (Fs[i_gpu] >= q - FWD_TOL)
+    ok_below = (i_gpu == 0) | (Fs[np.maximum(i_gpu - 1, 0)] < q + FWD_TOL)
     assert ok_at.all(), np.flatnonzero(~ok_at)[:8]
     assert ok_below.all(), np.flatnonzero(~ok_below)[:8]
     # ... and close to the oracle's bisection of the same model: where the
     # two are far apart, both must be crossings of j/256 (the model is not
     # monotone there, and either is a valid answer of the search)
-    ora = np.array([oracle_mod.invert_one_f64(p, out["mu"], out["sd"], out["smin"], out["smax"], qq) for qq in q],
-                   dtype=np.uint64)
-    assert np.array_equal(np.maximum.accumulate(ora),
-                          oracle_mod.invert_f64(p, out["mu"], out["sd"], out["smin"], out["smax"]))
-    hs_sorted = np.sort(hold)
-    far = np.abs(np.searchsorted(hs_sorted, ms) - np.searchsorted(hs_sorted, ora)) > RANK_TOL
-    fo = _model_at(oracle_mod, p, out["mu"], out["sd"], ora)
-    fo_below = _model_at(oracle_mod, p, out["mu"], out["sd"], np.where(ora > smin, ora - np.uint64(1), ora))
-    crossing = ((ora == smax) | (fo >= q - FWD_TOL)) & ((ora == smin) | (fo_below < q + FWD_TOL))
+    i_ora = np.array([oracle_mod.invert_one_f64(p, out["scale"], out["mu"], out["sd"], tk, qq) for qq in q])
+    assert np.array_equal(np.maximum.accumulate(tk[i_ora]),
+                          oracle_mod.invert_f64(p, out["scale"], out["mu"], out["sd"], tk))
+    far = np.abs(i_gpu - i_ora) > RANK_TOL
+    crossing = (((i_ora == m - 1) | (Fs[i_ora] >= q - FWD_TOL)) &
+                ((i_ora == 0) | (Fs[np.maximum(i_ora - 1, 0)] < q + FWD_TOL)))
     assert crossing[far].all(), np.flatnonzero(far & ~crossing)[:8]
     print(f"  {int(far.sum())} splitters at another crossing than the oracle's; model imbalance {imb_m:.3f}, "
           f"order statistics {imb_s:.3f}, use_model {int(use)}, final loss {out['final_loss']:.3g}", flush=True)

@@ -102,49 +102,91 @@ def test_init_is_xavier_uniform(oracle_mod):
 
 def test_feature_stats_match_numpy(oracle_mod):
     x = workloads.f64(5000, "lognormal", seed=6)
-    mu, sd = oracle_mod.feature_stats(x)
-    assert abs(mu - np.arcsinh(x).mean()) < 1e-12 and abs(sd - np.arcsinh(x).std()) < 1e-12
+    for sc in (1.0, 0.01, 3.5):
+        mu, sd = oracle_mod.feature_stats(x, sc)
+        f = np.arcsinh(x / sc)
+        assert abs(mu - f.mean()) < 1e-12 * max(1.0, abs(f.mean())) and abs(sd - f.std()) < 1e-12 * f.std()
+    # a quotient beyond the largest double is clamped (asinh stays finite)
+    big = np.array([1e308, -1e308, 1.0])
+    mu, sd = oracle_mod.feature_stats(big, 1e-10)
+    assert np.isfinite(mu) and np.isfinite(sd)
+
+
+def test_feature_scale_branches(oracle_mod):
+    """The scale rule on its three branches: a positive sample spanning more
+    than three decades takes its 1% order statistic, a negative one minus its
+    99% order statistic, anything else its standard deviation."""
+    m = 1 << 14
+    x = np.sort(workloads.f64(m, "lognormal", seed=3))
+    assert oracle_mod.feature_scale(x) == x[int(0.01 * m)]
+    neg = np.sort(-x)
+    assert oracle_mod.feature_scale(neg) == -neg[int(0.99 * m)]
+    for dist in ("normal", "uniform", "mixture"):
+        y = np.sort(workloads.f64(m, dist, seed=4))
+        assert abs(oracle_mod.feature_scale(y) - y.std()) <= 1e-12 * y.std()
+    # positive, but within three decades: the standard deviation
+    u = np.sort(1.0 + workloads.f64(m, "uniform", seed=5))
+    assert abs(oracle_mod.feature_scale(u) - u.std()) <= 1e-12 * u.std()
+    assert oracle_mod.feature_scale(np.full(100, 7.0)) == 1.0  # no spread: 1
+
+
+def test_training_points(oracle_mod):
+    """min(4096, m) evenly spaced ranks of the sorted sample."""
+    for m in (1024, 4096, 1 << 16, 100000):
+        r = oracle_mod.training_points(m)
+        nt = min(4096, m)
+        assert r.size == nt and r[0] >= 0 and r[-1] < m
+        assert np.all(np.diff(r) >= m // nt) and np.all(np.diff(r) <= -(-m // nt))
+    assert np.array_equal(oracle_mod.training_points(1 << 16), np.arange(4096) * 16 + 8)
 
 
 def _cdf_data(oracle_mod, dist, m=4096, seed=8):
     x = np.sort(workloads.f64(m, dist, seed=seed))
-    mu, sd = oracle_mod.feature_stats(x)
-    z = (np.arcsinh(x) - mu) / sd
+    sc = oracle_mod.feature_scale(x)
+    mu, sd = oracle_mod.feature_stats(x, sc)
+    z = (np.arcsinh(x / sc) - mu) / sd
     y = (np.arange(m) + 0.5) / m
-    return x, z, y, mu, sd
+    return x, z, y, sc, mu, sd
 
 
 @pytest.mark.parametrize("dist", ["lognormal", "mixture"])
 def test_training_lowers_the_loss(oracle_mod, dist):
-    x, z, y, mu, sd = _cdf_data(oracle_mod, dist)
+    x, z, y, sc, mu, sd = _cdf_data(oracle_mod, dist)
     p, losses = oracle_mod.mlp_train(5, z, y, 150, 1e-2)
     assert losses[-1] < 0.2 * losses[0]
     assert np.all(np.isfinite(p))
 
 
-def _key_to_z(oracle_mod, keys, mu, sd):
+def _key_to_z(oracle_mod, keys, sc, mu, sd):
     bits = np.where(keys >> np.uint64(63) == 1, keys & np.uint64((1 << 63) - 1), ~keys)
     x = bits.view(np.float64)
-    return (np.arcsinh(x) - mu) / sd
+    return (np.arcsinh(x / sc) - mu) / sd
 
 
 def test_inversion_bisection_postcondition(oracle_mod):
-    x, z, y, mu, sd = _cdf_data(oracle_mod, "lognormal")
+    x, z, y, sc, mu, sd = _cdf_data(oracle_mod, "lognormal")
     p, _ = oracle_mod.mlp_train(5, z, y, 100, 1e-2)
-    keys = oracle_mod.f64_order_keys(x)
-    kmin, kmax = int(keys.min()), int(keys.max())
+    keys = oracle_mod.f64_order_keys(x)  # x is sorted
     nb = 64
-    s = oracle_mod.invert_f64(p, mu, sd, kmin, kmax, nb)
+    s = oracle_mod.invert_f64(p, sc, mu, sd, keys, nb)
     assert np.all(np.diff(s.astype(np.float64)) >= 0)  # running maximum applied
-    # recompute the raw bisection result for a few targets and check the
-    # invariant (F(K) >= q or K == kmax) and (K == kmin or F(K-1) < q)
-    raw = oracle_mod.invert_f64(p, mu, sd, kmin, kmax, 2)[0]  # q = 1/2, single splitter
-    f = oracle_mod.mlp_forward(p, _key_to_z(oracle_mod, np.array([raw, raw - 1], dtype=np.uint64), mu, sd))
-    assert (f[0] >= 0.5 or raw == kmax) and (raw == kmin or f[1] < 0.5)
+    assert np.all(np.isin(s, keys))  # every splitter is a sample key
+    # every raw bisection result meets the invariant
+    # (F(t_i) >= q or i == m - 1) and (i == 0 or F(t_{i-1}) < q)
+    F = oracle_mod.mlp_forward(p, _key_to_z(oracle_mod, keys, sc, mu, sd))
+    for j in range(1, nb):
+        q = j / nb
+        i = oracle_mod.invert_one_f64(p, sc, mu, sd, keys, q)
+        assert (F[i] >= q or i == keys.size - 1) and (i == 0 or F[i - 1] < q), j
     # a trained model's median splitter sits near the sample median
-    med = float(np.uint64(raw).view(np.uint64))
-    rank = np.searchsorted(keys.astype(np.float64), med) / keys.size
-    assert 0.3 < rank < 0.7
+    i = oracle_mod.invert_one_f64(p, sc, mu, sd, keys, 0.5)
+    assert 0.3 < i / keys.size < 0.7
+    # on a monotone stretch the bisection gives the first rank reaching q
+    # (brute force over the ranks)
+    mono = np.all(np.diff(F) >= 0)
+    if mono:
+        for j in range(1, nb):
+            assert s[j - 1] == keys[np.argmax(F >= j / nb)] or not np.any(F >= j / nb)
 
 
 def test_bucket_histogram_matches_numpy(oracle_mod):
