@@ -213,7 +213,7 @@ def _f64_total_order_key(bits):
     return np.where(neg, ~bits, bits | np.uint64(1 << 63))
 
 
-@pytest.mark.parametrize("dist", ["uniform", "sorted"])
+@pytest.mark.parametrize("dist", ["uniform", "normal", "sorted", "reverse"])
 def test_full_size_f64(hs, dist):
     """2^27 float64 keys, the size the benchmark times: sorted by key and a
     permutation of the input (compared with numpy's sort of the same bits)."""
@@ -224,6 +224,23 @@ def test_full_size_f64(hs, dist):
     k = _f64_total_order_key(got)
     assert np.all(k[:-1] <= k[1:])
     assert np.array_equal(np.sort(a).view(np.uint64), got)
+
+
+@pytest.mark.parametrize("dist,seed", [("zipf", 7), ("mixture", 8)])
+def test_full_size_f64_learned_inputs(hs, dist, seed):
+    """2^28 float64 keys of the learned-splitter workloads (Zipf ranks with
+    heavy repeats, an 8-Gaussian mixture), sorted by the plain method and by
+    the learned one (which falls back to the sample's order statistics on
+    these inputs): both equal numpy's sort of the same bits."""
+    print(f"full size {dist} 2^28", flush=True)
+    a = workloads.f64(1 << 28, dist, seed=seed)
+    want = np.sort(a).view(np.uint64)  # no NaN or negative zero in these inputs
+    t = _gpu(a)
+    hs.sort_(t)
+    assert np.array_equal(t.cpu().numpy().view(np.uint64), want), "plain"
+    t.copy_(_gpu(a))
+    hs.sort_(t, opts=hs.learned_opts(seed=100))
+    assert np.array_equal(t.cpu().numpy().view(np.uint64), want), "learned"
 
 
 def test_full_size_kv(hs):
