@@ -80,7 +80,9 @@ enum { HS_PIVOT_AUTO = 0,     /* the tuned default */
        HS_PIVOT_MEDIAN3 = 1,  /* median of first, middle, last (Sec. IV-A) */
        HS_PIVOT_NINTHER = 2,  /* median of three medians of three */
        HS_PIVOT_SAMPLE = 3 }; /* global levels: lower median of 64 evenly spaced keys
-                                 (ninther below 256 keys and on chip) */
+                                 (ninther below 256 keys); on chip every rule but
+                                 MEDIAN3 takes the lower median of 32 evenly spaced
+                                 keys (64 for a task's first split) */
 
 /* Sort methods (hs_opts.method). */
 enum { HS_METHOD_PLAIN = 0,     /* the paper's method: one pivot per partition */
@@ -132,9 +134,9 @@ typedef struct hs_opts {
                            * are partitioned again); capped at 8192 (4096 for float64 key/value) */
     int32_t method;       /* HS_METHOD_* */
     int32_t learn_flags;  /* HS_LEARN_* */
-    int32_t train_steps;  /* learned method: Adam steps (default 300) */
+    int32_t train_steps;  /* learned method: Adam steps (default 100) */
     int32_t sample_log2;  /* learned method: log2 of the training sample (default 16, range 10..20) */
-    float learning_rate;  /* learned method: Adam learning rate (default 1e-2) */
+    float learning_rate;  /* learned method: Adam learning rate (default 3e-2) */
     int32_t driver;       /* HS_DRIVER_*: how the partition levels are driven */
     int32_t spin_limit;   /* testing: cap on the polls of one grid-barrier wait (0: about 4M); a wait that
                            * runs out fails the call with HS_EINTERNAL */

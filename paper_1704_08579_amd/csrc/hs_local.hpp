@@ -174,23 +174,83 @@ __device__ __forceinline__ void wave_qsort(K *sk, uint32_t b, uint32_t e, int ru
     }
 }
 
+// Lanes of the row starting at position r0 that lie before position e.
+__device__ __forceinline__ uint32_t lanes_to(uint32_t e, uint32_t r0)
+{
+    return e <= r0 ? 0u : min(e - r0, (uint32_t)WAVE);
+}
+
+// Class counts of the lanes of mask mk in one row against pivot p, added to
+// the wave's running totals (the compares' ballots: scalar work).
+template <typename K>
+__device__ __forceinline__ void row_count(K x, K p, uint64_t mk, uint32_t &nl, uint32_t &nq)
+{
+    nl += popc(ballot(x < p) & mk);
+    nq += popc(ballot(x == p) & mk);
+}
+
+// The lanes of mask mk (FULL: every lane) of one row go to their class's
+// next slot: the class's base plus the number of lanes of the class below
+// (mbcnt, the base riding in its accumulator); the bases then advance by
+// the class counts.  THREE: classes < p, == p, > p (bases cl, ce, cg);
+// otherwise < p and >= p (cl, cg).
+template <bool FULL, bool THREE, typename K>
+__device__ __forceinline__ void row_place(K *sk, K x, K p, uint64_t mk, uint32_t &cl, uint32_t &ce, uint32_t &cg,
+                                          int lane)
+{
+    const uint64_t lt = ballot(x < p) & mk;
+    uint32_t d;
+    if constexpr (THREE) {
+        const uint64_t eq = ballot(x == p) & mk, gt = mk & ~(lt | eq);
+        d = lane_select(lt, mbcnt_add(lt, cl), lane_select(eq, mbcnt_add(eq, ce), mbcnt_add(gt, cg)));
+        ce += popc(eq);
+        cg += popc(gt);
+    } else {
+        const uint64_t ge = mk & ~lt;
+        d = lane_select(lt, mbcnt_add(lt, cl), mbcnt_add(ge, cg));
+        cg += popc(ge);
+    }
+    cl += popc(lt);
+    if (FULL || ((mk >> lane) & 1ull)) sk[d] = x;
+}
+
+// Whether a range of m keys with nl keys below its pivot and ne equal to it
+// is split three ways (< p, == p final, > p) rather than two (< p, >= p).
+// Two ways is cheaper per row; it needs nl > 0 to make progress (the pivot
+// is one of the range's keys, so then both sides are smaller than the
+// range), and three ways retires a large run of keys equal to the pivot at
+// once.
+__device__ __forceinline__ bool split_three(uint32_t nl, uint32_t ne, uint32_t m)
+{
+    return nl == 0u || 32u * ne >= m;
+}
+
+// Per-range class counts as one 64-bit word: keys below the pivot, keys
+// equal to it, and keys of the range counted (bits 0-15, 16-31, 32-47).
+__device__ __forceinline__ unsigned long long pack_counts(uint32_t nl, uint32_t ne, uint32_t c)
+{
+    return (unsigned long long)(nl | (ne << 16)) | ((unsigned long long)c << 32);
+}
+
 // One workgroup per task of LEAF+1 .. T keys, claimed dynamically (the next
 // claim is issued at the start of a task so its latency hides behind it).
 //
 // Block levels.  Wave w owns the span [w*KW, (w+1)*KW) of the task; row j of
 // the span is positions w*KW + 64 j + lane.  At each level every live range
-// (longer than KW) is partitioned three ways around its pivot, all of them
-// at once.  A live range is longer than a span, so a span meets at most two:
-// A, holding the span's first position, and B, starting inside the span;
-// both are wave-uniform, and so is the split of each row between them.  Two
-// compares per row give the class masks as ballots; each wave publishes its
-// class counts for A and B, and after one barrier every wave knows where
-// its keys of each class go.  The keys, still in registers, are written in
-// place to their class's next slot (running base + mbcnt of the class
-// mask), and a second barrier ends the level.  The live list is held in
-// lanes (lane s: range s, with its pivot), computed identically by every
-// wave from per-range totals published by the wave holding the range's
-// first position; children of 2..KW keys are queued for the waves.
+// (longer than KW) is partitioned around its pivot, all of them at once.  A
+// live range is longer than a span, so a span meets at most two: A, holding
+// the span's first position, and B, starting inside the span; both are
+// wave-uniform, and so is the split of each row between them.  Every wave
+// takes the pivots of its A and B itself, from the same samples of the
+// range (so all waves holding a range agree): the median of 32 evenly
+// spaced keys (64 at the first level), or the paper's 3-value median.  The
+// compares' ballots count each class of A and B in the span; each wave
+// publishes its counts and adds them to the ranges' totals (one 64-bit LDS
+// atomic per range).  After one barrier every wave knows the totals and the
+// counts of the waves before it, and writes its keys, still in registers, in
+// place to their class's next slot: keys keep their order within a class.  Wave 0 meanwhile builds
+// the next level's live list and queues children of 2..KW keys; a second
+// barrier ends the level.
 //
 // Wave levels.  Waves take queued ranges one at a time and sort each with
 // wave_qsort.  Should the queue fill up, it is drained before the next block
@@ -209,20 +269,20 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
     constexpr int MAXACT = T / (KW + 1) + 1;  // live ranges at once
     constexpr int MAXQ = 256;                 // queued ranges
     constexpr uint32_t NONE = 0xFFu;
-    static_assert(NW * KW == T && 2 * MAXACT <= WAVE && T < 65536, "span layout");
+    static_assert(NW * KW == T && 2 * MAXACT <= WAVE && NW <= 8 && T < 65536, "span layout");
 
     __shared__ K sk[T + KW];  // one span of slack: wave_qsort reads whole rows past its range
     __shared__ uint32_t qr[MAXQ];
-    __shared__ uint32_t wl[NW][MAXACT];
-    __shared__ __align__(16) uint32_t wcnt[NW][4];
-    __shared__ uint32_t s_qnext, s_task[2];
+    __shared__ uint32_t s_live[2][MAXACT];               // live ranges of a level (b | e << 16)
+    __shared__ unsigned long long s_cnt[2][MAXACT];      // their class counts (pack_counts)
+    __shared__ unsigned long long s_wc[NW][2];           // each wave's shares of its A and B
+    __shared__ uint32_t s_na[2], s_nq, s_qnext, s_task[2];
 
     // the wave index is uniform: readfirstlane lets the compiler keep the
     // span's row masks and class bases in scalar registers
     const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const uint32_t sb = (uint32_t)w * KW;
     const uint32_t ntask = min(ctl->ntask, task_cap);
-    auto lds_rd = [&](uint32_t p) { return sk[p]; };
 
     // queued ranges [0, cnt), claimed through s_qnext, largest first when the
     // list fits a wave (every wave sorts the same claim order: (size, index)
@@ -260,10 +320,9 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
         const bool sraw = tk.src == SRC_RAW;
         auto g_rd = [&](uint32_t i) { return sraw ? raw_load<F>(raw, b + i) : sbuf[b + i]; };
 
-        // live list (lane s: packed range s and its pivot) and queue length,
-        // identical in every wave
+        // live list (lane s: packed range s) and queue length, identical in
+        // every wave
         uint32_t na = 0, nq = 0, ent = 0;
-        K pv = 0;
         // the span's rows, straight from global memory; rows past the task read
         // its last key (kept out of every class by the row masks)
         K x[KPT];
@@ -277,8 +336,7 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
         }
         if (m > (uint32_t)KW) {
             na = 1;
-            ent = m << 16;
-            pv = pick_pivot<K>(g_rd, 0, m, rule);
+            ent = lane == 0 ? m << 16 : 0u;
         } else {
             nq = 1;
             const int rem = (int)m - (int)(sb + (uint32_t)lane);
@@ -287,11 +345,14 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
                 if (j * WAVE < rem) sk[sb + (uint32_t)(j * WAVE + lane)] = x[j];
             if (tid == 0) qr[0] = m << 16;
         }
+        if (tid < 2 * MAXACT) (&s_cnt[0][0])[tid] = 0ull;
         if (tid == 0) s_qnext = 0;
         __syncthreads();
 
+        int lp = 0;            // which of the two live-list / count buffers this level uses
         bool reset_q = false;  // the queue was drained before this level
-        // one block level; FIRST: the rows are in x already
+        // one block level; FIRST: the rows are in x already and the task is
+        // the only range
         auto level = [&](auto FIRST) {
             constexpr bool first = decltype(FIRST)::value;
             const bool lv = lane < (int)na;
@@ -300,120 +361,177 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
             const uint64_t mB = ballot(lv && sb < eb && eb < sb + (uint32_t)KW);
             const uint32_t iA = mA ? (uint32_t)__builtin_ctzll(mA) : NONE;
             const uint32_t iB = mB ? (uint32_t)__builtin_ctzll(mB) : NONE;
-            uint32_t bA = 0, eA = 0, bB = 0;
-            K pA = 0, pB = 0;
+            uint32_t bA = 0, eA = 0, bB = 0, eB = 0;
             if (iA != NONE) {
                 const uint32_t t = lane_bcast(ent, (int)iA);
                 bA = t & 0xFFFFu;
                 eA = t >> 16;
-                pA = lane_bcast(pv, (int)iA);
             }
             if (iB != NONE) {
-                bB = lane_bcast(ent, (int)iB) & 0xFFFFu;
-                pB = lane_bcast(pv, (int)iB);
+                const uint32_t t = lane_bcast(ent, (int)iB);
+                bB = t & 0xFFFFu;
+                eB = t >> 16;
             }
-            // rows of the span: [0, jAf) are all A, row jAf holds A in lanes
-            // [0, kAp), row jBs holds B in lanes [kBp, 64), rows past jBs are all B
-            const uint32_t jAf = iA != NONE ? min((eA - sb) / WAVE, (uint32_t)KPT) : 0u;
-            const uint32_t kAp = (iA != NONE && eA - sb < (uint32_t)KW) ? (eA - sb) % WAVE : 0u;
-            const uint32_t jBs = iB != NONE ? (bB - sb) / WAVE : (uint32_t)KPT;
-            const uint32_t kBp = iB != NONE ? (bB - sb) % WAVE : 0u;
             if constexpr (!first) {
 #pragma unroll
                 for (int j = 0; j < KPT; ++j) x[j] = sk[sb + (uint32_t)(j * WAVE + lane)];
             }
 
-            // ---- pass 1: class counts of A and B, per lane
+            // ---- pivots of A and B (keys of the range; every wave holding a
+            //      range takes the same samples)
+            K pA = 0, pB = 0;
+            if (rule == PIVOT_MEDIAN3) {
+                if constexpr (first) {
+                    pA = med3<K>(g_rd(0), g_rd((m - 1) / 2), g_rd(m - 1));
+                } else {
+                    if (iA != NONE) pA = med3<K>(sk[bA], sk[bA + (eA - bA - 1) / 2], sk[eA - 1]);
+                    if (iB != NONE) pB = med3<K>(sk[bB], sk[bB + (eB - bB - 1) / 2], sk[eB - 1]);
+                }
+            } else if constexpr (first) {
+                K v[1] = {g_rd(((m - 1) * (uint32_t)lane) / (WAVE - 1))};
+                bitonic_wave<1>(v, lane);
+                pA = lane_bcast(v[0], WAVE / 2 - 1);
+            } else {
+                // lanes 0-31 sample A, lanes 32-63 sample B; the first five stages of
+                // the one-key network sort each half on its own
+                const bool hb = lane >= WAVE / 2;
+                const bool has = hb ? iB != NONE : iA != NONE;
+                const uint32_t rb = hb ? bB : bA, rn = hb ? eB - bB : eA - bA;
+                const uint32_t at = has ? rb + ((rn - 1) * (uint32_t)(lane & 31)) / 31u : 0u;
+                K v = sk[at];
+                bitonic_lanes<5>(v, lane);
+                pA = lane_bcast(v, 15);
+                pB = lane_bcast(v, 47);
+            }
+
+            // row j of the span (positions r0 = sb + 64 j ..): A holds its lanes
+            // [0, kA), B its lanes [kB, 64); lanes in between belong to no live
+            // range.  Both bounds are uniform, and so is every branch on them.
+            auto row_split = [&](int j, uint32_t &kA, uint32_t &kB) {
+                const uint32_t r0 = sb + (uint32_t)(j * WAVE);
+                kA = iA != NONE ? lanes_to(eA, r0) : 0u;
+                kB = iB != NONE ? lanes_to(bB, r0) : (uint32_t)WAVE;
+            };
+            // the span lies inside A (then B is absent): every row is a full A row
+            const bool fullA = iA != NONE && eA >= sb + (uint32_t)KW;
+
+            // ---- pass 1: class counts of A and B in this span
             uint32_t al = 0, aq = 0, bl = 0, bq = 0;
+            if (fullA) {
 #pragma unroll
-            for (int j = 0; j < KPT; ++j) {
-                if ((uint32_t)j < jAf) {
-                    al += (uint32_t)(x[j] < pA);
-                    aq += (uint32_t)(x[j] == pA);
-                } else if ((uint32_t)j > jBs) {
-                    bl += (uint32_t)(x[j] < pB);
-                    bq += (uint32_t)(x[j] == pB);
-                } else if ((uint32_t)j == jAf || (uint32_t)j == jBs) {
-                    const bool inA = (uint32_t)j == jAf && (uint32_t)lane < kAp;
-                    const bool inB = (uint32_t)j == jBs && (uint32_t)lane >= kBp;
-                    al += (uint32_t)(inA && x[j] < pA);
-                    aq += (uint32_t)(inA && x[j] == pA);
-                    bl += (uint32_t)(inB && x[j] < pB);
-                    bq += (uint32_t)(inB && x[j] == pB);
-                }
-            }
-            const uint32_t cA = wave_sum(al | (aq << 16)), cB = wave_sum(bl | (bq << 16));
-            if (lane == 0) *(uint4 *)&wcnt[w][0] = make_uint4(cA, cB, iA, iB);
-            __syncthreads();
-            if (reset_q && tid == 0) s_qnext = 0;  // every wave is past its drain
-            // ---- per-range totals (lane s: range s) and, for A, the counts of the
-            //      waves before this one
-            uint32_t tot = 0, pre = 0;
-#pragma unroll
-            for (int l = 0; l < NW; ++l) {
-                const uint4 c = *(const uint4 *)&wcnt[l][0];
-                const uint32_t v = (c.z == (uint32_t)lane ? c.x : 0u) + (c.w == (uint32_t)lane ? c.y : 0u);
-                tot += v;
-                pre += l < w ? v : 0u;
-            }
-            const uint32_t totA = iA != NONE ? lane_bcast(tot, (int)iA) : 0u;
-            const uint32_t preA = iA != NONE ? lane_bcast(pre, (int)iA) : 0u;
-            const uint32_t totB = iB != NONE ? lane_bcast(tot, (int)iB) : 0u;
-            // ---- children: live ones (> KW keys) form the next list, 2..KW keys are
-            //      queued (by wave 0, before the barrier that ends the level)
-            uint32_t na_n, ent_n;
-            {
-                uint32_t lb = 0, le = 0, rb = 0, re = 0;
-                if (lv) {
-                    lb = eb;
-                    le = eb + (tot & 0xFFFFu);
-                    rb = le + (tot >> 16);
-                    re = ee;
-                }
-                const bool aL = le - lb > (uint32_t)KW, aR = re - rb > (uint32_t)KW;
-                const bool qL = le - lb >= 2u && !aL, qR = re - rb >= 2u && !aR;
-                const uint32_t na_me = (uint32_t)aL + (uint32_t)aR, nq_me = (uint32_t)qL + (uint32_t)qR;
-                const uint32_t ai = wave_incl_scan(na_me), qi = wave_incl_scan(nq_me);
-                uint32_t ap = ai - na_me, qp = nq + qi - nq_me;
-                if (aL) wl[w][ap++] = lb | (le << 16);
-                if (aR) wl[w][ap] = rb | (re << 16);
-                if (w == 0) {
-                    if (qL) qr[qp++] = lb | (le << 16);
-                    if (qR) qr[qp] = rb | (re << 16);
-                }
-                na_n = lane_bcast(ai, WAVE - 1);
-                nq += lane_bcast(qi, WAVE - 1);
-                ent_n = lane < (int)na_n ? wl[w][lane] : 0u;  // this wave's own slots: no barrier
-            }
-            // ---- pass 2: every key to its class's next slot, in place
-            {
-                const uint32_t nlA = totA & 0xFFFFu, neA = totA >> 16, plA = preA & 0xFFFFu, peA = preA >> 16;
-                uint32_t aL = bA + plA, aE = bA + nlA + peA, aG = bA + nlA + neA + (sb - bA) - plA - peA;
-                const uint32_t nlB = totB & 0xFFFFu, neB = totB >> 16;
-                uint32_t gL = bB, gE = bB + nlB, gG = bB + nlB + neB;
+                for (int j = 0; j < KPT; ++j) row_count(x[j], pA, ~0ull, al, aq);
+            } else {
 #pragma unroll
                 for (int j = 0; j < KPT; ++j) {
-                    if ((uint32_t)j < jAf) {
-                        sk[row_slot(x[j], pA, aL, aE, aG, lane)] = x[j];
-                    } else if ((uint32_t)j > jBs) {
-                        sk[row_slot(x[j], pB, gL, gE, gG, lane)] = x[j];
-                    } else {
-                        if ((uint32_t)j == jAf && kAp) {
-                            const uint32_t d = row_slot_in(x[j], pA, lanes_below(kAp), 0u, aL, aE, aG, lane);
-                            if ((uint32_t)lane < kAp) sk[d] = x[j];
-                        }
-                        if ((uint32_t)j == jBs) {
-                            const uint32_t d = row_slot_in(x[j], pB, ~lanes_below(kBp), kBp, gL, gE, gG, lane);
-                            if ((uint32_t)lane >= kBp) sk[d] = x[j];
-                        }
+                    uint32_t kA, kB;
+                    row_split(j, kA, kB);
+                    if (kA) row_count(x[j], pA, lanes_below(kA), al, aq);
+                    if (kB < (uint32_t)WAVE) row_count(x[j], pB, ~lanes_below(kB), bl, bq);
+                }
+            }
+            // this wave's shares of A and B: published for the waves after it,
+            // and added to the ranges' totals
+            if (lane == 0) {
+                const unsigned long long cA = iA != NONE ? pack_counts(al, aq, min(eA, sb + (uint32_t)KW) - sb) : 0ull;
+                const unsigned long long cB = iB != NONE ? pack_counts(bl, bq, min(eB, sb + (uint32_t)KW) - bB) : 0ull;
+                s_wc[w][0] = cA;
+                s_wc[w][1] = cB;
+                if (iA != NONE) atomicAdd(&s_cnt[lp][iA], cA);
+                if (iB != NONE) atomicAdd(&s_cnt[lp][iB], cB);
+            }
+            __syncthreads();
+            if (reset_q && tid == 0) s_qnext = 0;  // every wave is past its drain
+            // the shares of A held by the waves before this one (lane l: wave l;
+            // A is the B of its first wave unless it starts at that wave's span);
+            // B starts in this span, so no earlier wave holds any of it.  Keys
+            // thus keep their order within each class: the split is stable.
+            unsigned long long preA = 0;
+            if (iA != NONE) {
+                const uint32_t wa0 = bA / (uint32_t)KW;
+                unsigned long long v = 0;
+                if ((uint32_t)lane < (uint32_t)w && (uint32_t)lane >= wa0)
+                    v = s_wc[lane][(uint32_t)lane == wa0 && bA % (uint32_t)KW != 0u ? 1 : 0];
+                v += xor_lanes<1>((uint64_t)v, lane);
+                v += xor_lanes<2>((uint64_t)v, lane);
+                v += xor_lanes<4>((uint64_t)v, lane);
+                preA = lane_bcast((uint64_t)v, 0);
+            }
+            const unsigned long long preB = 0;
+
+            // ---- class bases of this wave's share of A and B
+            uint32_t aL = 0, aE = 0, aG = 0, gL = 0, gE = 0, gG = 0;
+            bool threeA = false, threeB = false;
+            auto bases = [&](uint32_t i, uint32_t rb, uint32_t re, unsigned long long pre, bool &three,
+                             uint32_t &cl, uint32_t &ce, uint32_t &cg) {
+                const unsigned long long t = s_cnt[lp][i];
+                const uint32_t nl = (uint32_t)t & 0xFFFFu, ne = ((uint32_t)t >> 16) & 0xFFFFu;
+                const uint32_t pl = (uint32_t)pre & 0xFFFFu, pe = ((uint32_t)pre >> 16) & 0xFFFFu,
+                               pc = (uint32_t)(pre >> 32);
+                three = split_three(nl, ne, re - rb);
+                cl = rb + pl;
+                ce = rb + nl + pe;
+                cg = three ? rb + nl + ne + (pc - pl - pe) : rb + nl + (pc - pl);
+            };
+            if (iA != NONE) bases(iA, bA, eA, preA, threeA, aL, aE, aG);
+            if (iB != NONE) bases(iB, bB, eB, preB, threeB, gL, gE, gG);
+
+            // ---- next level's live list and queued children (wave 0, lane s:
+            //      range s), published before the barrier that ends the level
+            if (w == 0) {
+                uint32_t lb = 0, le = 0, rb = 0, re = 0;
+                if (lv) {
+                    const unsigned long long t = s_cnt[lp][lane];
+                    const uint32_t nl = (uint32_t)t & 0xFFFFu, ne = ((uint32_t)t >> 16) & 0xFFFFu;
+                    lb = eb;
+                    le = eb + nl;
+                    rb = split_three(nl, ne, ee - eb) ? le + ne : le;
+                    re = ee;
+                }
+                const bool aLv = le - lb > (uint32_t)KW, aRv = re - rb > (uint32_t)KW;
+                const bool qL = le - lb >= 2u && !aLv, qR = re - rb >= 2u && !aRv;
+                const uint32_t na_me = (uint32_t)aLv + (uint32_t)aRv, nq_me = (uint32_t)qL + (uint32_t)qR;
+                const uint32_t ai = wave_incl_scan(na_me), qi = wave_incl_scan(nq_me);
+                uint32_t ap = ai - na_me, qp = nq + qi - nq_me;
+                if (aLv) s_live[lp ^ 1][ap++] = lb | (le << 16);
+                if (aRv) s_live[lp ^ 1][ap] = rb | (re << 16);
+                if (qL) qr[qp++] = lb | (le << 16);
+                if (qR) qr[qp] = rb | (re << 16);
+                if (lane < MAXACT) s_cnt[lp ^ 1][lane] = 0ull;
+                if (lane == WAVE - 1) {
+                    s_na[lp ^ 1] = ai;
+                    s_nq = nq + qi;
+                }
+            }
+
+            // ---- pass 2: every key to its class's next slot, in place
+            if (fullA) {
+                if (threeA) {
+#pragma unroll
+                    for (int j = 0; j < KPT; ++j) row_place<true, true>(sk, x[j], pA, ~0ull, aL, aE, aG, lane);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < KPT; ++j) row_place<true, false>(sk, x[j], pA, ~0ull, aL, aE, aG, lane);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < KPT; ++j) {
+                    uint32_t kA, kB;
+                    row_split(j, kA, kB);
+                    if (kA) {
+                        if (threeA) row_place<false, true>(sk, x[j], pA, lanes_below(kA), aL, aE, aG, lane);
+                        else row_place<false, false>(sk, x[j], pA, lanes_below(kA), aL, aE, aG, lane);
+                    }
+                    if (kB < (uint32_t)WAVE) {
+                        if (threeB) row_place<false, true>(sk, x[j], pB, ~lanes_below(kB), gL, gE, gG, lane);
+                        else row_place<false, false>(sk, x[j], pB, ~lanes_below(kB), gL, gE, gG, lane);
                     }
                 }
             }
             __syncthreads();
-            na = na_n;
-            ent = ent_n;
-            pv = 0;
-            if (lane < (int)na) pv = pick_pivot<K>(lds_rd, ent & 0xFFFFu, ent >> 16, rule);
+            lp ^= 1;
+            na = s_na[lp];
+            nq = s_nq;
+            ent = lane < (int)na ? s_live[lp][lane] : 0u;
         };
 
         if (na) level(std::true_type{});

@@ -40,45 +40,49 @@ def pair_multiset_equal(k0, v0, k1, v1) -> bool:
     return bool(np.array_equal(a, b))
 
 
-def ninther_adversary(m: int, span: int = 1024) -> np.ndarray:
-    """int32 keys 0..m-1 arranged so that the on-chip sort's block levels
-    peel only a few keys off a live range per level.
+def median3_adversary(m: int, span: int = 1024) -> np.ndarray:
+    """int32 keys 0..m-1 arranged so that the on-chip sort's block levels,
+    run with the paper's 3-value pivot (HS_PIVOT_MEDIAN3: the median of the
+    first, middle and last key of a range, Sec. IV-A), peel only a few keys
+    off the live range per level.
 
     McIlroy's adversary ("A Killer Adversary for Quicksort", 1999): keys are
     fixed lazily, the first time the pivot rule reads them; a key not yet
-    fixed compares greater than every fixed one.  The pivot rule followed is
-    the on-chip one for ranges longer than a span: the median of three
-    medians of nine evenly spaced keys (positions b + (s-1)*i/8).  New keys
-    are fixed in the order that puts the ninther at the fourth-smallest
-    sample, so each level leaves a few keys below the pivot (a child of
-    2..span keys, queued for a wave) and the rest above it: an 8192-key task
-    takes about 900 block levels.  The block levels' three-
-    way partition is stable (each class keeps the keys' order), which is what
-    lets the construction follow the ranges from level to level.
+    fixed compares greater than every fixed one.  Each level fixes the
+    range's unfixed samples to the next smallest values, so the median is
+    one of the smallest keys of the range: the keys below it (a child of
+    2..span keys, queued for a wave) leave, the rest stays live.  The block
+    levels' split keeps the keys' order within each class (two classes, < p
+    and >= p, when some key is below the pivot and fewer than 1/32 of the
+    range equal it, else three: < p, == p, > p), which is what lets the
+    construction follow the ranges from level to level: an 8192-key task
+    takes thousands of block levels.
     """
     val = [-1] * m
     nxt = 0
     arr = list(range(m))
     live = [(0, m)]
-    rank_of_sample = [0, 1, 8, 2, 3, 7, 4, 5, 6]  # groups (0,1,8), (2,3,7), (4,5,6): medians 1, 3, 5
     while live:
         nl = []
         for b, e in live:
             s = e - b
-            pos = [b + (s - 1) * i // 8 for i in range(9)]
-            for _, el in sorted((rank_of_sample[k], arr[p]) for k, p in enumerate(pos) if val[arr[p]] < 0):
-                if val[el] < 0:
-                    val[el] = nxt
+            for p in (b, e - 1, b + (s - 1) // 2):
+                if val[arr[p]] < 0:
+                    val[arr[p]] = nxt
                     nxt += 1
-            v = [val[arr[p]] for p in pos]
-            med = [sorted(v[3 * g:3 * g + 3])[1] for g in range(3)]
-            pv = sorted(med)[1]
+            pv = sorted(val[arr[p]] for p in (b, b + (s - 1) // 2, e - 1))[1]
             seg = arr[b:e]
             lt = [x for x in seg if 0 <= val[x] < pv]
             eq = [x for x in seg if val[x] == pv]
             gt = [x for x in seg if val[x] < 0 or val[x] > pv]
-            arr[b:e] = lt + eq + gt
-            rb = b + len(lt) + len(eq)
+            if len(lt) == 0 or 32 * len(eq) >= s:
+                arr[b:e] = lt + eq + gt
+                rb = b + len(lt) + len(eq)
+            else:
+                arr[b:e] = lt + [x for x in seg if not (0 <= val[x] < pv)]
+                rb = b + len(lt)
+            if len(lt) > span:
+                nl.append((b, b + len(lt)))
             if e - rb > span:
                 nl.append((rb, e))
         live = nl

@@ -5,17 +5,17 @@
   keys is a single wave's network, leaf=512 routes it through the workgroup
   instead), one wave's span (1024 keys), a few spans, the on-chip limit
   (8192 keys);
-* an input built by McIlroy's adversary for the block levels' ninther
-  (tests/helpers.py): hundreds of block levels inside one task, each
-  queueing a small child, so the wave queue fills and is drained between
-  block levels; int32, float64 and key/value words, alone and as segments of
-  a batched sort.
+* an input built by McIlroy's adversary for the block levels run with the
+  paper's 3-value pivot (tests/helpers.py): thousands of block levels inside
+  one task, each queueing a small child, so the wave queue fills and is
+  drained between block levels; int32, float64 and key/value words, alone
+  and as segments of a batched sort.
 """
 import numpy as np
 import pytest
 
 import workloads
-from helpers import kv_index_check, ninther_adversary
+from helpers import kv_index_check, median3_adversary
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def hs():
 
 @pytest.fixture(scope="module")
 def adv():
-    return ninther_adversary(8192)
+    return median3_adversary(8192)
 
 
 def _gpu(a):
@@ -80,7 +80,7 @@ def test_adversary_forces_levels(adv):
     assert not np.all(adv[:-1] <= adv[1:])
 
 
-@pytest.mark.parametrize("pivot", [0, 2, 3])
+@pytest.mark.parametrize("pivot", [0, 1, 2, 3])
 def test_queue_drains_i32(hs, oracle_mod, adv, pivot):
     o = hs.Opts()
     o.pivot_rule = pivot
@@ -90,28 +90,39 @@ def test_queue_drains_i32(hs, oracle_mod, adv, pivot):
 
 
 def test_adversary_reaches_deep_levels(hs, adv):
-    """The adversarial task's on-chip phase runs hundreds of block levels
-    where a random task of the same size runs about four: it takes far
-    longer (a witness that the queue-draining path ran, not a timing bar)."""
+    """With the 3-value pivot, the adversarial task's on-chip phase runs
+    thousands of block levels where a random task of the same size runs
+    about four: it takes far longer (a witness that the queue-draining path
+    ran, not a timing bar)."""
+    o = hs.Opts()
+    o.pivot_rule = 1
     rnd = workloads.uniform_i32(adv.size, seed=9)
     for _ in range(2):  # warm
-        hs.sort_(_gpu(rnd))
-    t_adv = min(hs.sort_(_gpu(adv), stats=True)["local_ms"] for _ in range(3))
-    t_rnd = min(hs.sort_(_gpu(rnd), stats=True)["local_ms"] for _ in range(3))
+        hs.sort_(_gpu(rnd), opts=o)
+    t_adv = min(hs.sort_(_gpu(adv), opts=o, stats=True)["local_ms"] for _ in range(3))
+    t_rnd = min(hs.sort_(_gpu(rnd), opts=o, stats=True)["local_ms"] for _ in range(3))
     assert t_adv > 20 * t_rnd, (t_adv, t_rnd)
 
 
-def test_queue_drains_f64_and_kv(hs, oracle_mod, adv):
+@pytest.mark.parametrize("pivot", [0, 1])
+def test_queue_drains_f64_and_kv(hs, oracle_mod, adv, pivot):
+    o = hs.Opts()
+    o.pivot_rule = pivot
     f = adv.astype(np.float64) * -0.25  # reversed order, negative values and a signed zero
-    assert np.array_equal(_sort(hs, f).view(np.uint64), oracle_mod.sort_f64(f).view(np.uint64))
+    assert np.array_equal(_sort(hs, f, o).view(np.uint64), oracle_mod.sort_f64(f).view(np.uint64))
+    g = adv.astype(np.float64) * 0.25 - 1000.0  # the adversary's order, negative and positive values
+    assert np.array_equal(_sort(hs, g, o).view(np.uint64), oracle_mod.sort_f64(g).view(np.uint64))
     v = np.arange(adv.size, dtype=np.int32)
-    ko, vo = _sort_kv(hs, adv, v)
+    ko, vo = _sort_kv(hs, adv, v, o)
     assert np.array_equal(ko, oracle_mod.sort_kv_i32(adv, v)[0])
     kv_index_check(adv, ko, vo)
 
 
-def test_queue_drains_segmented(hs, oracle_mod, adv):
+@pytest.mark.parametrize("pivot", [0, 1])
+def test_queue_drains_segmented(hs, oracle_mod, adv, pivot):
     """20 adversarial tasks among 40 random segments in one batched sort."""
+    o = hs.Opts()
+    o.pivot_rule = pivot
     g = workloads.rng(77)
     parts, off = [], [0]
     for i in range(60):
@@ -121,7 +132,7 @@ def test_queue_drains_segmented(hs, oracle_mod, adv):
     keys = np.concatenate(parts)
     off = np.asarray(off, dtype=np.int64)
     t = _gpu(keys)
-    hs.sort_segmented_(t, _gpu(off))
+    hs.sort_segmented_(t, _gpu(off), opts=o)
     torch.cuda.synchronize()
     assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
 
