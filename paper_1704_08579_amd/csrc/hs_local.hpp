@@ -31,6 +31,15 @@ template <> struct LocalCfg<uint32_t> { static constexpr int T = 8192, NT = 512,
 template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 512, LEAF = 512, LW = 512, WPC = 2; };
 // 16-byte words: half the keys in the same LDS, eight rows per span.
 template <> struct LocalCfg<u128> { static constexpr int T = 4096, NT = 512, LEAF = 256, LW = 256, WPC = 2; };
+// A second shape for 8-byte words, taken when the on-chip limit is at most
+// 4096 keys: half the keys per task in half the LDS (37 KB), so four
+// workgroups share a CU, with eight rows of 64 keys per span and spans that
+// go to the 512-key network whole.
+template <typename K> struct LocalCfgHalf { static constexpr bool on = false; };
+template <> struct LocalCfgHalf<uint64_t> {
+    static constexpr bool on = true;
+    static constexpr int T = 4096, NT = 512, LEAF = 512, LW = 512, WPC = 4;
+};
 
 // Sort the keys of one wave's registers (any load order) with the smallest
 // network that holds `sz` keys, and hand back key i of the sorted order to

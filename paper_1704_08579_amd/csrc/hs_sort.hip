@@ -487,6 +487,21 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     Ctl *ctl = (Ctl *)(ws + L.ctl);
     Ctl *h = d->h_ctl;
     hipEvent_t *lev = &d->ev[2 * LMAX];  // [0,1] on-chip sort, [2..4] learned front end, [5,6] level driver
+    // the on-chip workgroup sort (single: one task, one workgroup); 8-byte
+    // words take the half-size shape when the on-chip limit allows it (four
+    // workgroups per CU instead of two)
+    auto launch_local = [&](bool single) -> int {
+        auto go = [&](auto CFG) -> int {
+            using LC = decltype(CFG);
+            HS_LAUNCH((k_local<F, LC::NT, LC::T, LC::LW, LC::WPC>), single ? 1 : d->ncu * LC::WPC, LC::NT, stream,
+                      ctl, tasks, buf[0], buf[1], raw, local_rule, L.task_cap);
+            return HS_OK;
+        };
+        if constexpr (LocalCfgHalf<K>::on) {
+            if (T <= (uint32_t)LocalCfgHalf<K>::T) return go(LocalCfgHalf<K>{});
+        }
+        return go(LocalCfg<K>{});
+    };
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HS_HIP(hipStreamIsCapturing(stream, &cap));
     const bool capturing = cap != hipStreamCaptureStatusNone;
@@ -518,11 +533,10 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     // a whole array that is one on-chip task: set-up and one workgroup, no
     // read-back (neither kernel can report an error for a single task)
     if (!learned && !d_off && (uint64_t)n <= T && (uint64_t)n > LEAF) {
-        using LC = LocalCfg<K>;
         HS_LAUNCH(k_init_one_task<F>, 1, 256, stream, ctl, tasks, (uint32_t)n);
         if (st) HS_HIP(hipEventRecord(lev[0], stream));
-        HS_LAUNCH((k_local<F, LC::NT, LC::T, LC::LW, LC::WPC>), 1, LC::NT, stream, ctl, tasks, buf[0], buf[1], raw,
-                  local_rule, L.task_cap);
+        const int rc = launch_local(true);
+        if (rc) return rc;
         if (st && !capturing) {
             HS_HIP(hipEventRecord(lev[1], stream));
             HS_HIP(hipEventSynchronize(lev[1]));
@@ -665,8 +679,8 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
         using LC = LocalCfg<K>;
         if (st) HS_HIP(hipEventRecord(lev[0], stream));
         HS_LAUNCH((k_small<F, LC::LEAF>), d->ncu * 8, 256, stream, ctl, tasks, buf[0], buf[1], raw, L.task_cap);
-        HS_LAUNCH((k_local<F, LC::NT, LC::T, LC::LW, LC::WPC>), d->ncu * LC::WPC, LC::NT, stream, ctl, tasks,
-                  buf[0], buf[1], raw, local_rule, L.task_cap);
+        const int rc = launch_local(false);
+        if (rc) return rc;
         if (st) HS_HIP(hipEventRecord(lev[1], stream));
     }
     if (capturing) return HS_OK;  // the caller checks the error word (plan entry points)
