@@ -28,7 +28,7 @@ namespace hs {
 // 32-bit words go to the network from a span (1024 keys) on.
 template <typename K> struct LocalCfg;
 template <> struct LocalCfg<uint32_t> { static constexpr int T = 8192, NT = 512, LEAF = 1024, LW = 1024, WPC = 4; };
-template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 512, LEAF = 512, LW = 512, WPC = 2; };
+template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 1024, LEAF = 512, LW = 512, WPC = 2; };
 // 16-byte words: half the keys in the same LDS, eight rows per span.
 template <> struct LocalCfg<u128> { static constexpr int T = 4096, NT = 512, LEAF = 256, LW = 256, WPC = 2; };
 // A second shape for 8-byte words, taken when the on-chip limit is at most
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
     constexpr int MAXACT = T / (KW + 1) + 1;  // live ranges at once
     constexpr int MAXQ = 256;                 // queued ranges
     constexpr uint32_t NONE = 0xFFu;
-    static_assert(NW * KW == T && 2 * MAXACT <= WAVE && NW <= 8 && T < 65536, "span layout");
+    static_assert(NW * KW == T && 2 * MAXACT <= WAVE && NW <= 16 && T < 65536, "span layout");
 
     __shared__ K sk[T + KW];  // one span of slack: wave_qsort reads whole rows past its range
     __shared__ uint32_t qr[MAXQ];
@@ -463,6 +463,7 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
                 v += xor_lanes<1>((uint64_t)v, lane);
                 v += xor_lanes<2>((uint64_t)v, lane);
                 v += xor_lanes<4>((uint64_t)v, lane);
+                if constexpr (NW > 8) v += xor_lanes<8>((uint64_t)v, lane);
                 preA = lane_bcast((uint64_t)v, 0);
             }
             const unsigned long long preB = 0;
