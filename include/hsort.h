@@ -82,7 +82,7 @@ enum { HS_PIVOT_AUTO = 0,     /* the tuned default */
        HS_PIVOT_SAMPLE = 3 }; /* global levels: lower median of 64 evenly spaced keys
                                  (ninther below 256 keys); on chip every rule but
                                  MEDIAN3 takes the lower median of 32 evenly spaced
-                                 keys (64 for a task's first split) */
+                                 keys */
 
 /* Sort methods (hs_opts.method). */
 enum { HS_METHOD_PLAIN = 0,     /* the paper's method: one pivot per partition */

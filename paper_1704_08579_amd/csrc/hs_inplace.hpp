@@ -58,10 +58,7 @@ __device__ __forceinline__ uint32_t ip_level_tiles(const Ctl *ctl, int par, cons
 template <typename K>
 __device__ __forceinline__ void ip_tile_range(const Seg<K> &sg, uint32_t t, uint32_t &p0, uint32_t &cnt)
 {
-    constexpr uint32_t TILE = PartCfg<K>::TILE;
-    const uint32_t a = sg.b / TILE + (t - sg.tile0);
-    p0 = max(sg.b, a * TILE);
-    cnt = min(sg.e, (a + 1) * TILE) - p0;
+    seg_tile_range<K>(sg.b, sg.e, sg.tile0, t, p0, cnt);
 }
 
 // Segment holding tile t (every tile holds at least one key).

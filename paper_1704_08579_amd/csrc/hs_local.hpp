@@ -252,14 +252,16 @@ __device__ __forceinline__ unsigned long long pack_counts(uint32_t nl, uint32_t 
 // wave-uniform, and so is the split of each row between them.  Every wave
 // takes the pivots of its A and B itself, from the same samples of the
 // range (so all waves holding a range agree): the median of 32 evenly
-// spaced keys (64 at the first level), or the paper's 3-value median.  The
+// spaced keys, or the paper's 3-value median.  The
 // compares' ballots count each class of A and B in the span; each wave
 // publishes its counts and adds them to the ranges' totals (one 64-bit LDS
 // atomic per range).  After one barrier every wave knows the totals and the
 // counts of the waves before it, and writes its keys, still in registers, in
-// place to their class's next slot: keys keep their order within a class.  Wave 0 meanwhile builds
-// the next level's live list and queues children of 2..KW keys; a second
-// barrier ends the level.
+// place to their class's next slot: keys keep their order within a class.
+// Wave 0 meanwhile builds the next level's live list and queues children of
+// 2..KW keys; a second barrier ends the level.  The task's rows go to LDS as
+// they are loaded and every level reads its rows from there, so one copy of
+// the level's code serves all levels.
 //
 // Wave levels.  Waves take queued ranges one at a time and sort each with
 // wave_qsort.  Should the queue fill up, it is drained before the next block
@@ -327,7 +329,6 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
         const uint32_t b = tk.b, m = tk.e - tk.b;
         const K *sbuf = tk.src == SRC_BUF0 ? buf0 : buf1;
         const bool sraw = tk.src == SRC_RAW;
-        auto g_rd = [&](uint32_t i) { return sraw ? raw_load<F>(raw, b + i) : sbuf[b + i]; };
 
         // live list (lane s: packed range s) and queue length, identical in
         // every wave
@@ -343,15 +344,17 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
 #pragma unroll
             for (int j = 0; j < KPT; ++j) x[j] = sbuf[min(g0 + (uint32_t)(j * WAVE), glast)];
         }
+        {  // the rows to LDS (every level reads its rows and pivot samples there)
+            const int rem = (int)m - (int)(sb + (uint32_t)lane);
+#pragma unroll
+            for (int j = 0; j < KPT; ++j)
+                if (j * WAVE < rem) sk[sb + (uint32_t)(j * WAVE + lane)] = x[j];
+        }
         if (m > (uint32_t)KW) {
             na = 1;
             ent = lane == 0 ? m << 16 : 0u;
         } else {
             nq = 1;
-            const int rem = (int)m - (int)(sb + (uint32_t)lane);
-#pragma unroll
-            for (int j = 0; j < KPT; ++j)
-                if (j * WAVE < rem) sk[sb + (uint32_t)(j * WAVE + lane)] = x[j];
             if (tid == 0) qr[0] = m << 16;
         }
         if (tid < 2 * MAXACT) (&s_cnt[0][0])[tid] = 0ull;
@@ -360,10 +363,9 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
 
         int lp = 0;            // which of the two live-list / count buffers this level uses
         bool reset_q = false;  // the queue was drained before this level
-        // one block level; FIRST: the rows are in x already and the task is
-        // the only range
-        auto level = [&](auto FIRST) {
-            constexpr bool first = decltype(FIRST)::value;
+        // one block level (one copy of its code serves every level: the
+        // kernel's hot code stays within the instruction cache)
+        auto level = [&]() {
             const bool lv = lane < (int)na;
             const uint32_t eb = ent & 0xFFFFu, ee = ent >> 16;
             const uint64_t mA = ballot(lv && eb <= sb && sb < ee);
@@ -381,25 +383,16 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
                 bB = t & 0xFFFFu;
                 eB = t >> 16;
             }
-            if constexpr (!first) {
+            // the span's rows
 #pragma unroll
-                for (int j = 0; j < KPT; ++j) x[j] = sk[sb + (uint32_t)(j * WAVE + lane)];
-            }
+            for (int j = 0; j < KPT; ++j) x[j] = sk[sb + (uint32_t)(j * WAVE + lane)];
 
             // ---- pivots of A and B (keys of the range; every wave holding a
             //      range takes the same samples)
             K pA = 0, pB = 0;
             if (rule == PIVOT_MEDIAN3) {
-                if constexpr (first) {
-                    pA = med3<K>(g_rd(0), g_rd((m - 1) / 2), g_rd(m - 1));
-                } else {
-                    if (iA != NONE) pA = med3<K>(sk[bA], sk[bA + (eA - bA - 1) / 2], sk[eA - 1]);
-                    if (iB != NONE) pB = med3<K>(sk[bB], sk[bB + (eB - bB - 1) / 2], sk[eB - 1]);
-                }
-            } else if constexpr (first) {
-                K v[1] = {g_rd(((m - 1) * (uint32_t)lane) / (WAVE - 1))};
-                bitonic_wave<1>(v, lane);
-                pA = lane_bcast(v[0], WAVE / 2 - 1);
+                if (iA != NONE) pA = med3<K>(sk[bA], sk[bA + (eA - bA - 1) / 2], sk[eA - 1]);
+                if (iB != NONE) pB = med3<K>(sk[bB], sk[bB + (eB - bB - 1) / 2], sk[eB - 1]);
             } else {
                 // lanes 0-31 sample A, lanes 32-63 sample B; the first five stages of
                 // the one-key network sort each half on its own
@@ -544,14 +537,13 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
             ent = lane < (int)na ? s_live[lp][lane] : 0u;
         };
 
-        if (na) level(std::true_type{});
         while (na) {
             reset_q = nq + 2u * MAXACT > (uint32_t)MAXQ;
             if (reset_q) {  // make room: sort what is queued
                 drain(nq);
                 nq = 0;
             }
-            level(std::false_type{});
+            level();
         }
         drain(nq);
         __syncthreads();
