@@ -1165,6 +1165,12 @@ __global__ void k_zero_words(uint32_t *p, uint32_t nwords)
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+// *p = v (one word of the control block, from the host's stream order).
+__global__ void k_set_word(uint32_t *p, uint32_t v)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+
 // v[i] = i (the indices an argsort carries as values).
 __global__ void k_iota(int32_t *v, uint32_t n)
 {

@@ -293,7 +293,10 @@ __global__ __launch_bounds__(NT, WPC * NT / 256) void k_local(Ctl *ctl, const Ta
     // span's row masks and class bases in scalar registers
     const int tid = threadIdx.x, lane = lane_id(), w = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const uint32_t sb = (uint32_t)w * KW;
-    const uint32_t ntask = min(ctl->ntask, task_cap);
+    // tasks are claimed from ctl->task_next on (a second launch after more
+    // partition levels starts where the first one's tasks ended); nothing is
+    // sorted once a partition level has flagged an error
+    const uint32_t ntask = ctl->err ? 0u : min(ctl->ntask, task_cap);
 
     // queued ranges [0, cnt), claimed through s_qnext, largest first when the
     // list fits a wave (every wave sorts the same claim order: (size, index)
@@ -606,16 +609,22 @@ __global__ __launch_bounds__(256) void k_init_one_task(Ctl *ctl, Task<typename K
 // 16 keys, one wave sorts them together, a quarter of its lanes each (the
 // network's first four stages stay inside 16-lane groups); when they fit 32
 // keys, two at a time on half-waves; otherwise one after another.
+//
+// small_first: the small tasks before it are done already (a second launch
+// after more partition levels sorts only the tasks they added).  Nothing is
+// sorted once a partition level has flagged an error.
 template <int F, int LEAF>
 __global__ __launch_bounds__(256) void k_small(const Ctl *ctl, const Task<typename KeyOf<F>::type> *tasks,
                                                const typename KeyOf<F>::type *buf0,
-                                               const typename KeyOf<F>::type *buf1, Raw raw, uint32_t task_cap)
+                                               const typename KeyOf<F>::type *buf1, Raw raw, uint32_t task_cap,
+                                               uint32_t small_first)
 {
     using K = typename KeyOf<F>::type;
     const int lane = lane_id();
-    const uint32_t nsmall = min(ctl->nsmall, task_cap);
+    const uint32_t nall = ctl->err ? 0u : min(ctl->nsmall, task_cap);
+    const uint32_t nsmall = nall > small_first ? nall - small_first : 0u;
     const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
-    auto task_at = [&](uint32_t i) { return tasks[task_cap - 1 - i]; };
+    auto task_at = [&](uint32_t i) { return tasks[task_cap - 1 - small_first - i]; };
     auto ld = [&](const Task<K> &tk, uint32_t j) {
         return tk.src == SRC_RAW ? raw_load<F>(raw, tk.b + j) : (tk.src == SRC_BUF0 ? buf0 : buf1)[tk.b + j];
     };

@@ -652,39 +652,81 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
                   buf[1], raw, tasks, T, LEAF, rule, guard, first, LMAX, L.cand_cap, L.task_cap,
                   (o && o->spin_limit > 0) ? (uint32_t)o->spin_limit : BARRIER_SPIN_LIMIT);
         if (st) HS_HIP(hipEventRecord(lev[6], stream));
-    } else {
-        // host-driven levels: batches of fixed-grid launches, one read-back per batch
+    }
+    // on-chip sorts: fixed grids, the task counts are read on the device
+    // (small_first: small tasks already sorted by an earlier launch)
+    auto run_onchip = [&](uint32_t small_first) -> int {
+        using LC = LocalCfg<K>;
+        if (st) HS_HIP(hipEventRecord(lev[0], stream));
+        HS_LAUNCH((k_small<F, LC::LEAF>), d->ncu * 8, 256, stream, ctl, tasks, buf[0], buf[1], raw, L.task_cap,
+                  small_first);
+        const int rc = launch_local(false);
+        if (rc) return rc;
+        if (st) HS_HIP(hipEventRecord(lev[1], stream));
+        return HS_OK;
+    };
+    // the control block as it is after the on-chip sorts is in h already
+    bool have_final = false;
+    if (host_driver) {
+        // host-driven levels: batches of fixed-grid launches.  For a single
+        // array the first batch runs the levels balanced splits would need plus
+        // three (sampled pivots spread the segment sizes; a level with an empty
+        // list exits at once) and the on-chip sorts follow it at once, before
+        // any read-back: one read-back then usually ends the call.  Should
+        // levels remain, further batches run with a read-back each, and the
+        // on-chip sorts run again over the tasks the new levels added.
         int level = level0;
-        // the first batch runs the levels balanced splits would need plus
-        // three: sampled pivots spread the segment sizes, so a second batch
-        // (and its read-back) usually follows otherwise, while a level with an
-        // empty list exits at once
-        int batch = (!learned && !d_off && (uint64_t)n > T) ? levels_for((uint64_t)n, T) + 3 : 0;
-        for (;;) {
-            for (int bi = 0; bi < batch && level < LMAX; ++bi, ++level) {
+        int batch = 0;
+        uint32_t ntask_done = 0, nsmall_done = 0;
+        bool sorted_some = false;
+        if (!learned && !d_off && (uint64_t)n > T) {
+            for (int bi = 0, nb = levels_for((uint64_t)n, T) + 3; bi < nb && level < LMAX; ++bi, ++level) {
                 const int rc = launch_level(level);
                 if (rc) return rc;
             }
+            const int rc = run_onchip(0);
+            if (rc) return rc;
+            sorted_some = true;
             HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
             HS_HIP(hipStreamSynchronize(stream));
             if (h->err) return fail(HS_EINTERNAL, "partition levels reported error bits 0x%x", h->err);
             const LevelCounts &lc = h->lev[level & 1];
-            if ((uint32_t)lc.segs_tiles == 0) break;
-            if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
-            batch = levels_for(lc.max_seg, T);
+            if ((uint32_t)lc.segs_tiles == 0) {
+                have_final = true;
+            } else {
+                if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
+                batch = levels_for(lc.max_seg, T);
+                ntask_done = h->ntask;
+                nsmall_done = h->nsmall;
+            }
         }
-    }
-    // on-chip sorts: fixed grids, the task counts are read on the device
-    {
-        using LC = LocalCfg<K>;
-        if (st) HS_HIP(hipEventRecord(lev[0], stream));
-        HS_LAUNCH((k_small<F, LC::LEAF>), d->ncu * 8, 256, stream, ctl, tasks, buf[0], buf[1], raw, L.task_cap);
-        const int rc = launch_local(false);
+        if (!have_final) {
+            for (;;) {
+                for (int bi = 0; bi < batch && level < LMAX; ++bi, ++level) {
+                    const int rc = launch_level(level);
+                    if (rc) return rc;
+                }
+                HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+                HS_HIP(hipStreamSynchronize(stream));
+                if (h->err) return fail(HS_EINTERNAL, "partition levels reported error bits 0x%x", h->err);
+                const LevelCounts &lc = h->lev[level & 1];
+                if ((uint32_t)lc.segs_tiles == 0) break;
+                if (level >= LMAX) return fail(HS_EINTERNAL, "more than %d partition levels", LMAX);
+                batch = levels_for(lc.max_seg, T);
+            }
+            // the on-chip sort claims tasks from task_next: the earlier launch's
+            // tasks end at ntask_done
+            if (sorted_some)
+                HS_LAUNCH(k_set_word, 1, 64, stream, &ctl->task_next, ntask_done);
+            const int rc = run_onchip(nsmall_done);
+            if (rc) return rc;
+        }
+    } else {
+        const int rc = run_onchip(0);
         if (rc) return rc;
-        if (st) HS_HIP(hipEventRecord(lev[1], stream));
     }
     if (capturing) return HS_OK;  // the caller checks the error word (plan entry points)
-    HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    if (!have_final) HS_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     float loss = 0.f;
     if (st) {
         if (learned) HS_HIP(hipMemcpyAsync(d->h_lctl, lctl, sizeof(LearnCtl), hipMemcpyDeviceToHost, stream));

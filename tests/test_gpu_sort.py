@@ -297,6 +297,40 @@ def test_drivers_bit_exact(hs, oracle_mod, driver):
     assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
 
 
+def _levels_for(size, T):
+    """Levels that balanced splits need to bring `size` keys down to T."""
+    lv = 1
+    while size > T:
+        size = (size + 1) // 2
+        lv += 1
+    return lv
+
+
+def test_host_driver_levels_beyond_first_batch(hs, oracle_mod):
+    """The host-driven loop runs a first batch of levels and the on-chip
+    sorts before its first read-back; skewed splits (median-of-3 pivots on an
+    adversarial order, a small on-chip limit) leave levels after that batch,
+    which then run with the on-chip sorts a second time over the tasks they
+    add.  The output must match the oracle, values riding along too."""
+    n, T = 1 << 18, 600
+    x = _adversarial(n, 3)["organ_pipe"]
+    t = _gpu(x)
+    st = hs.sort_(t, opts=_driver_opts(hs, 1, local_T=T, pivot=1), stats=True)
+    assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_i32(x))
+    assert st["passes"] > _levels_for(n, T) + 3, st["passes"]
+    v = np.arange(n, dtype=np.int32)
+    k, vv = _gpu(x), _gpu(v)
+    hs.sort_kv_(k, vv, opts=_driver_opts(hs, 1, local_T=T, pivot=1))
+    ko, vo = k.cpu().numpy(), vv.cpu().numpy()
+    assert np.array_equal(ko, oracle_mod.sort_kv_i32(x, v)[0])
+    kv_index_check(x, ko, vo)
+    f = x.astype(np.float64) * -0.5
+    t = _gpu(f)
+    st = hs.sort_(t, opts=_driver_opts(hs, 1, local_T=T, pivot=1), stats=True)
+    assert np.array_equal(t.cpu().numpy().view(np.uint64), oracle_mod.sort_f64(f).view(np.uint64))
+    assert st["passes"] > _levels_for(n, T) + 3, st["passes"]
+
+
 def test_persistent_driver_barrier_timeout_is_reported(hs):
     """A grid-barrier wait capped at one poll (forced from the host) ends the
     level driver with an error instead of waiting: the call fails cleanly and
