@@ -48,6 +48,8 @@ CONFIGS = {
     "f64_2e27": ("f64", 1 << 27, ["uniform", "normal", "sorted", "reverse"], 2,
                  "sort_f64, 2^27 float64 keys x 4 distributions (uniform [0,1), N(0,1), sorted, reverse)"),
     "i32_2e20": ("i32", 1 << 20, None, 1, "sort_i32, 2^20 int32 keys uniform over the full range"),
+    "i32_2e20_plan": ("i32", 1 << 20, None, 1,
+                      "sort_i32, 2^20 int32 keys uniform over the full range, one graph replay (hs_plan_exec)"),
     "kvf64_2e27": ("kvf64", 1 << 27, None, 6,
                    "sort_kv_f64, 2^27 (float64 key, int32 value) pairs, 2^16 distinct N(0,1) keys, "
                    "values = original index"),
@@ -76,11 +78,14 @@ CONFIGS = {
 
 HEADLINE = "i32_2e28"
 # measured beside the headline in a default run
-BESIDE = ["f64_2e28", "kv_2e28", "plain_2e28_lognormal", "learned_2e28_lognormal", "seg_A", "i32_2e20", "f64_2e27"]
+BESIDE = ["f64_2e28", "kv_2e28", "plain_2e28_lognormal", "learned_2e28_lognormal", "seg_A", "i32_2e20",
+          "i32_2e20_plan", "f64_2e27"]
 # measured too with --extra
 EXTRA = ["kvf64_2e27", "seg_B", "learned_2e28", "sampled_2e28_learned_inputs", "plain_2e28_learned_inputs",
          "f64_2e27_inplace", "i32_2e28_inplace"]
 
+# configurations sorted by replaying a graph plan of a single array
+PLANNED = {"i32_2e20_plan"}
 # configurations sorted with the partition levels in place
 INPLACE = {"f64_2e27_inplace", "i32_2e28_inplace"}
 # configurations sorted with the learned-splitter method: name -> learn_flags
@@ -244,6 +249,12 @@ def run_workload(name, steps, warmup, driver=0, stat_runs=3):
         graph = dict(tune_report=report, tune_s=round(tune_s, 2),
                      knobs=dict(local_T=tuned.local_T, leaf=tuned.leaf, pivot_rule=tuned.pivot_rule))
         stat_opts = tuned
+    elif name in PLANNED:
+        c = cases[0]
+        c.restore()
+        c.plan = hs.Plan(c.work)
+        graph = dict(plan="hs_plan_create / hs_plan_exec, default knobs")
+        stat_opts = opts
     else:
         stat_opts = opts
     ev0 = torch.cuda.Event(enable_timing=True)
