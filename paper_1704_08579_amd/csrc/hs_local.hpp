@@ -19,13 +19,15 @@ namespace hs {
 // LEAF: the largest task sorted by one wave straight from global memory
 // (k_small); LW: the largest range a wave of k_local hands to the bitonic
 // network (larger ones are partitioned first); WPC: workgroups resident per
-// CU (LDS: 160 KB per CU; registers: 16 waves per CU keep the 128-VGPR
-// budget that a span of keys per lane needs).  A wave partition level costs
-// about 25 lane operations per key, the network's in-register layers 1
-// (32-bit words: a min/max pair) or 2.5 (64-bit words) per key and layer, so
-// halving a range saves the network fewer operations than the level costs
-// down to 512 keys for 64-bit words (measured: 512 beats 256 and 128), and
-// 32-bit words go to the network from a span (1024 keys) on.
+// CU (LDS: 160 KB per CU; WPC * NT / 256 waves per SIMD, which sets the VGPR
+// budget: 8 waves, 64 VGPRs, for int32 and 8-byte words).  A wave partition
+// level costs about 25 lane operations per key, the network's in-register
+// layers 1 (32-bit words: a min/max pair) or 2.5 (64-bit words) per key and
+// layer, so halving a range saves the network fewer operations than the
+// level costs down to 512 keys for 64-bit words (measured: 512 beats 256 and
+// 128), and 32-bit words go to the network from a span (1024 keys) on.
+// 8-byte words: 1024-thread workgroups with spans of 512 keys (two per CU:
+// the LDS of two 8192-key tasks), 5% faster than 512-thread ones.
 template <typename K> struct LocalCfg;
 template <> struct LocalCfg<uint32_t> { static constexpr int T = 8192, NT = 512, LEAF = 1024, LW = 1024, WPC = 4; };
 template <> struct LocalCfg<uint64_t> { static constexpr int T = 8192, NT = 1024, LEAF = 512, LW = 512, WPC = 2; };
