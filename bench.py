@@ -27,6 +27,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import platform
 import statistics
@@ -259,18 +260,34 @@ def run_workload(name, steps, warmup, driver=0, stat_runs=3):
         stat_opts = opts
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    # the copy ceiling: the device copy that restores the first array's input
+    # (reads and writes its bytes once), best of five
+    copy_ms = []
+    for _ in range(5):
+        ev0.record()
+        cases[0].restore()
+        ev1.record()
+        ev1.synchronize()
+        copy_ms.append(ev0.elapsed_time(ev1))
+    c0 = cases[0]
+    copy_bytes = 2 * (c0.src.numel() * c0.src.element_size() +
+                      (c0.vsrc.numel() * c0.vsrc.element_size() if c0.vsrc is not None else 0))
+    copy_gbs = copy_bytes / (min(copy_ms) * 1e-3) / 1e9
     step_ms = []
+    case_ms = [[] for _ in cases]
     torch.cuda.synchronize()
     for step in range(warmup + steps):
         timed = step >= warmup
         ms_step = 0.0
-        for c in cases:
+        for ci, c in enumerate(cases):
             c.restore()
             ev0.record()
             c.sort(hs, opts, False)
             ev1.record()
             ev1.synchronize()
             ms_step += ev0.elapsed_time(ev1)
+            if timed:
+                case_ms[ci].append(ev0.elapsed_time(ev1))
             if c.plan is not None:
                 c.plan.check()
             if step == warmup:
@@ -310,7 +327,28 @@ def run_workload(name, steps, warmup, driver=0, stat_runs=3):
                     learn_ms=st["learn_ms"], multiway_ms=st["multiway_ms"], fallback_used=st["fallback_used"],
                     splitters=st["splitters"], model_imbalance=st["model_imbalance"],
                     sample_imbalance=st["sample_imbalance"], final_loss=st["final_loss"],
-                    bytes_per_key=st["bytes_alg"] / c.n))
+                    bytes_per_key=st["bytes_alg"] / c.n,
+                    gkeys_without_front_end=c.n / ((statistics.median(case_ms[cases.index(c)]) - st["learn_ms"])
+                                                   * 1e-3) / 1e9))
+    if graph is not None and CONFIGS[name][0] == "seg":
+        # the plain comparison of a batched sort: one hs_sort_i32 call per array,
+        # over the first 2000 arrays
+        c = cases[0]
+        c.restore()
+        off = c.host[1]
+        ks = 0
+        torch.cuda.synchronize()
+        ev0.record()
+        for i in range(min(2000, len(off) - 1)):
+            a, b = int(off[i]), int(off[i + 1])
+            if b - a >= 2:
+                hs.sort_(c.work[a:b])
+            ks += b - a
+        ev1.record()
+        ev1.synchronize()
+        graph["eager_loop"] = dict(arrays=min(2000, len(off) - 1), keys=ks,
+                                   gkeys_per_s=round(ks / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 3),
+                                   what="one hs_sort_i32 call per array, the first arrays of the batch")
     keys_step = sum(c.n for c in cases)
     s = cases[0].s
     med = statistics.median(step_ms)
@@ -333,6 +371,8 @@ def run_workload(name, steps, warmup, driver=0, stat_runs=3):
                    gbs=2 * s * acc["local_keys"] / (acc["local_ms"] * 1e-3) / 1e9 if acc["local_ms"] > 0 else 0.0),
         graph=graph,
         learned={d: {k: round(sum(r[k] for r in v) / len(v), 4) for k in v[0]} for d, v in learn.items()} or None,
+        copy_gbs=copy_gbs,
+        ideal_bytes_per_key=ideal_bytes_per_key(name, s),
     )
     for c in cases:
         if c.plan is not None:
@@ -341,6 +381,18 @@ def run_workload(name, steps, warmup, driver=0, stat_runs=3):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     return out
+
+
+def ideal_bytes_per_key(name, s):
+    """Bytes per key of a plain sort with perfect splits: 2 s per level,
+    ceil(log2(n / T)) levels, plus the on-chip sort (T: the on-chip limit),
+    for a single array sorted by the plain method; None otherwise."""
+    kind, n = CONFIGS[name][0], CONFIGS[name][1]
+    if kind == "seg" or name in LEARNED:
+        return None
+    T = 4096 if kind == "kvf64" else 8192
+    levels = max(0, math.ceil(math.log2(n / T)))
+    return 2 * s * (levels + 1)
 
 
 def summary(r):
@@ -353,7 +405,12 @@ def summary(r):
          "partition_gbs": round(r["partition"]["gbs"], 1),
          "partition_ms_per_step": round(r["partition"]["ms_per_step"], 3),
          "local_sort_ms_per_step": round(r["local"]["ms_per_step"], 3),
-         "levels_per_sort": round(r["levels_per_sort"], 2), "output_checked": True}
+         "levels_per_sort": round(r["levels_per_sort"], 2), "output_checked": True,
+         "copy_ceiling_gbs": round(r["copy_gbs"], 1)}
+    if r["ideal_bytes_per_key"]:
+        d["ideal_bytes_per_key"] = r["ideal_bytes_per_key"]
+    if CONFIGS[r["name"]][1] * r["elem_bytes"] <= (8 << 20):
+        d["note"] = "the input fits the on-chip caches (L2 and MALL): the roofline fractions are not HBM figures"
     if r["learned"]:
         d["per_distribution"] = r["learned"]
     if r["graph"]:
@@ -557,6 +614,7 @@ def main():
                    "local_sort_ms_per_step": round(r["local"]["ms_per_step"], 3),
                    "partition_ms_per_step": round(p["ms_per_step"], 3),
                    "partition_launches_per_step": p["launches_per_step"],
+                   "ideal_bytes_per_key": r["ideal_bytes_per_key"],
                    "output_checked": True},
         "roofline": {"bound": "hbm",
                      "kernel": ("k_levels (every partition level of a sort in one persistent launch)" if persistent
@@ -566,7 +624,9 @@ def main():
                      "traffic": measured_traffic(args.config, kernel),
                      "bytes_per_launch": round(p["bytes_per_launch"]),
                      "avg_launch_ms": round(p["avg_launch_ms"], 4),
-                     "whole_sort_frac": round(r["whole_sort_roofline"], 4)},
+                     "whole_sort_frac": round(r["whole_sort_roofline"], 4),
+                     "copy_ceiling_gbs": round(r["copy_gbs"], 1),
+                     "frac_of_copy_ceiling": round(p["gbs"] / r["copy_gbs"], 4)},
         "cpu_baseline": cpu,
     }
     if r["learned"]:
