@@ -77,113 +77,12 @@ __device__ __forceinline__ void wave_sort(uint32_t sz, int lane, const Ld &ld, c
     }
 }
 
-// Three-way partition of one row of keys against pivot p (Sec. III-B, with
-// an equal class, as the on-chip levels use it): the slot of a lane's key is
-// its class's running base plus the number of lanes of that class below it,
-// and the bases advance by the class counts.  row_slot takes a full row;
-// row_slot_in a row whose range holds the lanes of mask mk, k0 being the
-// lowest of them.  The class masks are the compares' ballots, so the
-// bookkeeping is scalar and one ds_write per row places 64 keys.
-template <typename K>
-__device__ __forceinline__ uint32_t row_slot(K x, K p, uint32_t &cl, uint32_t &ce, uint32_t &cg, int lane)
-{
-    const uint64_t ml = ballot(x < p), mq = ballot(x == p);
-    const uint32_t rl = mask_below(ml), rq = mask_below(mq);
-    const uint32_t d = lane_select(ml, cl + rl, lane_select(mq, ce + rq, cg + ((uint32_t)lane - rl - rq)));
-    const uint32_t nl = popc(ml), nq = popc(mq);
-    cl += nl;
-    ce += nq;
-    cg += (uint32_t)WAVE - nl - nq;
-    return d;
-}
-template <typename K>
-__device__ __forceinline__ uint32_t row_slot_in(K x, K p, uint64_t mk, uint32_t k0, uint32_t &cl, uint32_t &ce,
-                                                uint32_t &cg, int lane)
-{
-    const uint64_t ml = ballot(x < p) & mk, mq = ballot(x == p) & mk;
-    const uint32_t rl = mask_below(ml), rq = mask_below(mq);
-    const uint32_t d = lane_select(ml, cl + rl, lane_select(mq, ce + rq, cg + ((uint32_t)lane - k0 - rl - rq)));
-    const uint32_t nl = popc(ml), nq = popc(mq);
-    cl += nl;
-    ce += nq;
-    cg += popc(mk) - nl - nq;
-    return d;
-}
-
-// One wave sorts sk[b, e) (at most KR rows of 64 keys; the array has KR*64
-// keys of slack past the task, so a row read past e stays in bounds).  A
-// range longer than LW is partitioned three ways with its keys held in
-// registers (row j: positions b + 64 j + lane): a first pass counts the
-// classes in per-lane counters, a second writes each key in place to its
-// slot (every key of the range is in registers before the first write).
-// Ranges of at most LW keys go through the bitonic network.  Pending ranges
-// sit on a stack held across the lanes of one register (entry i in lane i);
-// children that need the network are pushed last, so they are taken before
-// any other partition, and the stack only ever holds disjoint ranges longer
-// than LW, plus two.
-template <int KR, int LW, typename K>
-__device__ __forceinline__ void wave_qsort(K *sk, uint32_t b, uint32_t e, int rule, int lane)
-{
-    static_assert(LW >= WAVE && KR * WAVE / (LW + 1) + 2 <= WAVE, "the stack of pending ranges fits one register");
-    uint32_t stk = 0;
-    int sp = 0;
-    for (;;) {
-        b = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);  // uniform: row masks stay scalar
-        e = (uint32_t)__builtin_amdgcn_readfirstlane((int)e);
-        const uint32_t s = e - b;
-        if (LW >= KR * WAVE || s <= (uint32_t)LW) {
-            if (s >= 2)
-                wave_sort<LW, K>(s, lane, [&](uint32_t q) { return sk[b + q]; },
-                                 [&](uint32_t q, K v) { sk[b + q] = v; });
-        } else if constexpr (LW < KR * WAVE) {
-            const K p = pick_pivot<K>([&](uint32_t i) { return sk[i]; }, b, e, rule);
-            const uint32_t nf = s / WAVE, kp = s % WAVE;  // full rows; lanes of the last, partial row
-            K x[KR];
-            // every load first, in groups of four rows
-#pragma unroll
-            for (int g = 0; g < KR / 4; ++g)
-                if (g == 0 || (uint32_t)(g * 4 * WAVE) < s)
-#pragma unroll
-                    for (int j = g * 4; j < g * 4 + 4; ++j) x[j] = sk[b + (uint32_t)(j * WAVE + lane)];
-            uint32_t vl = 0, vq = 0;
-#pragma unroll
-            for (int j = 0; j < KR; ++j) {
-                if ((uint32_t)j < nf) {
-                    vl += (uint32_t)(x[j] < p);
-                    vq += (uint32_t)(x[j] == p);
-                } else if ((uint32_t)j == nf) {
-                    const bool in = (uint32_t)lane < kp;
-                    vl += (uint32_t)(in && x[j] < p);
-                    vq += (uint32_t)(in && x[j] == p);
-                }
-            }
-            const uint32_t c = wave_sum(vl | (vq << 16));
-            const uint32_t nl = c & 0xFFFFu, ne = c >> 16;
-            uint32_t cl = b, ce = b + nl, cg = b + nl + ne;
-#pragma unroll
-            for (int j = 0; j < KR; ++j) {
-                if ((uint32_t)j < nf) {
-                    sk[row_slot(x[j], p, cl, ce, cg, lane)] = x[j];
-                } else if ((uint32_t)j == nf && kp) {
-                    const uint32_t d = row_slot_in(x[j], p, lanes_below(kp), 0u, cl, ce, cg, lane);
-                    if ((uint32_t)lane < kp) sk[d] = x[j];
-                }
-            }
-            const uint32_t le = b + nl, rb = le + ne;
-            const uint32_t pl = b | (le << 16), pr = rb | (e << 16);
-            const bool bl = nl > (uint32_t)LW, br = e - rb > (uint32_t)LW;
-            auto push = [&](uint32_t v) { stk = lane == sp ? v : stk; ++sp; };
-            if (bl) push(pl);
-            if (br) push(pr);
-            if (!bl && nl >= 2) push(pl);
-            if (!br && e - rb >= 2) push(pr);
-        }
-        if (sp == 0) return;
-        const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)stk, --sp);
-        b = t & 0xFFFFu;
-        e = t >> 16;
-    }
-}
+// Partition of one row of keys against pivot p (Sec. III-B; on chip with an
+// equal class when the range calls for it): the slot of a lane's key is its
+// class's running base plus the number of lanes of that class below it, and
+// the bases advance by the class counts.  The class masks are the compares'
+// ballots, so the bookkeeping is scalar and one ds_write per row places 64
+// keys.
 
 // Lanes of the row starting at position r0 that lie before position e.
 __device__ __forceinline__ uint32_t lanes_to(uint32_t e, uint32_t r0)
@@ -241,6 +140,69 @@ __device__ __forceinline__ bool split_three(uint32_t nl, uint32_t ne, uint32_t m
 __device__ __forceinline__ unsigned long long pack_counts(uint32_t nl, uint32_t ne, uint32_t c)
 {
     return (unsigned long long)(nl | (ne << 16)) | ((unsigned long long)c << 32);
+}
+
+// One wave sorts sk[b, e) (at most KR rows of 64 keys; the array has KR*64
+// keys of slack past the task, so a row read past e stays in bounds).  A
+// range longer than LW is partitioned three ways with its keys held in
+// registers (row j: positions b + 64 j + lane): a first pass counts the
+// classes from the compares' ballots, a second writes each key in place to
+// its slot (every key of the range is in registers before the first write).
+// Ranges of at most LW keys go through the bitonic network.  Pending ranges
+// sit on a stack held across the lanes of one register (entry i in lane i);
+// children that need the network are pushed last, so they are taken before
+// any other partition, and the stack only ever holds disjoint ranges longer
+// than LW, plus two.
+template <int KR, int LW, typename K>
+__device__ __forceinline__ void wave_qsort(K *sk, uint32_t b, uint32_t e, int rule, int lane)
+{
+    static_assert(LW >= WAVE && KR * WAVE / (LW + 1) + 2 <= WAVE, "the stack of pending ranges fits one register");
+    uint32_t stk = 0;
+    int sp = 0;
+    for (;;) {
+        b = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);  // uniform: row masks stay scalar
+        e = (uint32_t)__builtin_amdgcn_readfirstlane((int)e);
+        const uint32_t s = e - b;
+        if (LW >= KR * WAVE || s <= (uint32_t)LW) {
+            if (s >= 2)
+                wave_sort<LW, K>(s, lane, [&](uint32_t q) { return sk[b + q]; },
+                                 [&](uint32_t q, K v) { sk[b + q] = v; });
+        } else if constexpr (LW < KR * WAVE) {
+            const K p = pick_pivot<K>([&](uint32_t i) { return sk[i]; }, b, e, rule);
+            const uint32_t nf = s / WAVE, kp = s % WAVE;  // full rows; lanes of the last, partial row
+            K x[KR];
+            // every load first, in groups of four rows
+#pragma unroll
+            for (int g = 0; g < KR / 4; ++g)
+                if (g == 0 || (uint32_t)(g * 4 * WAVE) < s)
+#pragma unroll
+                    for (int j = g * 4; j < g * 4 + 4; ++j) x[j] = sk[b + (uint32_t)(j * WAVE + lane)];
+            uint32_t nl = 0, ne = 0;
+#pragma unroll
+            for (int j = 0; j < KR; ++j) {
+                if ((uint32_t)j < nf) row_count(x[j], p, ~0ull, nl, ne);
+                else if ((uint32_t)j == nf && kp) row_count(x[j], p, lanes_below(kp), nl, ne);
+            }
+            uint32_t cl = b, ce = b + nl, cg = b + nl + ne;
+#pragma unroll
+            for (int j = 0; j < KR; ++j) {
+                if ((uint32_t)j < nf) row_place<true, true>(sk, x[j], p, ~0ull, cl, ce, cg, lane);
+                else if ((uint32_t)j == nf && kp) row_place<false, true>(sk, x[j], p, lanes_below(kp), cl, ce, cg, lane);
+            }
+            const uint32_t le = b + nl, rb = le + ne;
+            const uint32_t pl = b | (le << 16), pr = rb | (e << 16);
+            const bool bl = nl > (uint32_t)LW, br = e - rb > (uint32_t)LW;
+            auto push = [&](uint32_t v) { stk = lane == sp ? v : stk; ++sp; };
+            if (bl) push(pl);
+            if (br) push(pr);
+            if (!bl && nl >= 2) push(pl);
+            if (!br && e - rb >= 2) push(pr);
+        }
+        if (sp == 0) return;
+        const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)stk, --sp);
+        b = t & 0xFFFFu;
+        e = t >> 16;
+    }
 }
 
 // One workgroup per task of LEAF+1 .. T keys, claimed dynamically (the next
