@@ -473,6 +473,8 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     const uint32_t T = local_limit<K>(o);
     const uint32_t LEAF = leaf_limit<K>(o);
     const int rule = pivot_rule(o);
+    // on chip, MEDIAN3 takes the 3-value median and every other rule the
+    // median of 32 samples
     const int local_rule = (o && o->pivot_rule > 0) ? o->pivot_rule : PIVOT_NINTHER;
     const bool learned = P.on && (uint64_t)n > T;
 
