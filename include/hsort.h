@@ -116,7 +116,7 @@ typedef struct hs_stats {
     /* Kernel times measured with HIP events on `stream` around each launch
      * (filled only when stats are requested). */
     double partition_ms;   /* sum over the partition-pass launches */
-    double local_ms;       /* the on-chip sort launches */
+    double local_ms;       /* the on-chip sort launches (both, when levels outlasted the first batch) */
     int64_t partition_launches;
     /* learned method only */
     double model_imbalance;  /* largest non-equality bucket / (n/256), model splitters, held-out sample */

@@ -669,6 +669,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     };
     // the control block as it is after the on-chip sorts is in h already
     bool have_final = false;
+    float local_ms_before = 0.f;  // an earlier on-chip launch's time (stats)
     if (host_driver) {
         // host-driven levels: batches of fixed-grid launches.  For a single
         // array the first batch runs the levels balanced splits would need plus
@@ -700,6 +701,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
                 batch = levels_for(lc.max_seg, T);
                 ntask_done = h->ntask;
                 nsmall_done = h->nsmall;
+                if (st) HS_HIP(hipEventElapsedTime(&local_ms_before, lev[0], lev[1]));
             }
         }
         if (!have_final) {
@@ -765,7 +767,7 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
         }
         float ms = 0.f;
         HS_HIP(hipEventElapsedTime(&ms, lev[0], lev[1]));
-        st->local_ms = ms;
+        st->local_ms = ms + local_ms_before;
         if (learned) {
             const LearnCtl &lc = *d->h_lctl;
             // the multiway pass reads the keys twice and writes them once
