@@ -617,7 +617,8 @@ __device__ __forceinline__ void partition_level(uint32_t ntiles, uint32_t nseg,
     // probes lo + span*l/64; tile0 grows with the index, so the probes at or
     // below tt are a prefix of the lanes.  Every segment has a tile, so the
     // answer lies within tt - lo_tile0 segments of lo: two rounds of parallel
-    // loads when a workgroup's next tile is nwg = 512 tiles on.
+    // loads when a workgroup's next tile is nwg = 512 tiles on (two rounds of
+    // one workgroup per compute unit).
     auto search = [&](uint32_t tt, uint32_t lo, uint32_t lo_tile0) -> uint32_t {
         uint32_t hi = (uint32_t)min((uint64_t)nseg, (uint64_t)lo + (tt - lo_tile0) + 1u);
         while (hi - lo > 1) {

@@ -600,8 +600,8 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     if (occ_p < 1) occ_p = 1;
     // two rounds of workgroups: the tiles of a level differ in cost (partial
     // tiles at segment ends, segment changes), and workgroups of a second
-    // round start where the first round's finish early (measured: 1% faster
-    // whole int32 and float64 sorts than one round)
+    // round start where the first round's finish early (measured: int32 2^28
+    // partition passes 6.28 ms, against 6.33 with one round and 6.31 with four)
     const int part_grid = d->ncu * occ_p * 2;
     const int fin_grid = d->ncu * FIN_BLOCKS_PER_CU;
     uint64_t *ipmask = (uint64_t *)(ws + L.ipmask);

@@ -178,6 +178,22 @@ def test_segmented_forced_levels(hs, oracle_mod):
     assert np.array_equal(t.cpu().numpy(), oracle_mod.sort_segmented_i32(keys, off))
 
 
+@pytest.mark.parametrize("dtype", [np.int32, np.float64])
+def test_segmented_one_tile_segments(hs, oracle_mod, dtype):
+    """Thousands of segments of one or two partition tiles each in one level
+    list (on-chip limit 300, segments of 301-3000 keys): a workgroup's
+    consecutive tiles lie hundreds of segments apart, so every tile finds its
+    segment by the bounded search."""
+    off = workloads.segment_offsets(6000, 301, 3000, seed=11)
+    n = int(off[-1])
+    keys = workloads.uniform_i32(n, seed=12) if dtype == np.int32 else workloads.f64(n, "normal", seed=12)
+    t, o = _gpu(keys), _gpu(off)
+    hs.sort_segmented_(t, o, opts=_opts(hs, 3, 300))
+    want = oracle_mod.sort_segmented_i32(keys, off) if dtype == np.int32 else \
+        oracle_mod.sort_segmented_f64(keys, off)
+    assert np.array_equal(t.cpu().numpy().view(np.uint8), want.view(np.uint8))
+
+
 def test_unaligned_views(hs, oracle_mod):
     """Tensors that start 4 bytes into an allocation (not 16-byte aligned)."""
     a = workloads.uniform_i32(100001, seed=77)
