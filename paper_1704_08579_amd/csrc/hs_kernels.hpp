@@ -578,10 +578,11 @@ template <int N> __device__ __forceinline__ void wait_vmcnt()
 // and write to the few segments those tiles belong to (measured against
 // contiguous runs of tiles per workgroup: int32 2^28 partition passes 6.54 ->
 // 6.26 ms, float64 12.35 -> 11.93 ms; the first level, whose writes go to two
-// streams either way, 388 -> 362 us).  The tile count is bounded by the tiles of the segments in the list
-// (a list overflow, which is flagged, cannot create tiles without keys), so
-// every tile holds at least one key.  The LDS staging area is the caller's,
-// so the persistent driver shares it between levels.
+// streams either way, 388 -> 362 us).  The tile count is bounded by the
+// tiles of the segments in the list (a list overflow, which is flagged,
+// cannot create tiles without keys), so every tile holds at least one key.
+// The LDS staging area is the caller's, so the persistent driver shares it
+// between levels.
 //
 // Order within a tile: classify, scan, reserve (the cursor atomic), issue
 // the next tile's loads, compact in LDS, write out.  Loads and stores share
