@@ -572,7 +572,7 @@ def main():
                     help="partition levels in one persistent launch, or one launch per level")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
+        print("bench.py: the sort runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
     if args.steps < 1:
         print("bench.py: --steps must be at least 1", file=sys.stderr)
