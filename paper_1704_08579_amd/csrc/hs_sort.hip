@@ -672,18 +672,25 @@ int sort_body(DevState *d, char *ws, const Layout &L, Raw raw, int64_t n, const 
     float local_ms_before = 0.f;  // an earlier on-chip launch's time (stats)
     if (host_driver) {
         // host-driven levels: batches of fixed-grid launches.  For a single
-        // array the first batch runs the levels balanced splits would need plus
-        // three (sampled pivots spread the segment sizes; a level with an empty
-        // list exits at once) and the on-chip sorts follow it at once, before
-        // any read-back: one read-back then usually ends the call.  Should
-        // levels remain, further batches run with a read-back each, and the
-        // on-chip sorts run again over the tasks the new levels added.
+        // array the first batch runs the levels balanced splits would need
+        // (levels_for, which counts one more) plus a margin, because sampled
+        // pivots spread the segment sizes: two levels up to levels_for = 8,
+        // three beyond (measured over uniform, normal, sorted and reversed
+        // int32 and float64 arrays of 2^14..2^28 keys: at most levels_for + 1
+        // non-empty levels up to 2^20, + 2 at 2^22..2^26, + 3 at 2^28).  An
+        // empty level costs its two launches (about 20 us); a missing one a
+        // read-back and a second on-chip launch.  The on-chip sorts follow the
+        // batch at once, before any read-back: one read-back then usually ends
+        // the call.  Should levels remain, further batches run with a
+        // read-back each, and the on-chip sorts run again over the tasks the
+        // new levels added.
         int level = level0;
         int batch = 0;
         uint32_t ntask_done = 0, nsmall_done = 0;
         bool sorted_some = false;
         if (!learned && !d_off && (uint64_t)n > T) {
-            for (int bi = 0, nb = levels_for((uint64_t)n, T) + 3; bi < nb && level < LMAX; ++bi, ++level) {
+            const int lf = levels_for((uint64_t)n, T);
+            for (int bi = 0, nb = lf + (lf <= 8 ? 2 : 3); bi < nb && level < LMAX; ++bi, ++level) {
                 const int rc = launch_level(level);
                 if (rc) return rc;
             }
