@@ -43,8 +43,9 @@ def _opts(hs, pivot=0, local_T=0):
     return o
 
 
+# the last two straddle the first batch's margin change (levels_for 8 -> 9 at T = 8192)
 SIZES = [2, 3, 63, 64, 65, 255, 256, 257, 1000, 4095, 4096, 4097, 8192, 8193, 16383, 16384, 16385,
-         50001, (1 << 17) + 13]
+         50001, (1 << 17) + 13, 1 << 20, (1 << 20) + 1]
 
 
 @pytest.mark.parametrize("n", SIZES)
